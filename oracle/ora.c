@@ -1,0 +1,552 @@
+/*
+ * ora.c — plain, slow CPU reference ("oracle") for the exact-diagonalisation
+ * hot path of the Pyqcm paper (arXiv 2305.18643, section "Exact
+ * diagonalizations").  Everything is double precision and written as the
+ * plain definition, with no blocking or reordering.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU
+ * baseline leg of bench.py may load this library.  It shares no source with
+ * the HIP library in paper_2305_18643_amd/ and includes none of its headers.
+ *
+ * Conventions (each one is the paper's, restated):
+ *  - a spin string is an integer whose bit k is the occupation of orbital k
+ *    (orbitals numbered 0..L-1; subsection "Coding of the basis states",
+ *    eq. (basis), with all up creation operators to the left of all down
+ *    creation operators);
+ *  - the states of one spin sector are the L-bit strings of popcount N in
+ *    ascending numeric order; their position is the label I_sigma(b);
+ *  - the full label is i = I_up(b_up) + d_up * I_dn(b_dn), so that
+ *    i_up = i mod d_up and i_dn = i div d_up (same subsection);
+ *  - H = sum_{ab,sigma} t_ab c+_a c_b + sum_k U_k n_k,up n_k,dn, the chemical
+ *    potential and any bath energy living on the diagonal of t
+ *    (eq. (Hubbard) and eq. (cdmft1)).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* binomial coefficient C(n,k); 0 outside 0<=k<=n (sector dimension    */
+/* d(N) = L!/(N!(L-N)!), subsection "Coding of the basis states")      */
+int64_t ora_binom(int n, int k)
+{
+    if (n < 0 || k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+    return r;
+}
+
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+/* All L-bit strings with N set bits, ascending.  Uses the classic "next
+ * larger integer with the same popcount" step, so the order is ascending by
+ * construction.  Returns the count written. */
+int64_t ora_enumerate(int L, int N, uint32_t *out)
+{
+    if (N < 0 || N > L || L > 32) return -1;
+    int64_t n = 0;
+    if (N == 0) { out[0] = 0; return 1; }
+    uint64_t x = (N == 64) ? ~0ull : ((1ull << N) - 1);
+    uint64_t lim = 1ull << L;
+    while (x < lim) {
+        out[n++] = (uint32_t)x;
+        uint64_t c = x & (~x + 1);      /* lowest set bit */
+        uint64_t r = x + c;
+        x = (((r ^ x) >> 2) / c) | r;
+    }
+    return n;
+}
+
+/* Label of a string inside its sector: the combinatorial number system,
+ * sum over the set bits p_0 < p_1 < ... of C(p_j, j+1).  This equals the
+ * position of the string in the ascending list (pinned by a brute-force
+ * test). */
+int64_t ora_rank(uint32_t b)
+{
+    int64_t r = 0;
+    int j = 0;
+    for (int p = 0; p < 32; p++) {
+        if (b >> p & 1u) { j++; r += ora_binom(p, j); }
+    }
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea & Flood 2014, public-domain reference by     */
+/* Vigna), used counter-style: output number i (i = 0,1,...) of the     */
+/* generator seeded with `seed` is mix(seed + (i+1)*gamma).              */
+/* Start vector entry i: 2*(u_i >> 11)*2^-53 - 1, exact in FP64.         */
+static uint64_t splitmix_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void ora_start_vector(uint64_t seed, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t u = splitmix_at(seed, (uint64_t)i);
+        out[i] = 2.0 * (double)(u >> 11) * 0x1.0p-53 - 1.0;
+    }
+}
+
+uint64_t ora_splitmix(uint64_t seed, uint64_t i) { return splitmix_at(seed, i); }
+
+/* ------------------------------------------------------------------ */
+/* Hamiltonian matrix elements, subsection "Coding of the basis states": */
+/* two strings of one spin are connected by c+_a c_c when they differ    */
+/* exactly at a and c; the element is (-1)^M t_ac with M the number of   */
+/* occupied orbitals strictly between a and c.  The interaction counts   */
+/* the doubly occupied orbitals (bitwise and of the two spin strings).   */
+
+typedef struct {
+    int L, nup, ndn;
+    int64_t dup, ddn;
+    uint32_t *su, *sd;
+} sector_t;
+
+static int sector_init(sector_t *s, int L, int nup, int ndn)
+{
+    s->L = L; s->nup = nup; s->ndn = ndn;
+    s->dup = ora_binom(L, nup); s->ddn = ora_binom(L, ndn);
+    if (s->dup <= 0 || s->ddn <= 0) return -1;
+    s->su = (uint32_t *)malloc(sizeof(uint32_t) * s->dup);
+    s->sd = (uint32_t *)malloc(sizeof(uint32_t) * s->ddn);
+    ora_enumerate(L, nup, s->su);
+    ora_enumerate(L, ndn, s->sd);
+    return 0;
+}
+
+static void sector_free(sector_t *s) { free(s->su); free(s->sd); }
+
+/* occupied orbitals strictly between a and c in string b */
+static int between_count(uint32_t b, int a, int c)
+{
+    int lo = a < c ? a : c, hi = a < c ? c : a;
+    int m = 0;
+    for (int k = lo + 1; k < hi; k++) m += (b >> k) & 1u;
+    return m;
+}
+
+/* Diagonal element: sum_k t_kk (n_k,up + n_k,dn) + sum_k U_k n_k,up n_k,dn */
+static double diag_elem(int L, const double *t, const double *U,
+                        uint32_t bu, uint32_t bd)
+{
+    double d = 0.0;
+    for (int k = 0; k < L; k++) {
+        int nu = (bu >> k) & 1u, nd = (bd >> k) & 1u;
+        d += t[k * L + k] * (nu + nd);
+        if (nu && nd) d += U[k];
+    }
+    return d;
+}
+
+/* (H v)_i for one row i */
+static double hv_row(const sector_t *s, const double *t, const double *U,
+                     const double *v, int64_t i)
+{
+    const int L = s->L;
+    int64_t iu = i % s->dup, id = i / s->dup;
+    uint32_t bu = s->su[iu], bd = s->sd[id];
+    double acc = diag_elem(L, t, U, bu, bd) * v[i];
+    /* <i| t_ac c+_a c_c |j>: row i has a occupied and c empty; j has c
+     * occupied and a empty; a != c. */
+    for (int a = 0; a < L; a++) {
+        for (int c = 0; c < L; c++) {
+            if (a == c) continue;
+            double tac = t[a * L + c];
+            if (tac == 0.0) continue;
+            /* up spin */
+            if ((bu >> a & 1u) && !(bu >> c & 1u)) {
+                uint32_t bj = bu ^ (1u << a) ^ (1u << c);
+                double sg = (between_count(bu, a, c) & 1) ? -1.0 : 1.0;
+                int64_t j = ora_rank(bj) + s->dup * id;
+                acc += tac * sg * v[j];
+            }
+            /* down spin */
+            if ((bd >> a & 1u) && !(bd >> c & 1u)) {
+                uint32_t bj = bd ^ (1u << a) ^ (1u << c);
+                double sg = (between_count(bd, a, c) & 1) ? -1.0 : 1.0;
+                int64_t j = iu + s->dup * ora_rank(bj);
+                acc += tac * sg * v[j];
+            }
+        }
+    }
+    return acc;
+}
+
+/* w = H v over the whole sector (eq. (factorized) applied element by
+ * element).  nthreads <= 0: use the OpenMP default. */
+int ora_hv(int L, const double *t, const double *U, int nup, int ndn,
+           const double *v, double *w, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+    int64_t dim = s.dup * s.ddn;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < dim; i++) w[i] = hv_row(&s, t, U, v, i);
+    sector_free(&s);
+    return 0;
+}
+
+/* (H v)_i for a list of rows only (used on sectors too large for a full
+ * oracle pass: the sampled rows are computed one by one). */
+int ora_hv_rows(int L, const double *t, const double *U, int nup, int ndn,
+                const double *v, const int64_t *rows, int64_t nrows,
+                double *out, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; r++) out[r] = hv_row(&s, t, U, v, rows[r]);
+    sector_free(&s);
+    return 0;
+}
+
+/* (H v)_i for rows given as (up string, down string) pairs, sampled from a
+ * vector given only at the rows' neighbours is not possible; this variant
+ * reads v from a full vector as above but takes float input. */
+int ora_hv_rows_f32(int L, const double *t, const double *U, int nup,
+                    int ndn, const float *vf, const int64_t *rows,
+                    int64_t nrows, double *out, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t i = rows[r];
+        int64_t iu = i % s.dup, id = i / s.dup;
+        uint32_t bu = s.su[iu], bd = s.sd[id];
+        double acc = diag_elem(L, t, U, bu, bd) * (double)vf[i];
+        for (int a = 0; a < L; a++)
+            for (int c = 0; c < L; c++) {
+                if (a == c) continue;
+                double tac = t[a * L + c];
+                if (tac == 0.0) continue;
+                if ((bu >> a & 1u) && !(bu >> c & 1u)) {
+                    uint32_t bj = bu ^ (1u << a) ^ (1u << c);
+                    double sg = (between_count(bu, a, c) & 1) ? -1.0 : 1.0;
+                    acc += tac * sg * (double)vf[ora_rank(bj) + s.dup * id];
+                }
+                if ((bd >> a & 1u) && !(bd >> c & 1u)) {
+                    uint32_t bj = bd ^ (1u << a) ^ (1u << c);
+                    double sg = (between_count(bd, a, c) & 1) ? -1.0 : 1.0;
+                    acc += tac * sg * (double)vf[iu + s.dup * ora_rank(bj)];
+                }
+            }
+        out[r] = acc;
+    }
+    sector_free(&s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Symmetric tridiagonal helpers (T has alpha on the diagonal and       */
+/* beta[n] between n and n+1), eq. (tridiag).                            */
+
+/* number of eigenvalues of T_n strictly below x (Sturm sequence) */
+static int sturm_below(int n, const double *alpha, const double *beta, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; i++) {
+        double off = (i == 0) ? 0.0 : beta[i - 1] * beta[i - 1] / q;
+        q = alpha[i] - x - off;
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+/* k-th smallest eigenvalue (k = 0, 1, ...) by plain bisection */
+double ora_tridiag_eig(int n, const double *alpha, const double *beta, int k)
+{
+    double lo = alpha[0], hi = alpha[0];
+    for (int i = 0; i < n; i++) {
+        double r = 0.0;
+        if (i > 0) r += fabs(beta[i - 1]);
+        if (i < n - 1) r += fabs(beta[i]);
+        if (alpha[i] - r < lo) lo = alpha[i] - r;
+        if (alpha[i] + r > hi) hi = alpha[i] + r;
+    }
+    for (int it = 0; it < 200; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(n, alpha, beta, mid) > k) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Eigenvector of T_n for eigenvalue theta by inverse iteration, with
+ * Gaussian elimination with partial pivoting on the tridiagonal system. */
+void ora_tridiag_vec(int n, const double *alpha, const double *beta,
+                     double theta, double *x)
+{
+    double *dl = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
+    double *du = malloc(sizeof(double) * n), *du2 = malloc(sizeof(double) * n);
+    double *y = malloc(sizeof(double) * n);
+    int *swp = malloc(sizeof(int) * n);
+    double scale = 1.0;
+    for (int i = 0; i < n; i++) scale = fmax(scale, fabs(alpha[i]));
+    double tiny = 1e-15 * scale;
+    for (int i = 0; i < n; i++) x[i] = 1.0;
+    for (int iter = 0; iter < 4; iter++) {
+        for (int i = 0; i < n; i++) {
+            d[i] = alpha[i] - theta;
+            du[i] = (i < n - 1) ? beta[i] : 0.0;
+            dl[i] = (i < n - 1) ? beta[i] : 0.0;
+            du2[i] = 0.0;
+            y[i] = x[i];
+        }
+        /* LU with partial pivoting of the tridiagonal (rows i, i+1) */
+        for (int i = 0; i < n - 1; i++) {
+            if (fabs(dl[i]) > fabs(d[i])) {
+                swp[i] = 1;
+                double t0 = d[i]; d[i] = dl[i]; dl[i] = t0;
+                double t1 = du[i]; du[i] = d[i + 1]; d[i + 1] = t1;
+                if (i < n - 2) { du2[i] = du[i + 1]; du[i + 1] = 0.0; }
+                double ty = y[i]; y[i] = y[i + 1]; y[i + 1] = ty;
+            } else swp[i] = 0;
+            if (d[i] == 0.0) d[i] = tiny;
+            double m = dl[i] / d[i];
+            d[i + 1] -= m * du[i];
+            if (i < n - 2) du[i + 1] -= m * du2[i];
+            y[i + 1] -= m * y[i];
+        }
+        if (d[n - 1] == 0.0) d[n - 1] = tiny;
+        /* back substitution */
+        for (int i = n - 1; i >= 0; i--) {
+            double s = y[i];
+            if (i + 1 < n) s -= du[i] * x[i + 1];
+            if (i + 2 < n) s -= du2[i] * x[i + 2];
+            x[i] = s / d[i];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < n; i++) nrm += x[i] * x[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < n; i++) x[i] /= nrm;
+    }
+    /* fix the sign: first component non-negative */
+    if (x[0] < 0) for (int i = 0; i < n; i++) x[i] = -x[i];
+    free(dl); free(d); free(du); free(du2); free(y); free(swp);
+}
+
+/* ------------------------------------------------------------------ */
+/* Lanczos recurrence, subsection "The Lanczos algorithm for the ground  */
+/* state", in the normalised form: v_0 = x/|x|, w = H v_n - beta_{n-1}   */
+/* v_{n-1}, alpha_n = <v_n,w>, w -= alpha_n v_n, beta_n = |w|,           */
+/* v_{n+1} = w/beta_n.  Here beta[n] couples n and n+1, so beta[n]^2 is  */
+/* the paper's b_{n+1}^2.  T_M is the M x M tridiagonal of eq. (tridiag).*/
+/*                                                                      */
+/* Stop rule (the paper's test is garbled; this is the standard reading):*/
+/* after each step, theta_0 = lowest eigenvalue of T_M and s its         */
+/* normalised eigenvector; stop when beta[M-1]*|s[M-1]| <=               */
+/* tol*max(1,|theta_0|).  Also stop on breakdown, beta < btol*max|alpha|,*/
+/* or at max_iter.  fixed_steps > 0 disables the residual test.          */
+/*                                                                      */
+/* The ground-state vector comes from a second, identical pass that      */
+/* accumulates psi = sum_n s_n v_n (the paper retraces the iterations).  */
+
+static double dot(int64_t n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += x[i] * y[i];
+    return s;
+}
+
+typedef struct {
+    double e0, residual_est, true_residual;
+    int n_iter, converged, breakdown;
+} ora_gs_t;
+
+static int lanczos_core(const sector_t *s, const double *t, const double *U,
+                        const double *x0, int max_iter, int fixed_steps,
+                        double tol, double btol, double *alpha, double *beta,
+                        int *n_out, int *conv_out, int *bd_out,
+                        const double *coef, double *psi, int nthreads)
+{
+    const int64_t dim = s->dup * s->ddn;
+    double *v = malloc(sizeof(double) * dim);
+    double *vp = calloc(dim, sizeof(double));
+    double *w = malloc(sizeof(double) * dim);
+    double nrm = sqrt(dot(dim, x0, x0));
+    for (int64_t i = 0; i < dim; i++) v[i] = x0[i] / nrm;
+    if (psi) for (int64_t i = 0; i < dim; i++) psi[i] = 0.0;
+    int limit = fixed_steps > 0 ? fixed_steps : max_iter;
+    double amax = 0.0;
+    int M = 0, conv = 0, bd = 0;
+    double *sv = malloc(sizeof(double) * (limit + 1));
+    (void)nthreads;
+    for (int n = 0; n < limit; n++) {
+        if (psi) for (int64_t i = 0; i < dim; i++) psi[i] += coef[n] * v[i];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < dim; i++) w[i] = hv_row(s, t, U, v, i);
+        double bprev = (n == 0) ? 0.0 : beta[n - 1];
+        for (int64_t i = 0; i < dim; i++) w[i] -= bprev * vp[i];
+        double a = dot(dim, v, w);
+        for (int64_t i = 0; i < dim; i++) w[i] -= a * v[i];
+        double b = sqrt(dot(dim, w, w));
+        if (!coef) { alpha[n] = a; beta[n] = b; }
+        else { a = alpha[n]; b = beta[n]; }
+        if (fabs(a) > amax) amax = fabs(a);
+        M = n + 1;
+        if (!coef) {
+            if (b < btol * (amax > 0 ? amax : 1.0)) { bd = 1; conv = 1; break; }
+            if (fixed_steps <= 0) {
+                double th = ora_tridiag_eig(M, alpha, beta, 0);
+                ora_tridiag_vec(M, alpha, beta, th, sv);
+                double est = b * fabs(sv[M - 1]);
+                double sc = fabs(th) > 1.0 ? fabs(th) : 1.0;
+                if (est <= tol * sc) { conv = 1; break; }
+            }
+        } else if (n + 1 >= *n_out) break;
+        for (int64_t i = 0; i < dim; i++) { vp[i] = v[i]; v[i] = w[i] / b; }
+    }
+    if (!coef) { *n_out = M; *conv_out = conv; *bd_out = bd; }
+    free(v); free(vp); free(w); free(sv);
+    return 0;
+}
+
+/* Ground state of one (N_up, N_dn) sector.  x0: start vector (length dim;
+ * NULL -> SplitMix64 start vector for `seed`).  alpha/beta: [max(max_iter,
+ * fixed_steps)].  psi (nullable): normalised ground-state vector.
+ * out: e0, residual estimate, true residual |H psi - e0 psi| (if psi),
+ * n_iter, converged, breakdown. */
+int ora_lanczos_gs(int L, const double *t, const double *U, int nup, int ndn,
+                   const double *x0, uint64_t seed, int max_iter,
+                   int fixed_steps, double tol, double btol, double *alpha,
+                   double *beta, double *psi, double *out_d, int *out_i,
+                   int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const int64_t dim = s.dup * s.ddn;
+    double *xs = NULL;
+    if (!x0) { xs = malloc(sizeof(double) * dim); ora_start_vector(seed, dim, xs); x0 = xs; }
+    int M = 0, conv = 0, bd = 0;
+    lanczos_core(&s, t, U, x0, max_iter, fixed_steps, tol, btol, alpha, beta,
+                 &M, &conv, &bd, NULL, NULL, nthreads);
+    double th = ora_tridiag_eig(M, alpha, beta, 0);
+    double *sv = malloc(sizeof(double) * M);
+    ora_tridiag_vec(M, alpha, beta, th, sv);
+    out_d[0] = th;
+    out_d[1] = beta[M - 1] * fabs(sv[M - 1]);
+    out_d[2] = -1.0;
+    out_d[3] = (M > 1) ? ora_tridiag_eig(M, alpha, beta, 1) : NAN;
+    if (psi) {
+        int Mp = M;
+        lanczos_core(&s, t, U, x0, max_iter, fixed_steps, tol, btol, alpha,
+                     beta, &Mp, &conv, &bd, sv, psi, nthreads);
+        double nr = sqrt(dot(dim, psi, psi));
+        for (int64_t i = 0; i < dim; i++) psi[i] /= nr;
+        double *hp = malloc(sizeof(double) * dim);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < dim; i++) hp[i] = hv_row(&s, t, U, psi, i);
+        double r2 = 0.0;
+        for (int64_t i = 0; i < dim; i++) {
+            double d = hp[i] - th * psi[i];
+            r2 += d * d;
+        }
+        out_d[2] = sqrt(r2);
+        free(hp);
+    }
+    out_i[0] = M; out_i[1] = conv; out_i[2] = bd;
+    free(sv); free(xs);
+    sector_free(&s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Start vectors of the Green-function chains, subsection "The Lanczos  */
+/* algorithm for the Green function": c+_mu |Omega> (electron part) and  */
+/* c_mu |Omega> (hole part), up spin, and the sums (c_mu + c_nu)+ and     */
+/* (c_mu + c_nu) of the off-diagonal trick.  An up operator on orbital mu */
+/* anticommutes past the up creation operators of orbitals < mu, giving  */
+/* (-1)^{number of up electrons on orbitals below mu}.  nu < 0: single.  */
+/* kind 0: creation (target sector N_up+1), 1: annihilation (N_up-1).    */
+/* psi lives in (nup, ndn); out in the target sector, zero-filled here.  */
+int ora_apply_cdag_c(int L, int nup, int ndn, const double *psi, int kind,
+                     int mu, int nu, double *out)
+{
+    sector_t s, s2;
+    int nup2 = kind == 0 ? nup + 1 : nup - 1;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+    if (nup2 < 0 || nup2 > L) { sector_free(&s); return -2; }
+    sector_init(&s2, L, nup2, ndn);
+    int64_t dim2 = s2.dup * s2.ddn;
+    for (int64_t i = 0; i < dim2; i++) out[i] = 0.0;
+    int ops[2] = {mu, nu};
+    int nops = nu < 0 ? 1 : 2;
+    for (int64_t i = 0; i < s.dup * s.ddn; i++) {
+        int64_t iu = i % s.dup, id = i / s.dup;
+        uint32_t bu = s.su[iu];
+        for (int o = 0; o < nops; o++) {
+            int m = ops[o];
+            int occ = (bu >> m) & 1u;
+            if (kind == 0 && occ) continue;
+            if (kind == 1 && !occ) continue;
+            uint32_t b2 = bu ^ (1u << m);
+            int below = popc(bu & ((1u << m) - 1u));
+            double sg = (below & 1) ? -1.0 : 1.0;
+            int64_t j = ora_rank(b2) + s2.dup * id;
+            out[j] += sg * psi[i];
+        }
+    }
+    sector_free(&s);
+    sector_free(&s2);
+    return 0;
+}
+
+/* One continued-fraction chain: Lanczos from phi/|phi| in sector
+ * (nup, ndn) for at most max_steps steps, stopping early on breakdown
+ * (beta < btol*max|alpha|).  Writes b0sq = <phi|phi>, a[0..len-1] and
+ * b2[0..len-2] (b2[n] = beta[n]^2 couples floors n and n+1); returns len.
+ * An empty start vector gives b0sq = 0 and len = 0. */
+int ora_cf_chain(int L, const double *t, const double *U, int nup, int ndn,
+                 const double *phi, int max_steps, double btol, double *b0sq,
+                 double *a, double *b2, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const int64_t dim = s.dup * s.ddn;
+    double nn = dot(dim, phi, phi);
+    *b0sq = nn;
+    if (nn == 0.0) { sector_free(&s); return 0; }
+    double *alpha = malloc(sizeof(double) * max_steps);
+    double *beta = malloc(sizeof(double) * max_steps);
+    int M = 0, conv = 0, bd = 0;
+    lanczos_core(&s, t, U, phi, max_steps, max_steps, 0.0, btol, alpha, beta,
+                 &M, &conv, &bd, NULL, NULL, nthreads);
+    for (int n = 0; n < M; n++) a[n] = alpha[n];
+    for (int n = 0; n + 1 < M; n++) b2[n] = beta[n] * beta[n];
+    free(alpha); free(beta);
+    sector_free(&s);
+    return M;
+}

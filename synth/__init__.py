@@ -1,0 +1,195 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only builds inputs: hopping matrices t_ij (with the chemical
+potential and bath energies on the diagonal), on-site interactions U_i,
+sectors (N_up, N_dn), frequency grids, momentum grids and CPT lattice
+descriptions.  It holds none of the method's arithmetic.
+
+Conventions:
+  * a model is (t, U): t is L x L real symmetric, t_ii = eps_i - mu; U has
+    one entry per orbital and is 0 on bath orbitals (eq. (Hubbard) and
+    eq. (cdmft1) of the paper);
+  * "t = -1" means the matrix element t_ij = -1 on every nearest-neighbour
+    bond, "t' = 0.3" means t_ij = +0.3 on both diagonals of every plaquette;
+  * rectangular clusters number their sites x + nx*y;
+  * cluster orbitals come first and bath orbitals after them.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    name: str
+    t: np.ndarray
+    U: np.ndarray
+    nup: int
+    ndn: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def L(self) -> int:
+        return int(self.t.shape[0])
+
+
+def rect_cluster(nx: int, ny: int, t: float = -1.0, tp: float = 0.0, U: float = 8.0,
+                 mu: float = 4.0, nup: int | None = None, ndn: int | None = None,
+                 name: str | None = None) -> Model:
+    """Open-boundary nx x ny cluster, sites x + nx*y."""
+    L = nx * ny
+    T = np.zeros((L, L))
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            if x + 1 < nx:
+                T[i, i + 1] = T[i + 1, i] = t
+            if y + 1 < ny:
+                T[i, i + nx] = T[i + nx, i] = t
+            if tp != 0.0 and x + 1 < nx and y + 1 < ny:
+                a, b = i, i + 1 + nx
+                c, d = i + 1, i + nx
+                T[a, b] = T[b, a] = tp
+                T[c, d] = T[d, c] = tp
+    for i in range(L):
+        T[i, i] = -mu
+    nup = L // 2 if nup is None else nup
+    ndn = L // 2 if ndn is None else ndn
+    return Model(name or f"{nx}x{ny}", T, np.full(L, float(U)), nup, ndn,
+                 dict(nx=nx, ny=ny, t=t, tp=tp, U=U, mu=mu))
+
+
+def chain(L: int, t: float = -1.0, U: float = 4.0, mu: float = 2.0,
+          nup: int | None = None, ndn: int | None = None) -> Model:
+    """Open chain of L sites."""
+    m = rect_cluster(L, 1, t=t, U=U, mu=mu, nup=nup, ndn=ndn, name=f"chain{L}")
+    return m
+
+
+def two_site(t: float = -1.0, U: float = 4.0, mu: float = 0.0) -> Model:
+    return rect_cluster(2, 1, t=t, U=U, mu=mu, nup=1, ndn=1, name="dimer")
+
+
+def plaquette_2x2(U: float = 8.0, mu: float = 4.0) -> Model:
+    """2x2 plaquette, t = -1, U = 8, mu = 4, sector (2, 2), dim 36."""
+    return rect_cluster(2, 2, t=-1.0, U=U, mu=mu, nup=2, ndn=2, name="2x2")
+
+
+def cluster_3x4(U: float = 8.0, mu: float = 4.0, tp: float = 0.3) -> Model:
+    """3 rows x 4 columns, t = -1, t' = 0.3, U = 8, mu = 4, sector (6, 6)."""
+    return rect_cluster(4, 3, t=-1.0, tp=tp, U=U, mu=mu, nup=6, ndn=6, name="3x4")
+
+
+def cluster_4x4(U: float = 8.0) -> Model:
+    """4x4, t = -1, mu = U/2, sector (8, 8), dim 165,636,900."""
+    return rect_cluster(4, 4, t=-1.0, U=U, mu=U / 2, nup=8, ndn=8, name=f"4x4_U{U:g}")
+
+
+def random_model(seed: int, L: int, nup: int, ndn: int, density: float = 0.6,
+                 uniform_U: bool = False) -> Model:
+    """A random real symmetric t with random on-site U (test input)."""
+    rng = np.random.default_rng(seed)
+    T = rng.normal(0.0, 1.0, (L, L))
+    mask = rng.random((L, L)) < density
+    T = np.where(mask, T, 0.0)
+    T = np.triu(T, 1)
+    T = T + T.T
+    T[np.diag_indices(L)] = rng.uniform(-2.0, 2.0, L)
+    U = np.full(L, rng.uniform(1, 8)) if uniform_U else rng.uniform(0.0, 8.0, L)
+    return Model(f"rand{seed}_L{L}", T, U, nup, ndn, dict(seed=seed))
+
+
+def omega_grid(n: int = 64, lo: float = -10.0, hi: float = 10.0, eta: float = 0.1) -> np.ndarray:
+    """z_k = omega_k + i eta, omega_k = lo + (hi - lo) k / (n - 1)."""
+    w = lo + (hi - lo) * np.arange(n) / (n - 1)
+    return w + 1j * eta
+
+
+def k_grid_2d(n: int = 16) -> np.ndarray:
+    """k = (m/n, l/n, 0) in units of 2 pi, m, l = 0..n-1; row-major in (m, l)."""
+    m, l = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([m.ravel() / n, l.ravel() / n, np.zeros(n * n)], axis=1)
+
+
+def cpt_square_lattice_2x2(t: float = -1.0):
+    """Tiling of the square lattice by 2x2 plaquettes: site positions R_i
+    (sites x + 2y), super-lattice vectors E = (2,0,0), (0,2,0), (0,0,1) and
+    the inter-cluster nearest-neighbour bonds (i, j, shift, t): site i of the
+    cluster at the origin to site j of the cluster at shift . E."""
+    R = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], dtype=np.int32)
+    E = np.array([[2, 0, 0], [0, 2, 0], [0, 0, 1]], dtype=np.int32)
+    bonds = [(1, 0, (1, 0, 0), t), (3, 2, (1, 0, 0), t),
+             (2, 0, (0, 1, 0), t), (3, 1, (0, 1, 0), t)]
+    return R, E, bonds
+
+
+def chain_lattice_2(t: float = -1.0):
+    """1D lattice tiled by 2-site clusters (E = 2): positions and the single
+    inter-cluster bond."""
+    R = np.array([[0, 0, 0], [1, 0, 0]], dtype=np.int32)
+    E = np.array([[2, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.int32)
+    bonds = [(1, 0, (1, 0, 0), t)]
+    return R, E, bonds
+
+
+def impurity_model(rng: np.random.Generator, n_bath: int) -> Model:
+    """2x2 plaquette (t = -1) plus n_bath bath orbitals.  Bath orbital 4 + a
+    couples to cluster site a mod 4 with theta ~ U(0.2, 1) and has energy
+    eps ~ U(-3, 3); U ~ U(2, 10) on the four cluster sites, mu = U/2 there;
+    N_up, N_dn each drawn from {floor(n/2), ceil(n/2)}."""
+    n = 4 + n_bath
+    T = np.zeros((n, n))
+    for (i, j) in [(0, 1), (2, 3), (0, 2), (1, 3)]:
+        T[i, j] = T[j, i] = -1.0
+    Uval = rng.uniform(2.0, 10.0)
+    for i in range(4):
+        T[i, i] = -Uval / 2
+    for a in range(n_bath):
+        th = rng.uniform(0.2, 1.0)
+        eps = rng.uniform(-3.0, 3.0)
+        T[4 + a, a % 4] = T[a % 4, 4 + a] = th
+        T[4 + a, 4 + a] = eps
+    U = np.zeros(n)
+    U[:4] = Uval
+    lo, hi = n // 2, (n + 1) // 2
+    nup = int(rng.choice([lo, hi]))
+    ndn = int(rng.choice([lo, hi]))
+    return Model(f"imp{n}", T, U, nup, ndn, dict(n_bath=n_bath, U=Uval))
+
+
+def batched_solves(seed: int = 18643, count: int = 256) -> list[Model]:
+    """The batched workload: ``count`` impurity models with 2..10 bath orbitals."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        nb = int(rng.integers(2, 11))
+        out.append(impurity_model(rng, nb))
+    return out
+
+
+def serving_model(rng: np.random.Generator) -> Model:
+    """A serving request: n ~ U{4..14} orbitals, open chain or (n even, coin
+    flip) a 2 x n/2 ladder, t_ij ~ N(-1, 0.2) per bond, U ~ U(2, 10) on all
+    orbitals, mu = U/2, sector (ceil(n/2), floor(n/2))."""
+    n = int(rng.integers(4, 15))
+    ladder = (n % 2 == 0) and bool(rng.integers(0, 2))
+    T = np.zeros((n, n))
+    if ladder:
+        w = n // 2
+        bonds = [(x + w * y, x + 1 + w * y) for y in range(2) for x in range(w - 1)]
+        bonds += [(x, x + w) for x in range(w)]
+    else:
+        bonds = [(i, i + 1) for i in range(n - 1)]
+    for (i, j) in bonds:
+        T[i, j] = T[j, i] = rng.normal(-1.0, 0.2)
+    Uval = rng.uniform(2.0, 10.0)
+    T[np.diag_indices(n)] = -Uval / 2
+    return Model(f"srv{n}{'L' if ladder else 'C'}", T, np.full(n, Uval), (n + 1) // 2, n // 2,
+                 dict(ladder=ladder, U=Uval))
+
+
+def serving_requests(seed: int = 2305, count: int = 100) -> list[Model]:
+    rng = np.random.default_rng(seed)
+    return [serving_model(rng) for _ in range(count)]
