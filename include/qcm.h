@@ -1,0 +1,263 @@
+/*
+ * qcm.h — C ABI of the MI355X exact-diagonalisation hot path.
+ *
+ * The library computes, for the cluster Hubbard model in one fixed
+ * (N_up, N_dn) sector, the sparse product H.v, the Lanczos ground state, the
+ * continued-fraction Green function and the CPT Green function G(k, z), as
+ * described in arXiv 2305.18643 (Pyqcm), section "Exact diagonalizations"
+ * and section "Cluster perturbation theory".
+ *
+ * General rules (apply to every call):
+ *  - Every call returns an int: QCM_OK (0) on success, a negative QCM_E* code
+ *    on failure.  Nothing throws.  qcm_last_error() returns a thread-local
+ *    message describing the last failure of the calling thread.
+ *  - Arguments are validated before anything is enqueued; on a validation
+ *    error no output is touched.  On QCM_EHIP the outputs are undefined.
+ *  - "device" pointers are HIP device memory (e.g. torch tensors on the GPU);
+ *    "host" pointers are ordinary process memory.  The caller owns every
+ *    buffer.  The library never allocates device memory: each call that needs
+ *    scratch space takes a device workspace (d_ws, ws_bytes).  Passing
+ *    d_ws == NULL asks for the size only: the call writes the number of bytes
+ *    it needs to *ws_needed and returns QCM_OK without enqueueing anything.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it.  Calls documented as "synchronises" wait
+ *    for that stream before returning because they return host results.
+ *  - Vector layout: element i of a sector vector is the basis state with
+ *    up string B_up(i mod d_up) and down string B_dn(i div d_up), i.e. the
+ *    vector is a row-major d_dn x d_up matrix whose rows are indexed by the
+ *    down string (subsection "Coding of the basis states").
+ *  - Spin strings: bit k of a string is the occupation of orbital k.  The
+ *    states of one spin are the strings of popcount N in ascending numeric
+ *    order and their label is their position in that list.
+ *  - Fermion sign convention: every up creation operator stands to the left of
+ *    every down creation operator and, within one spin, orbital order is
+ *    ascending (eq. (basis)).
+ */
+#ifndef QCM_H
+#define QCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QCM_OK = 0,
+    QCM_EARG = -1,        /* invalid argument (NULL, bad size, asymmetric t, ...) */
+    QCM_ERANGE = -2,      /* L > 32, N > L, sector too large for 32-bit spin labels */
+    QCM_EWORKSPACE = -3,  /* workspace smaller than required */
+    QCM_EHIP = -4         /* a HIP runtime call failed; message has the HIP error */
+};
+
+/* Vector storage precision. */
+enum {
+    QCM_FP64 = 0,   /* vectors stored and computed in FP64 */
+    QCM_FP32V = 1   /* vectors stored in FP32; every product accumulates in FP64,
+                       dot products, alpha/beta, reorthogonalisation and the
+                       tridiagonal eigenproblem stay FP64 */
+};
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *qcm_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int qcm_version(void);
+
+/*
+ * The cluster (or cluster + bath) Hamiltonian
+ *   H = sum_{a,b,sigma} t_ab c+_{a sigma} c_{b sigma} + sum_k U_k n_{k up} n_{k dn}
+ * (eq. (Hubbard); eq. (cdmft1) for bath orbitals, which carry U_k = 0).
+ * The chemical potential and any bath energy sit on the diagonal of t
+ * (t_kk = eps_k - mu).  t must be real symmetric.  Host memory, read during
+ * the call only.
+ */
+typedef struct qcm_model {
+    int32_t L;          /* number of orbitals, 1..32 */
+    const double *t;    /* host [L*L], row-major, t[a*L+b] = t_ab */
+    const double *U;    /* host [L], on-site interaction per orbital */
+} qcm_model;
+
+/*
+ * A sector (N_up, N_dn) and its look-up tables (subsection "Coding of the
+ * basis states": the two-way tables B_sigma and I_sigma).  Filled by
+ * qcm_sector_basis; the device pointers point into the workspace given to
+ * that call, which the caller must keep alive and unmodified while the basis
+ * is in use.  rank tables: label of a string b of popcount N is
+ *   rank_lo[b & (2^Llo - 1)] + rank_hi[popc(b & (2^Llo-1)) * 2^Lhi + (b >> Llo)]
+ * with Llo = ceil(L/2), Lhi = L - Llo.
+ */
+typedef struct qcm_basis {
+    int32_t L, n_up, n_dn;
+    int32_t l_lo, l_hi;
+    int64_t d_up, d_dn, dim;            /* dim = d_up * d_dn */
+    const uint32_t *states_up;          /* device [d_up], ascending */
+    const uint32_t *states_dn;          /* device [d_dn], ascending */
+    const int32_t *rank_lo_up, *rank_hi_up;   /* device rank tables, up spin */
+    const int32_t *rank_lo_dn, *rank_hi_dn;   /* device rank tables, down spin */
+} qcm_basis;
+
+/*
+ * qcm_sector_basis — enumerate the sector (n_up, n_dn) of L orbitals on the
+ * device: the ascending string lists of each spin and their rank tables
+ * (subsection "Coding of the basis states", sector dimension d = d(N_up)
+ * d(N_dn) with d(N) = C(L, N)).
+ *   L, n_up, n_dn : 1 <= L <= 32, 0 <= n <= L; each C(L, n) < 2^31.
+ *   d_ws, ws_bytes: device workspace; holds the tables afterwards.
+ *   ws_needed     : host, receives the bytes needed (always written).
+ *   out           : host, filled with sizes and device pointers (also when
+ *                   d_ws == NULL, with NULL pointers).
+ * Errors: QCM_ERANGE for bad L/N, QCM_EWORKSPACE, QCM_EHIP.  Asynchronous.
+ */
+int qcm_sector_basis(int32_t L, int32_t n_up, int32_t n_dn, void *d_ws, size_t ws_bytes,
+                     size_t *ws_needed, qcm_basis *out, void *stream);
+
+/*
+ * qcm_hv — w = H v on one sector (eq. (factorized): H = K_up (x) 1 +
+ * 1 (x) K_dn + V_int, with the hopping sign (-1)^M t_ab of the subsection
+ * "Coding of the basis states" and the interaction counted from
+ * b_up & b_dn).
+ *   m     : the model; b: a basis from qcm_sector_basis with b->L == m->L.
+ *   prec  : QCM_FP64 (d_v, d_w are double[dim]) or QCM_FP32V (float[dim];
+ *           accumulation in FP64, one rounding on store).
+ *   d_v   : device input vector, not modified.  d_w: device output, must
+ *           not overlap d_v.
+ *   d_ws  : device workspace for the model-dependent hopping tables.
+ * Errors: QCM_EARG (t not symmetric, L mismatch, overlap), QCM_EWORKSPACE,
+ * QCM_EHIP.  Asynchronous.
+ */
+int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, const void *d_v, void *d_w,
+           void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream);
+
+/* Options of the Lanczos ground-state solver. */
+typedef struct qcm_lanczos_opts {
+    int32_t max_iter;     /* cap on Lanczos steps (the paper's default is 600) */
+    int32_t fixed_steps;  /* >0: run exactly this many steps (fewer only on
+                             breakdown) and skip the residual test */
+    int32_t want_vector;  /* 1: second pass rebuilding the ground state into d_gs */
+    int32_t reorth;       /* 0: none (the paper's recurrence); 1: local
+                             reorthogonalisation of each new vector against the
+                             two previous ones, FP64 dot products */
+    int32_t prec;         /* QCM_FP64 or QCM_FP32V */
+    int32_t check_every;  /* residual test every this many steps (>= 1) */
+    double tol;           /* stop when beta_M |s_M| <= tol * max(1, |theta_0|) */
+    double btol;          /* breakdown when beta < btol * max |alpha| */
+    uint64_t seed;        /* SplitMix64 seed of the start vector (when d_v0 == NULL) */
+    const void *d_v0;     /* device start vector in the vector precision, or NULL */
+} qcm_lanczos_opts;
+
+/* Fill `o` with defaults: max_iter 600, fixed_steps 0, want_vector 1,
+ * reorth 0, prec QCM_FP64, check_every 1, tol 1e-12, btol 1e-13, seed 1. */
+void qcm_lanczos_default_opts(qcm_lanczos_opts *o);
+
+typedef struct qcm_gs_result {
+    double e0;            /* lowest eigenvalue of the Lanczos tridiagonal T_M */
+    double residual_est;  /* beta_M * |last component of its eigenvector| */
+    double true_residual; /* |H psi - e0 psi| (FP64), when want_vector; else -1 */
+    double theta1;        /* second-lowest eigenvalue of T_M (may be a copy of e0
+                             created by loss of orthogonality) */
+    int32_t n_iter;       /* M, number of Lanczos steps */
+    int32_t converged;    /* residual test met (or breakdown) */
+    int32_t breakdown;    /* Krylov space exhausted */
+    int32_t pad;
+} qcm_gs_result;
+
+/*
+ * qcm_lanczos_gs — lowest eigenpair of H in the sector by the Lanczos
+ * recurrence (subsection "The Lanczos algorithm for the ground state",
+ * eqs. (Krylov), (LanczosRecursion), (tridiag)), in normalised form:
+ * v_0 = x/|x|; w = H v_n - beta_{n-1} v_{n-1}; alpha_n = <v_n, w>;
+ * w -= alpha_n v_n; beta_n = |w|; v_{n+1} = w / beta_n.  beta_n^2 is the
+ * paper's b_{n+1}^2.  The ground-state vector is rebuilt by a second
+ * identical pass, psi = sum_n s_n v_n, and normalised.
+ *   Start vector when d_v0 == NULL: x_i = 2 (u_i >> 11) 2^-53 - 1, u_i the
+ *   output number i of SplitMix64 seeded with `seed`.
+ *   h_alpha, h_beta: host [max(max_iter, fixed_steps)] or NULL; receive
+ *   alpha_n and beta_n (beta[n] couples n and n+1).
+ *   d_gs  : device double[dim] or NULL; the normalised ground state
+ *           (FP64 in both precisions).  Needs want_vector = 1.
+ *   h_out : host result.
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ * Non-convergence is not an error (converged = 0).
+ */
+int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_lanczos_opts *o,
+                   double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out,
+                   void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream);
+
+/* Options of the continued-fraction Green function. */
+typedef struct qcm_green_opts {
+    int32_t n_orb;        /* number of orbitals in `orbs` */
+    const int32_t *orbs;  /* host [n_orb], distinct orbitals in [0, L) */
+    int32_t max_steps;    /* Lanczos steps per chain (continued-fraction floors) */
+    int32_t prec;         /* QCM_FP64 or QCM_FP32V vector storage */
+    int32_t reorth;       /* as in qcm_lanczos_opts */
+    int32_t pad;
+    double btol;          /* chain stops when beta < btol * max |alpha| */
+} qcm_green_opts;
+
+/*
+ * qcm_green_cf — up-spin zero-temperature Green function G_ij(z), i, j in
+ * `orbs`, from Lanczos continued fractions (subsection "The Lanczos
+ * algorithm for the Green function", eqs. (green), (GreenCF1), (jacobi)):
+ *  - for each pair p = (i <= j): an electron chain from
+ *    (c_i + c_j)+ |Omega> in sector (n_up + 1, n_dn) and a hole chain from
+ *    (c_i + c_j) |Omega> in (n_up - 1, n_dn) (a single operator if i == j);
+ *  - b0^2 = <phi|phi>, then Lanczos from phi/b0 gives a_n, b_n;
+ *  - G_e(z) = b0^2/(z + E0 - a_0 - b_1^2/(z + E0 - a_1 - ...)),
+ *    G_h(z) = b0^2/(z - E0 + a_0 - b_1^2/(z - E0 + a_1 - ...));
+ *  - G_ii = G_e + G_h; G_ij = (G+_ij - G_ii - G_jj)/2 for a real H.
+ *   gs    : basis of the ground-state sector; d_gs: device double[gs->dim],
+ *           the normalised ground state; e0: its energy.
+ *   h_coef: host [n_pairs][2][1 + 2*max_steps] or NULL, pairs ordered
+ *           (0,0),(0,1),...,(0,n-1),(1,1),...; part 0 = electron, 1 = hole;
+ *           each entry holds b0sq, then a[max_steps], then b2[max_steps]
+ *           (b2[n] = b_{n+1}^2 couples floors n and n+1).
+ *   h_len : host [n_pairs][2] or NULL, number of floors of each chain.
+ *   n_z, h_z: host complex frequencies [n_z] as (re, im) pairs.
+ *   d_G   : device complex128 [n_z][n_orb][n_orb] (re, im interleaved).
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const double *d_gs, double e0,
+                 const qcm_green_opts *o, double *h_coef, int32_t *h_len, int32_t n_z,
+                 const double *h_z, double *d_G, void *d_ws, size_t ws_bytes, size_t *ws_needed,
+                 void *stream);
+
+/* An inter-cluster hopping term for CPT: amplitude t between site i of the
+ * cluster at the origin and site j of the cluster at shift[0] E1 +
+ * shift[1] E2 + shift[2] E3.  Its Hermitian partner is implied. */
+typedef struct qcm_bond {
+    int32_t i, j;
+    int32_t shift[3];
+    int32_t pad;
+    double t;
+} qcm_bond;
+
+/*
+ * qcm_cpt_gk — CPT Green function with G-scheme periodisation (section
+ * "Cluster perturbation theory", eqs. (CPT1), (CPT3)):
+ *   V(k)_ij = sum_bonds t exp(i k.r) (+ Hermitian partner), r = shift.E,
+ *   G(k, z) = (G_c(z)^-1 - V(k))^-1,
+ *   G_per(k, z) = (1/L) sum_ij exp(-i k.(R_i - R_j)) G_ij(k, z),
+ * with the partial Fourier convention of subsection "Partial Fourier
+ * transforms".
+ *   L     : cluster sites (<= 32); n_z: frequencies; d_Gc: device complex128
+ *           [n_z][L][L], the cluster Green function (e.g. from qcm_green_cf).
+ *   h_R   : host int32 [L][3] site positions; h_E: host int32 [3][3]
+ *           super-lattice vectors (rows).
+ *   n_bonds, h_bonds: host inter-cluster bonds.
+ *   n_k, h_k: host double [n_k][3], wave-vectors in units of 2 pi.
+ *   d_Gper: device complex128 [n_k][n_z].
+ *   d_ws  : device workspace.
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Asynchronous.
+ */
+int qcm_cpt_gk(int32_t L, int32_t n_z, const double *d_Gc, const int32_t *h_R,
+               const int32_t *h_E, int32_t n_bonds, const qcm_bond *h_bonds, int32_t n_k,
+               const double *h_k, double *d_Gper, void *d_ws, size_t ws_bytes,
+               size_t *ws_needed, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCM_H */

@@ -73,6 +73,9 @@ def _load():
         lib.ora_hv_rows_f32.restype = ctypes.c_int
         lib.ora_hv_rows_f32.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, ctypes.c_int, _f,
                                         _i64, ctypes.c_int64, _d, ctypes.c_int]
+        lib.ora_hv_absbound.restype = ctypes.c_int
+        lib.ora_hv_absbound.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, ctypes.c_int, _d,
+                                        _i64, ctypes.c_int64, _d, ctypes.c_int]
         lib.ora_tridiag_eig.restype = ctypes.c_double
         lib.ora_tridiag_eig.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int]
         lib.ora_tridiag_vec.restype = None
@@ -177,6 +180,25 @@ def hv_rows(t, U, nup: int, ndn: int, v: np.ndarray, rows, nthreads: int | None 
         rc = lib.ora_hv_rows(L, _p(t, _d), _p(U, _d), nup, ndn, _p(v, _d),
                              _p(rows, _i64), rows.shape[0], _p(out, _d),
                              nthreads or default_threads())
+    assert rc == 0
+    return out
+
+
+def hv_abs_bound(t, U, nup: int, ndn: int, v: np.ndarray, rows=None,
+                 nthreads: int | None = None) -> np.ndarray:
+    """sum_j |H_ij| |v_j| for every row (or the listed rows): the scale of the
+    rounding error of (H v)_i."""
+    L, t, U = _model_arrays(t, U)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    if rows is None:
+        out = np.empty(v.shape[0])
+        rp, n = None, 0
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.empty(rows.shape[0])
+        rp, n = _p(rows, _i64), rows.shape[0]
+    rc = _load().ora_hv_absbound(L, _p(t, _d), _p(U, _d), nup, ndn, _p(v, _d), rp, n,
+                                 _p(out, _d), nthreads or default_threads())
     assert rc == 0
     return out
 

@@ -105,11 +105,25 @@ uint64_t ora_splitmix(uint64_t seed, uint64_t i) { return splitmix_at(seed, i); 
 /* occupied orbitals strictly between a and c.  The interaction counts   */
 /* the doubly occupied orbitals (bitwise and of the two spin strings).   */
 
+/* A sector with its two-way look-up tables: the string lists B_sigma and,
+ * for L <= 24, the inverse tables I_sigma[b] (position of b in its list,
+ * -1 for strings of another popcount).  For L > 24 the label comes from the
+ * combinatorial sum ora_rank. */
 typedef struct {
     int L, nup, ndn;
     int64_t dup, ddn;
     uint32_t *su, *sd;
+    int32_t *iu, *id;
 } sector_t;
+
+static int32_t *inverse_table(int L, const uint32_t *st, int64_t d)
+{
+    if (L > 24) return NULL;
+    int32_t *t = (int32_t *)malloc(sizeof(int32_t) << L);
+    for (int64_t x = 0; x < ((int64_t)1 << L); x++) t[x] = -1;
+    for (int64_t i = 0; i < d; i++) t[st[i]] = (int32_t)i;
+    return t;
+}
 
 static int sector_init(sector_t *s, int L, int nup, int ndn)
 {
@@ -120,10 +134,17 @@ static int sector_init(sector_t *s, int L, int nup, int ndn)
     s->sd = (uint32_t *)malloc(sizeof(uint32_t) * s->ddn);
     ora_enumerate(L, nup, s->su);
     ora_enumerate(L, ndn, s->sd);
+    s->iu = inverse_table(L, s->su, s->dup);
+    s->id = inverse_table(L, s->sd, s->ddn);
     return 0;
 }
 
-static void sector_free(sector_t *s) { free(s->su); free(s->sd); }
+static void sector_free(sector_t *s) { free(s->su); free(s->sd); free(s->iu); free(s->id); }
+
+static int64_t label(const int32_t *inv, uint32_t b)
+{
+    return inv ? (int64_t)inv[b] : ora_rank(b);
+}
 
 /* occupied orbitals strictly between a and c in string b */
 static int between_count(uint32_t b, int a, int c)
@@ -166,19 +187,64 @@ static double hv_row(const sector_t *s, const double *t, const double *U,
             if ((bu >> a & 1u) && !(bu >> c & 1u)) {
                 uint32_t bj = bu ^ (1u << a) ^ (1u << c);
                 double sg = (between_count(bu, a, c) & 1) ? -1.0 : 1.0;
-                int64_t j = ora_rank(bj) + s->dup * id;
+                int64_t j = label(s->iu, bj) + s->dup * id;
                 acc += tac * sg * v[j];
             }
             /* down spin */
             if ((bd >> a & 1u) && !(bd >> c & 1u)) {
                 uint32_t bj = bd ^ (1u << a) ^ (1u << c);
                 double sg = (between_count(bd, a, c) & 1) ? -1.0 : 1.0;
-                int64_t j = iu + s->dup * ora_rank(bj);
+                int64_t j = iu + s->dup * label(s->id, bj);
                 acc += tac * sg * v[j];
             }
         }
     }
     return acc;
+}
+
+/* Rounding bound of a row: sum_j |H_ij| |v_j| (absolute values of every
+ * term of hv_row, signs dropped). */
+static double hv_row_abs(const sector_t *s, const double *t, const double *U,
+                         const double *v, int64_t i)
+{
+    const int L = s->L;
+    int64_t iu = i % s->dup, id = i / s->dup;
+    uint32_t bu = s->su[iu], bd = s->sd[id];
+    double dg = 0.0;
+    for (int k = 0; k < L; k++) {
+        int nu = (bu >> k) & 1u, nd = (bd >> k) & 1u;
+        dg += fabs(t[k * L + k]) * (nu + nd);
+        if (nu && nd) dg += fabs(U[k]);
+    }
+    double acc = dg * fabs(v[i]);
+    for (int a = 0; a < L; a++)
+        for (int c = 0; c < L; c++) {
+            if (a == c || t[a * L + c] == 0.0) continue;
+            double tac = fabs(t[a * L + c]);
+            if ((bu >> a & 1u) && !(bu >> c & 1u))
+                acc += tac * fabs(v[label(s->iu, bu ^ (1u << a) ^ (1u << c)) + s->dup * id]);
+            if ((bd >> a & 1u) && !(bd >> c & 1u))
+                acc += tac * fabs(v[iu + s->dup * label(s->id, bd ^ (1u << a) ^ (1u << c))]);
+        }
+    return acc;
+}
+
+int ora_hv_absbound(int L, const double *t, const double *U, int nup, int ndn,
+                    const double *v, const int64_t *rows, int64_t nrows,
+                    double *out, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int64_t n = rows ? nrows : s.dup * s.ddn;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; r++) out[r] = hv_row_abs(&s, t, U, v, rows ? rows[r] : r);
+    sector_free(&s);
+    return 0;
 }
 
 /* w = H v over the whole sector (eq. (factorized) applied element by
@@ -247,12 +313,12 @@ int ora_hv_rows_f32(int L, const double *t, const double *U, int nup,
                 if ((bu >> a & 1u) && !(bu >> c & 1u)) {
                     uint32_t bj = bu ^ (1u << a) ^ (1u << c);
                     double sg = (between_count(bu, a, c) & 1) ? -1.0 : 1.0;
-                    acc += tac * sg * (double)vf[ora_rank(bj) + s.dup * id];
+                    acc += tac * sg * (double)vf[label(s.iu, bj) + s.dup * id];
                 }
                 if ((bd >> a & 1u) && !(bd >> c & 1u)) {
                     uint32_t bj = bd ^ (1u << a) ^ (1u << c);
                     double sg = (between_count(bd, a, c) & 1) ? -1.0 : 1.0;
-                    acc += tac * sg * (double)vf[iu + s.dup * ora_rank(bj)];
+                    acc += tac * sg * (double)vf[iu + s.dup * label(s.id, bj)];
                 }
             }
         out[r] = acc;
@@ -512,7 +578,7 @@ int ora_apply_cdag_c(int L, int nup, int ndn, const double *psi, int kind,
             uint32_t b2 = bu ^ (1u << m);
             int below = popc(bu & ((1u << m) - 1u));
             double sg = (below & 1) ? -1.0 : 1.0;
-            int64_t j = ora_rank(b2) + s2.dup * id;
+            int64_t j = label(s2.iu, b2) + s2.dup * id;
             out[j] += sg * psi[i];
         }
     }

@@ -1,0 +1,332 @@
+"""ctypes binding of libqcm.so (the C ABI in include/qcm.h).
+
+Argument marshalling only: torch provides device memory (vectors and
+workspaces as CUDA/HIP tensors) and the current stream; every step of the
+computation runs in the library's HIP kernels.  If the library is missing or a
+GPU is not available the calls raise; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcm.so")
+
+QCM_OK, QCM_EARG, QCM_ERANGE, QCM_EWORKSPACE, QCM_EHIP = 0, -1, -2, -3, -4
+QCM_FP64, QCM_FP32V = 0, 1
+PREC = {"fp64": QCM_FP64, "fp32v": QCM_FP32V, QCM_FP64: QCM_FP64, QCM_FP32V: QCM_FP32V}
+
+_c_d = ctypes.POINTER(ctypes.c_double)
+_c_i32 = ctypes.POINTER(ctypes.c_int32)
+_c_sz = ctypes.POINTER(ctypes.c_size_t)
+
+
+class QcmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qcm error {code}: {msg}")
+        self.code = code
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("t", _c_d), ("U", _c_d)]
+
+
+class Basis(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("l_lo", ctypes.c_int32), ("l_hi", ctypes.c_int32),
+                ("d_up", ctypes.c_int64), ("d_dn", ctypes.c_int64), ("dim", ctypes.c_int64),
+                ("states_up", ctypes.c_void_p), ("states_dn", ctypes.c_void_p),
+                ("rank_lo_up", ctypes.c_void_p), ("rank_hi_up", ctypes.c_void_p),
+                ("rank_lo_dn", ctypes.c_void_p), ("rank_hi_dn", ctypes.c_void_p)]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
+                ("want_vector", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("btol", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("d_v0", ctypes.c_void_p)]
+
+
+class GsResult(ctypes.Structure):
+    _fields_ = [("e0", ctypes.c_double), ("residual_est", ctypes.c_double),
+                ("true_residual", ctypes.c_double), ("theta1", ctypes.c_double),
+                ("n_iter", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class GreenOpts(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("orbs", _c_i32), ("max_steps", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("reorth", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("btol", ctypes.c_double)]
+
+
+class Bond(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("shift", ctypes.c_int32 * 3),
+                ("pad", ctypes.c_int32), ("t", ctypes.c_double)]
+
+
+# every symbol declared in include/qcm.h
+EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
+           "qcm_lanczos_default_opts", "qcm_lanczos_gs", "qcm_green_cf", "qcm_cpt_gk"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqcm.so and declare the signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or "
+                           "python paper_2305_18643_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.qcm_last_error.restype = ctypes.c_char_p
+    lib.qcm_last_error.argtypes = []
+    lib.qcm_version.restype = ctypes.c_int
+    lib.qcm_sector_basis.restype = ctypes.c_int
+    lib.qcm_sector_basis.argtypes = [ctypes.c_int32] * 3 + [vp, sz, _c_sz, ctypes.POINTER(Basis), vp]
+    lib.qcm_hv.restype = ctypes.c_int
+    lib.qcm_hv.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Basis), ctypes.c_int32, vp, vp,
+                           vp, sz, _c_sz, vp]
+    lib.qcm_lanczos_default_opts.restype = None
+    lib.qcm_lanczos_default_opts.argtypes = [ctypes.POINTER(LanczosOpts)]
+    lib.qcm_lanczos_gs.restype = ctypes.c_int
+    lib.qcm_lanczos_gs.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Basis),
+                                   ctypes.POINTER(LanczosOpts), _c_d, _c_d, vp,
+                                   ctypes.POINTER(GsResult), vp, sz, _c_sz, vp]
+    lib.qcm_green_cf.restype = ctypes.c_int
+    lib.qcm_green_cf.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Basis), vp,
+                                 ctypes.c_double, ctypes.POINTER(GreenOpts), _c_d, _c_i32,
+                                 ctypes.c_int32, _c_d, vp, vp, sz, _c_sz, vp]
+    lib.qcm_cpt_gk.restype = ctypes.c_int
+    lib.qcm_cpt_gk.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, _c_i32, _c_i32,
+                               ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, _c_d, vp,
+                               vp, sz, _c_sz, vp]
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != QCM_OK:
+        raise QcmError(code, _lib.qcm_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the qcm library runs only on the device")
+    return torch
+
+
+def _stream(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _workspace(torch, nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class HostModel:
+    """(t, U) kept alive as contiguous float64 arrays plus the C struct."""
+
+    def __init__(self, t, U):
+        self.t = np.ascontiguousarray(t, dtype=np.float64)
+        self.U = np.ascontiguousarray(U, dtype=np.float64)
+        L = self.t.shape[0]
+        if self.t.shape != (L, L) or self.U.shape != (L,):
+            raise ValueError("t must be L x L and U of length L")
+        self.c = Model(L, self.t.ctypes.data_as(_c_d), self.U.ctypes.data_as(_c_d))
+
+    @property
+    def L(self):
+        return self.t.shape[0]
+
+
+def as_model(m) -> HostModel:
+    if isinstance(m, HostModel):
+        return m
+    if isinstance(m, tuple):
+        return HostModel(*m)
+    return HostModel(m.t, m.U)
+
+
+class SectorBasis:
+    """A device sector basis; owns the workspace its tables live in."""
+
+    def __init__(self, L: int, n_up: int, n_dn: int, device="cuda", stream=None):
+        torch = _torch()
+        lib = load_library()
+        self.c = Basis()
+        need = ctypes.c_size_t(0)
+        _check(lib.qcm_sector_basis(L, n_up, n_dn, None, 0, ctypes.byref(need),
+                                    ctypes.byref(self.c), None))
+        self.ws = _workspace(torch, need.value, device)
+        _check(lib.qcm_sector_basis(L, n_up, n_dn, _ptr(self.ws), self.ws.numel(),
+                                    ctypes.byref(need), ctypes.byref(self.c),
+                                    _stream(torch, stream)))
+        self.device = self.ws.device
+
+    L = property(lambda self: self.c.L)
+    n_up = property(lambda self: self.c.n_up)
+    n_dn = property(lambda self: self.c.n_dn)
+    d_up = property(lambda self: self.c.d_up)
+    d_dn = property(lambda self: self.c.d_dn)
+    dim = property(lambda self: self.c.dim)
+
+    def states(self, spin: int):
+        """Device uint32 string list of one spin (as an int64 copy)."""
+        torch = _torch()
+        d = self.d_up if spin == 0 else self.d_dn
+        ptr = self.c.states_up if spin == 0 else self.c.states_dn
+        base = self.ws.data_ptr()
+        off = ptr - base
+        raw = self.ws[off: off + 4 * d].view(torch.int32)
+        return raw.to(torch.int64) & 0xFFFFFFFF
+
+    def rank_tables(self, spin: int):
+        torch = _torch()
+        lo = self.c.rank_lo_up if spin == 0 else self.c.rank_lo_dn
+        hi = self.c.rank_hi_up if spin == 0 else self.c.rank_hi_dn
+        base = self.ws.data_ptr()
+        n_lo = 1 << self.c.l_lo
+        n_hi = (self.c.l_lo + 1) << self.c.l_hi
+        tlo = self.ws[lo - base: lo - base + 4 * n_lo].view(torch.int32)
+        thi = self.ws[hi - base: hi - base + 4 * n_hi].view(torch.int32)
+        return tlo, thi
+
+
+def sector_basis(L: int, n_up: int, n_dn: int, device="cuda", stream=None) -> SectorBasis:
+    return SectorBasis(L, n_up, n_dn, device, stream)
+
+
+def hv(model, basis: SectorBasis, v, w=None, stream=None, ws=None):
+    """w = H v.  v: device float64 (FP64) or float32 (FP32-vector) tensor."""
+    torch = _torch()
+    lib = load_library()
+    m = as_model(model)
+    prec = QCM_FP64 if v.dtype == torch.float64 else QCM_FP32V
+    if v.dtype not in (torch.float64, torch.float32) or v.numel() != basis.dim or not v.is_contiguous():
+        raise ValueError("v must be a contiguous float64/float32 tensor of length dim")
+    if w is None:
+        w = torch.empty_like(v)
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(basis.c), prec, None, None, None, 0,
+                      ctypes.byref(need), None))
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(torch, need.value, v.device)
+    _check(lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(basis.c), prec, _ptr(v), _ptr(w), _ptr(ws),
+                      ws.numel(), ctypes.byref(need), _stream(torch, stream)))
+    return w
+
+
+def lanczos_gs(model, basis: SectorBasis, *, max_iter=600, fixed_steps=0, want_vector=True,
+               reorth=0, prec="fp64", check_every=1, tol=1e-12, btol=1e-13, seed=1, v0=None,
+               stream=None, ws=None) -> dict:
+    """Lanczos ground state; returns e0, residuals, n_iter, flags, alpha, beta, psi."""
+    torch = _torch()
+    lib = load_library()
+    m = as_model(model)
+    o = LanczosOpts()
+    lib.qcm_lanczos_default_opts(ctypes.byref(o))
+    o.max_iter, o.fixed_steps, o.want_vector, o.reorth = max_iter, fixed_steps, int(want_vector), reorth
+    o.prec, o.check_every, o.tol, o.btol, o.seed = PREC[prec], check_every, tol, btol, seed
+    if v0 is not None:
+        want = torch.float64 if o.prec == QCM_FP64 else torch.float32
+        if v0.dtype != want or v0.numel() != basis.dim:
+            raise ValueError("v0 has the wrong dtype or size")
+        o.d_v0 = v0.data_ptr()
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_lanczos_gs(ctypes.byref(m.c), ctypes.byref(basis.c), ctypes.byref(o), None,
+                              None, None, None, None, 0, ctypes.byref(need), None))
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(torch, need.value, basis.device)
+    n = max(max_iter, fixed_steps)
+    alpha = np.zeros(n)
+    beta = np.zeros(n)
+    psi = torch.empty(basis.dim, dtype=torch.float64, device=basis.device) if want_vector else None
+    res = GsResult()
+    _check(lib.qcm_lanczos_gs(ctypes.byref(m.c), ctypes.byref(basis.c), ctypes.byref(o),
+                              alpha.ctypes.data_as(_c_d), beta.ctypes.data_as(_c_d), _ptr(psi),
+                              ctypes.byref(res), _ptr(ws), ws.numel(), ctypes.byref(need),
+                              _stream(torch, stream)))
+    M = res.n_iter
+    return dict(e0=res.e0, residual_est=res.residual_est, true_residual=res.true_residual,
+                theta1=res.theta1, n_iter=M, converged=bool(res.converged),
+                breakdown=bool(res.breakdown), alpha=alpha[:M], beta=beta[:M], psi=psi)
+
+
+def green_cf(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_steps=200, prec="fp64",
+             reorth=0, btol=1e-13, stream=None, ws=None) -> dict:
+    """Continued-fraction up-spin G_ij(z) for i, j in orbs; returns G (device
+    complex128 [n_z, n, n]), coef (numpy [n_pairs, 2, 1 + 2 max_steps]) and
+    len (numpy [n_pairs, 2])."""
+    torch = _torch()
+    lib = load_library()
+    m = as_model(model)
+    orbs_a = np.ascontiguousarray(orbs, dtype=np.int32)
+    n = orbs_a.shape[0]
+    npairs = n * (n + 1) // 2
+    o = GreenOpts(n, orbs_a.ctypes.data_as(_c_i32), max_steps, PREC[prec], reorth, 0, btol)
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1).ravel())
+    nz = z.shape[0]
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_green_cf(ctypes.byref(m.c), ctypes.byref(basis.c), None, e0, ctypes.byref(o),
+                            None, None, nz, zz.ctypes.data_as(_c_d), None, None, 0,
+                            ctypes.byref(need), None))
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(torch, need.value, basis.device)
+    G = torch.zeros((max(nz, 1), n, n), dtype=torch.complex128, device=basis.device)
+    coef = np.zeros((npairs, 2, 1 + 2 * max_steps))
+    lens = np.zeros((npairs, 2), dtype=np.int32)
+    if psi.dtype != torch.float64 or psi.numel() != basis.dim:
+        raise ValueError("psi must be a float64 device vector of the basis dimension")
+    _check(lib.qcm_green_cf(ctypes.byref(m.c), ctypes.byref(basis.c), _ptr(psi), float(e0),
+                            ctypes.byref(o), coef.ctypes.data_as(_c_d),
+                            lens.ctypes.data_as(_c_i32), nz, zz.ctypes.data_as(_c_d),
+                            ctypes.c_void_p(G.data_ptr()), _ptr(ws), ws.numel(),
+                            ctypes.byref(need), _stream(torch, stream)))
+    return dict(G=G[:nz], coef=coef, len=lens)
+
+
+def cpt_gk(Gc, R, E, bonds, ks, z=None, stream=None):
+    """CPT G-scheme periodised G(k, z).  Gc: device complex128 [n_z, L, L];
+    bonds: iterable of (i, j, (s1, s2, s3), t); ks [n_k, 3] in units of 2 pi.
+    Returns device complex128 [n_k, n_z]."""
+    torch = _torch()
+    lib = load_library()
+    if Gc.dtype != torch.complex128 or Gc.dim() != 3 or not Gc.is_contiguous():
+        raise ValueError("Gc must be a contiguous complex128 [n_z, L, L] tensor")
+    nz, L, _ = Gc.shape
+    R = np.ascontiguousarray(R, dtype=np.int32).reshape(L, 3)
+    E = np.ascontiguousarray(E, dtype=np.int32).reshape(3, 3)
+    ks = np.ascontiguousarray(ks, dtype=np.float64).reshape(-1, 3)
+    bl = list(bonds)
+    barr = (Bond * max(len(bl), 1))()
+    for q, (i, j, s, t) in enumerate(bl):
+        barr[q].i, barr[q].j, barr[q].t = int(i), int(j), float(t)
+        for a in range(3):
+            barr[q].shift[a] = int(s[a])
+    out = torch.zeros((ks.shape[0], nz), dtype=torch.complex128, device=Gc.device)
+    need = ctypes.c_size_t(0)
+    args = (L, nz)
+    _check(lib.qcm_cpt_gk(*args, None, R.ctypes.data_as(_c_i32), E.ctypes.data_as(_c_i32),
+                          len(bl), barr, ks.shape[0], ks.ctypes.data_as(_c_d), None, None, 0,
+                          ctypes.byref(need), None))
+    ws = _workspace(torch, need.value, Gc.device)
+    _check(lib.qcm_cpt_gk(*args, ctypes.c_void_p(Gc.data_ptr()), R.ctypes.data_as(_c_i32),
+                          E.ctypes.data_as(_c_i32), len(bl), barr, ks.shape[0],
+                          ks.ctypes.data_as(_c_d), ctypes.c_void_p(out.data_ptr()), _ptr(ws),
+                          ws.numel(), ctypes.byref(need), _stream(torch, stream)))
+    return out

@@ -1,0 +1,321 @@
+// Continued-fraction Green function (paper: section "Exact diagonalizations",
+// subsection "The Lanczos algorithm for the Green function", eqs. (green),
+// (GreenCF1), (jacobi) and the off-diagonal trick for a real H).
+//
+// For every pair (i <= j) of the requested orbitals two chains are run:
+// electron, from (c_i + c_j)+ |Omega> in sector (N_up + 1, N_dn), and hole,
+// from (c_i + c_j) |Omega> in (N_up - 1, N_dn).  All chains of one part live
+// in the same sector, so they run together through the multi-chain engine.
+// Start vectors are built by a gather over the target sector: only the up
+// string changes, the sign is (-1)^(up electrons on orbitals below the
+// operator's orbital), and the down label is untouched.
+#include <math.h>
+#include <string.h>
+
+#include "lanczos_engine.h"
+
+namespace qcm {
+
+int engine_normalize_from_partials(Engine &e, hipStream_t s);
+
+struct PairOps {
+    int32_t mu[2];
+};
+
+// phi_c = sum over the chain's operators of sign * psi[source], gathered per
+// target element; partial sums of |phi|^2 (FP64, before rounding).
+template <typename T>
+__global__ void __launch_bounds__(256) k_apply_ops(
+    const double *__restrict__ psi, int64_t d_src_up, const int32_t *__restrict__ rlo_src,
+    const int32_t *__restrict__ rhi_src, int l_lo, int l_hi,
+    const uint32_t *__restrict__ states_tgt, int64_t d_tgt_up, int64_t dim_tgt, int kind,
+    const int32_t *__restrict__ ops, T *__restrict__ out, int nchunks,
+    double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int c = blockIdx.y;
+    const int o0 = ops[2 * c], o1 = ops[2 * c + 1];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i >= dim_tgt) break;
+        int64_t iu = i % d_tgt_up, idn = i / d_tgt_up;
+        uint32_t bt = states_tgt[iu];
+        double val = 0.0;
+        for (int q = 0; q < 2; ++q) {
+            int m = q == 0 ? o0 : o1;
+            if (m < 0) continue;
+            uint32_t bit = 1u << m;
+            bool has = bt & bit;
+            // kind 0 (creation): target has m, source lacks it; kind 1: reverse
+            if ((kind == 0) != has) continue;
+            uint32_t bs = bt ^ bit;
+            int below = __popc(bt & (bit - 1u));
+            int64_t j = (int64_t)spin_rank(rlo_src, rhi_src, l_lo, l_hi, bs) + d_src_up * idn;
+            double x = psi[j];
+            val += (below & 1) ? -x : x;
+        }
+        out[(int64_t)c * dim_tgt + i] = (T)val;
+        acc = fma(val, val, acc);
+    }
+    // fixed tree
+    const int t = threadIdx.x;
+    sh[t] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    if (t == 0) partial[(int64_t)c * nchunks + blockIdx.x] = sh[0];
+}
+
+// coef[(c*2 + part) * stride]: b0sq, a[maxs], b2[maxs]; len[c*2 + part]
+__global__ void k_store_coef(ChainState cs, int nvec, int part, double *__restrict__ coef,
+                             int32_t *__restrict__ len, int stride) {
+    int c = blockIdx.x;
+    if (c >= nvec) return;
+    double *o = coef + (int64_t)(c * 2 + part) * stride;
+    int L = cs.len[c];
+    for (int n = threadIdx.x; n < cs.maxs; n += blockDim.x) {
+        o[1 + n] = n < L ? cs.alpha[(int64_t)c * cs.maxs + n] : 0.0;
+        double b = cs.beta[(int64_t)c * cs.maxs + n];
+        o[1 + cs.maxs + n] = n + 1 < L ? b * b : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        o[0] = cs.b0sq[c];
+        len[c * 2 + part] = L;
+    }
+}
+
+__global__ void k_zero_coef(int npairs, int part, double *__restrict__ coef,
+                            int32_t *__restrict__ len, int stride) {
+    int c = blockIdx.x;
+    double *o = coef + (int64_t)(c * 2 + part) * stride;
+    for (int n = threadIdx.x; n < stride; n += blockDim.x) o[n] = 0.0;
+    if (threadIdx.x == 0) len[c * 2 + part] = 0;
+}
+
+struct cplx {
+    double re, im;
+};
+
+// One continued fraction at z, bottom floor first.  part 0 (electron):
+// b0sq / (z + E0 - a0 - b1^2/(z + E0 - a1 - ...)); part 1 (hole):
+// b0sq / (z - E0 + a0 - b1^2/(z - E0 + a1 - ...)).
+__device__ cplx cf_value(const double *__restrict__ co, int len, int maxs, cplx z, double e0,
+                         int part) {
+    cplx r{0.0, 0.0};
+    if (len <= 0 || co[0] == 0.0) return r;
+    const double sg = part == 0 ? 1.0 : -1.0;
+    const double zr = part == 0 ? z.re + e0 : z.re - e0;
+    const double zi = z.im;
+    const double *a = co + 1, *b2 = co + 1 + maxs;
+    double gr = zr - sg * a[len - 1], gi = zi;
+    for (int n = len - 2; n >= 0; --n) {
+        double den = gr * gr + gi * gi;
+        double qr = b2[n] * gr / den, qi = -b2[n] * gi / den;  // b2 / g
+        gr = zr - sg * a[n] - qr;
+        gi = zi - qi;
+    }
+    double den = gr * gr + gi * gi;
+    r.re = co[0] * gr / den;
+    r.im = -co[0] * gi / den;
+    return r;
+}
+
+// F[z][p] = G_e + G_h of pair p
+__global__ void k_cf_pairs(const double *__restrict__ coef, const int32_t *__restrict__ len,
+                           int npairs, int maxs, int nz, const double *__restrict__ zs, double e0,
+                           double *__restrict__ F) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nz * npairs) return;
+    int iz = (int)(e / npairs), p = (int)(e % npairs);
+    cplx z{zs[2 * iz], zs[2 * iz + 1]};
+    const int stride = 1 + 2 * maxs;
+    cplx g0 = cf_value(coef + (int64_t)(p * 2 + 0) * stride, len[p * 2 + 0], maxs, z, e0, 0);
+    cplx g1 = cf_value(coef + (int64_t)(p * 2 + 1) * stride, len[p * 2 + 1], maxs, z, e0, 1);
+    F[2 * e] = g0.re + g1.re;
+    F[2 * e + 1] = g0.im + g1.im;
+}
+
+// G[z][i][j]: diagonal pairs directly, off-diagonal (F_ij - F_ii - F_jj)/2
+__global__ void k_cf_combine(const double *__restrict__ F, const int32_t *__restrict__ pidx,
+                             int n, int npairs, int nz, double *__restrict__ G) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nz * n * n) return;
+    int iz = (int)(e / (n * n));
+    int ij = (int)(e % (n * n));
+    int i = ij / n, j = ij % n;
+    int a = i < j ? i : j, b = i < j ? j : i;
+    const double *f = F + (int64_t)iz * npairs * 2;
+    int pab = pidx[a * n + b];
+    double re = f[2 * pab], im = f[2 * pab + 1];
+    if (a != b) {
+        int paa = pidx[a * n + a], pbb = pidx[b * n + b];
+        re = 0.5 * (re - f[2 * paa] - f[2 * pbb]);
+        im = 0.5 * (im - f[2 * paa + 1] - f[2 * pbb + 1]);
+    }
+    G[2 * e] = re;
+    G[2 * e + 1] = im;
+}
+
+}  // namespace qcm
+
+using namespace qcm;
+
+static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o,
+                          int n_z) {
+    const int L = m->L;
+    const int npairs = o->n_orb * (o->n_orb + 1) / 2;
+    size_t need = model_dev_bytes(L) + hop_tables_bytes(m, gs->d_dn) + 4096;
+    size_t part_max = 0;
+    for (int part = 0; part < 2; ++part) {
+        int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
+        if (nup2 < 0 || nup2 > L) continue;
+        int64_t du2 = binom(L, nup2);
+        size_t b = spin_tables_bytes(L, nup2) + hop_tables_bytes(m, du2) +
+                   engine_bytes(o->prec, npairs, du2 * gs->d_dn, o->max_steps);
+        if (b > part_max) part_max = b;
+    }
+    need += part_max;
+    const int stride = 1 + 2 * o->max_steps;
+    need += sizeof(double) * (size_t)npairs * 2 * stride + 256;
+    need += sizeof(int32_t) * (size_t)npairs * 2 + 256;
+    need += sizeof(int32_t) * (size_t)npairs * 2 + 256;
+    need += sizeof(int32_t) * (size_t)o->n_orb * o->n_orb + 256;
+    need += sizeof(double) * 2 * (size_t)n_z + 256;
+    need += sizeof(double) * 2 * (size_t)n_z * npairs + 256;
+    return need;
+}
+
+extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const double *d_gs,
+                            double e0, const qcm_green_opts *o, double *h_coef, int32_t *h_len,
+                            int32_t n_z, const double *h_z, double *d_G, void *d_ws,
+                            size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!ws_needed || !o) return fail(QCM_EARG, "qcm_green_cf: NULL ws_needed or opts");
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(gs, m->L));
+    const int L = m->L;
+    if (o->n_orb < 1 || o->n_orb > L || !o->orbs)
+        return fail(QCM_EARG, "qcm_green_cf: bad orbital list");
+    for (int i = 0; i < o->n_orb; ++i) {
+        if (o->orbs[i] < 0 || o->orbs[i] >= L)
+            return fail(QCM_EARG, "qcm_green_cf: orbital %d out of range", o->orbs[i]);
+        for (int j = 0; j < i; ++j)
+            if (o->orbs[j] == o->orbs[i]) return fail(QCM_EARG, "qcm_green_cf: repeated orbital");
+    }
+    if (o->max_steps < 1) return fail(QCM_EARG, "qcm_green_cf: max_steps < 1");
+    if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
+        return fail(QCM_EARG, "qcm_green_cf: bad prec");
+    if (n_z < 0 || (n_z > 0 && (!h_z || (!d_G && d_ws))))
+        return fail(QCM_EARG, "qcm_green_cf: bad frequency arguments");
+    size_t need = green_bytes(m, gs, o, n_z);
+    *ws_needed = need;
+    if (!d_ws) return QCM_OK;
+    if (!d_gs) return fail(QCM_EARG, "qcm_green_cf: d_gs is NULL");
+    if (ws_bytes < need)
+        return fail(QCM_EWORKSPACE, "qcm_green_cf: workspace %zu < %zu", ws_bytes, need);
+
+    hipStream_t s = as_stream(stream);
+    const int n = o->n_orb;
+    const int npairs = n * (n + 1) / 2;
+    const int maxs = o->max_steps;
+    const int stride = 1 + 2 * maxs;
+
+    // pair list and index
+    std::vector<int32_t> ops(2 * npairs), pidx(n * n, 0);
+    {
+        int p = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i; j < n; ++j) {
+                ops[2 * p] = o->orbs[i];
+                ops[2 * p + 1] = i == j ? -1 : o->orbs[j];
+                pidx[i * n + j] = p;
+                pidx[j * n + i] = p;
+                ++p;
+            }
+    }
+    Carver cv(d_ws);
+    ModelDev md;
+    QCM_TRY(upload_model(m, cv, &md, s));
+    const int nb = count_bonds(m);
+    SpinTables dn = spin_from_basis(gs, 1);
+    SpinTables upg = spin_from_basis(gs, 0);
+    HopTables hd;
+    QCM_TRY(build_hop_tables(md, dn, cv, &hd, s, nb));
+    double *coef = cv.take<double>((size_t)npairs * 2 * stride);
+    int32_t *lenv = cv.take<int32_t>((size_t)npairs * 2);
+    int32_t *ops_d = cv.take<int32_t>((size_t)npairs * 2);
+    int32_t *pidx_d = cv.take<int32_t>((size_t)n * n);
+    double *z_d = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1));
+    double *F = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1) * npairs);
+    QCM_HIP(hipMemcpyAsync(ops_d, ops.data(), sizeof(int32_t) * ops.size(), hipMemcpyHostToDevice, s));
+    QCM_HIP(hipMemcpyAsync(pidx_d, pidx.data(), sizeof(int32_t) * pidx.size(),
+                           hipMemcpyHostToDevice, s));
+    if (n_z > 0)
+        QCM_HIP(hipMemcpyAsync(z_d, h_z, sizeof(double) * 2 * n_z, hipMemcpyHostToDevice, s));
+    const size_t part_base = cv.off;
+
+    for (int part = 0; part < 2; ++part) {
+        const int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
+        if (nup2 < 0 || nup2 > L) {
+            k_zero_coef<<<npairs, 256, 0, s>>>(npairs, part, coef, lenv, stride);
+            QCM_LAUNCH_CHECK();
+            continue;
+        }
+        cv.off = part_base;
+        SpinTables up2;
+        QCM_TRY(build_spin_tables(L, nup2, cv, &up2, s));
+        HvOp op;
+        op.md = md;
+        op.up = up2;
+        op.dn = dn;
+        op.hd = hd;
+        op.dim = up2.d * dn.d;
+        QCM_TRY(build_hop_tables(md, up2, cv, &op.hu, s, nb));
+        Engine e;
+        QCM_TRY(engine_init(e, op, o->prec, npairs, maxs, o->btol, o->reorth, cv));
+        QCM_TRY(engine_reset(e, s));
+        const dim3 g((unsigned)e.nchunks, (unsigned)npairs);
+        if (o->prec == QCM_FP64)
+            k_apply_ops<double><<<g, 256, 0, s>>>(d_gs, gs->d_up, upg.rank_lo, upg.rank_hi,
+                                                  upg.l_lo, upg.l_hi, up2.states, up2.d, op.dim,
+                                                  part, ops_d, (double *)e.vbuf[e.iv], e.nchunks,
+                                                  e.partial);
+        else
+            k_apply_ops<float><<<g, 256, 0, s>>>(d_gs, gs->d_up, upg.rank_lo, upg.rank_hi,
+                                                 upg.l_lo, upg.l_hi, up2.states, up2.d, op.dim,
+                                                 part, ops_d, (float *)e.vbuf[e.iv], e.nchunks,
+                                                 e.partial);
+        QCM_LAUNCH_CHECK();
+        QCM_TRY(engine_normalize_from_partials(e, s));
+        std::vector<int32_t> done(npairs);
+        for (int step = 0; step < maxs; ++step) {
+            QCM_TRY(engine_step(e, step, s));
+            if ((step + 1) % 32 == 0 && step + 1 < maxs) {
+                QCM_HIP(hipMemcpyAsync(done.data(), e.cs.done, sizeof(int32_t) * npairs,
+                                       hipMemcpyDeviceToHost, s));
+                QCM_HIP(hipStreamSynchronize(s));
+                bool all = true;
+                for (int c = 0; c < npairs; ++c) all = all && done[c];
+                if (all) break;
+            }
+        }
+        k_store_coef<<<npairs, 256, 0, s>>>(e.cs, npairs, part, coef, lenv, stride);
+        QCM_LAUNCH_CHECK();
+    }
+    if (n_z > 0) {
+        int64_t tot = (int64_t)n_z * npairs;
+        k_cf_pairs<<<ceil_div(tot, 256), 256, 0, s>>>(coef, lenv, npairs, maxs, n_z, z_d, e0, F);
+        int64_t tot2 = (int64_t)n_z * n * n;
+        k_cf_combine<<<ceil_div(tot2, 256), 256, 0, s>>>(F, pidx_d, n, npairs, n_z, d_G);
+        QCM_LAUNCH_CHECK();
+    }
+    if (h_coef)
+        QCM_HIP(hipMemcpyAsync(h_coef, coef, sizeof(double) * npairs * 2 * stride,
+                               hipMemcpyDeviceToHost, s));
+    if (h_len)
+        QCM_HIP(hipMemcpyAsync(h_len, lenv, sizeof(int32_t) * npairs * 2, hipMemcpyDeviceToHost, s));
+    QCM_HIP(hipStreamSynchronize(s));
+    return QCM_OK;
+}

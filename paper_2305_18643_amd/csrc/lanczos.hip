@@ -1,0 +1,706 @@
+// Lanczos recurrence on the device (paper: section "Exact diagonalizations",
+// subsection "The Lanczos algorithm for the ground state", eqs. (Krylov),
+// (LanczosRecursion), (tridiag)), in normalised form:
+//   w = H v_n - beta_{n-1} v_{n-1};  alpha_n = <v_n, w>;  w -= alpha_n v_n;
+//   beta_n = |w|;  v_{n+1} = w / beta_n          (beta_n^2 = paper's b_{n+1}^2)
+//
+// The engine runs nvec independent chains in one sector at once (vectors laid
+// out consecutively), which is how the Green-function chains are batched.
+// Every dot product is a deterministic two-level sum: fixed chunks of
+// kChunk elements summed in a fixed order by one workgroup each, then the
+// chunk sums summed in a fixed order.  Results therefore depend only on the
+// inputs, never on launch shapes or on other work sharing the GPU.
+#include <math.h>
+
+#include "lanczos_engine.h"
+
+namespace qcm {
+
+// ---------------------------------------------------------------- reductions
+
+template <typename T>
+__device__ __forceinline__ double ldd(const T *p) {
+    return (double)*p;
+}
+
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+    // 256 threads, fixed tree
+    const int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[c][chunk] = sum over the chunk of x*y (vector c)
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_dot_partial(const TX *__restrict__ x,
+                                                     const TY *__restrict__ y, int64_t n,
+                                                     int nchunks, double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int c = blockIdx.y;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const TX *xc = x + (int64_t)c * n;
+    const TY *yc = y + (int64_t)c * n;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n) acc = fma(ldd(xc + i), ldd(yc + i), acc);
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
+}
+
+// Sum of the chunk partials of each chain, then the recurrence bookkeeping.
+// mode 0: alpha[c][n] = s, amax update.
+// mode 1: beta[c][n] = sqrt(s), breakdown test, inv[c] = 1/beta or 0.
+// mode 2: out[c] = s (plain).
+// mode 3: alpha[c][n] += s, corr[c] = s (reorthogonalisation against v_n)
+// mode 4: corr2[c] = s (reorthogonalisation against v_{n-1})
+// mode 5: b0sq[c] = s, inv[c] = s > 0 ? 1/sqrt(s) : 0 (start-vector norm)
+__global__ void __launch_bounds__(256) k_finish(const double *__restrict__ partial, int nchunks,
+                                                int mode, ChainState cs, int n,
+                                                double *__restrict__ out) {
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nchunks; k += 256) acc += partial[(int64_t)c * nchunks + k];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+        case 0: {
+            cs.alpha[(int64_t)c * cs.maxs + n] = s;
+            double a = fabs(s);
+            if (a > cs.amax[c]) cs.amax[c] = a;
+            break;
+        }
+        case 1: {
+            double b = sqrt(s);
+            cs.beta[(int64_t)c * cs.maxs + n] = b;
+            if (!cs.done[c]) {
+                double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
+                if (!(b >= cs.btol * am)) {
+                    cs.done[c] = 1;
+                    cs.len[c] = n + 1;
+                } else {
+                    cs.len[c] = n + 1;
+                }
+            }
+            cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
+            break;
+        }
+        case 2:
+            out[c] = s;
+            break;
+        case 3:
+            cs.alpha[(int64_t)c * cs.maxs + n] += s;
+            cs.corr[c] = s;
+            break;
+        case 4:
+            cs.corr2[c] = s;
+            break;
+        case 5:
+            cs.b0sq[c] = s;
+            cs.inv[c] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+            if (!(s > 0.0)) {
+                cs.done[c] = 1;
+                cs.len[c] = 0;
+            }
+            break;
+    }
+}
+
+// ---------------------------------------------------------------- vector updates
+
+template <typename T>
+__device__ __forceinline__ void st(T *p, double x) {
+    *p = (T)x;
+}
+
+// w -= beta[c][n-1] * vp  (n > 0), and partial <v, w>
+template <typename T>
+__global__ void __launch_bounds__(256) k_sub_prev_dot(T *__restrict__ w, const T *__restrict__ vp,
+                                                      const T *__restrict__ v, int64_t n_el,
+                                                      int nchunks, ChainState cs, int n,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int c = blockIdx.y;
+    const double b = n > 0 ? cs.beta[(int64_t)c * cs.maxs + n - 1] : 0.0;
+    const int64_t off = (int64_t)c * n_el;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n_el) {
+            double x = ldd(w + off + i);
+            if (n > 0) {
+                x = fma(-b, ldd(vp + off + i), x);
+                st(w + off + i, x);
+                x = ldd(w + off + i);  // the stored value, in storage precision
+            }
+            acc = fma(ldd(v + off + i), x, acc);
+        }
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
+}
+
+// w -= alpha[c][n] * v, and partial <w, w>
+template <typename T>
+__global__ void __launch_bounds__(256) k_sub_cur_norm(T *__restrict__ w, const T *__restrict__ v,
+                                                      int64_t n_el, int nchunks, ChainState cs,
+                                                      int n, double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int c = blockIdx.y;
+    const double a = cs.alpha[(int64_t)c * cs.maxs + n];
+    const int64_t off = (int64_t)c * n_el;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n_el) {
+            double x = fma(-a, ldd(v + off + i), ldd(w + off + i));
+            st(w + off + i, x);
+            x = ldd(w + off + i);
+            acc = fma(x, x, acc);
+        }
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
+}
+
+// w -= corr[c] * v + corr2[c] * vp (local reorthogonalisation)
+template <typename T>
+__global__ void __launch_bounds__(256) k_reorth(T *__restrict__ w, const T *__restrict__ v,
+                                                const T *__restrict__ vp, int64_t n_el,
+                                                ChainState cs) {
+    const int c = blockIdx.y;
+    const double c1 = cs.corr[c], c2 = cs.corr2[c];
+    const int64_t off = (int64_t)c * n_el;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n_el) {
+            double x = ldd(w + off + i);
+            x = fma(-c1, ldd(v + off + i), x);
+            x = fma(-c2, ldd(vp + off + i), x);
+            st(w + off + i, x);
+        }
+    }
+}
+
+// x *= inv[c]
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale(T *__restrict__ x, int64_t n_el, ChainState cs) {
+    const int c = blockIdx.y;
+    const double s = cs.inv[c];
+    const int64_t off = (int64_t)c * n_el;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n_el) st(x + off + i, ldd(x + off + i) * s);
+    }
+}
+
+// psi += coef[n] * v  (psi FP64, one chain)
+template <typename T>
+__global__ void __launch_bounds__(256) k_accum(double *__restrict__ psi, const T *__restrict__ v,
+                                               int64_t n_el, const double *__restrict__ coef,
+                                               int n) {
+    const double s = coef[n];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n_el) psi[i] = fma(s, ldd(v + i), psi[i]);
+    }
+}
+
+// SplitMix64 start vector, entry i = 2 (u_i >> 11) 2^-53 - 1 with
+// u_i = mix(seed + (i+1) * golden gamma) (Steele, Lea & Flood 2014).
+template <typename T>
+__global__ void __launch_bounds__(256) k_splitmix(T *__restrict__ x, int64_t n, uint64_t seed) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    double u = (double)(z >> 11) * 0x1.0p-53;
+    x[i] = (T)(2.0 * u - 1.0);
+}
+
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) k_convert(TO *__restrict__ o, const TI *__restrict__ in,
+                                                 int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (TO)in[i];
+}
+
+// partial sum of (w - theta psi)^2, FP64
+__global__ void __launch_bounds__(256) k_resid_partial(const double *__restrict__ w,
+                                                       const double *__restrict__ psi, double th,
+                                                       int64_t n, int nchunks,
+                                                       double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        int64_t i = base + k;
+        if (i < n) {
+            double r = fma(-th, psi[i], w[i]);
+            acc = fma(r, r, acc);
+        }
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- tridiagonal
+
+// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots)
+__device__ int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b,
+                           double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < M; ++i) {
+        double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// k-th smallest eigenvalue by 256-way multisection: every thread tests one
+// point of the current bracket; 9 rounds narrow it by 257^9.
+__device__ double tridiag_kth(int M, const double *a, const double *b, int k, double *sh_lo,
+                              double *sh_hi) {
+    const int t = threadIdx.x;
+    __shared__ int cnts[256];
+    if (t == 0) {
+        double lo = a[0], hi = a[0];
+        for (int i = 0; i < M; ++i) {
+            double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < M - 1 ? fabs(b[i]) : 0.0);
+            lo = fmin(lo, a[i] - r);
+            hi = fmax(hi, a[i] + r);
+        }
+        double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
+        *sh_lo = lo - pad;
+        *sh_hi = hi + pad;
+    }
+    __syncthreads();
+    for (int round = 0; round < 10; ++round) {
+        double lo = *sh_lo, hi = *sh_hi;
+        double x = lo + (hi - lo) * (double)(t + 1) / 257.0;
+        cnts[t] = sturm_below(M, a, b, x);
+        __syncthreads();
+        if (t == 0) {
+            // first point with more than k eigenvalues below it
+            int j = 256;
+            for (int q = 0; q < 256; ++q)
+                if (cnts[q] > k) {
+                    j = q;
+                    break;
+                }
+            double nlo = j == 0 ? lo : lo + (hi - lo) * (double)j / 257.0;
+            double nhi = j == 256 ? hi : lo + (hi - lo) * (double)(j + 1) / 257.0;
+            *sh_lo = nlo;
+            *sh_hi = nhi;
+        }
+        __syncthreads();
+    }
+    double r = 0.5 * (*sh_lo + *sh_hi);
+    __syncthreads();
+    return r;
+}
+
+// Eigenvector for theta by inverse iteration; Gaussian elimination with
+// row pivoting on the tridiagonal (T - theta).  One thread.
+__device__ void tridiag_vector(int M, const double *a, const double *b, double theta, double *x,
+                               double *d, double *du, double *du2, double *dl, double *y) {
+    double scale = 1.0;
+    for (int i = 0; i < M; ++i) scale = fmax(scale, fabs(a[i]));
+    const double tiny = 1e-15 * scale;
+    for (int i = 0; i < M; ++i) x[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i < M; ++i) {
+            d[i] = a[i] - theta;
+            du[i] = i < M - 1 ? b[i] : 0.0;
+            dl[i] = i < M - 1 ? b[i] : 0.0;
+            du2[i] = 0.0;
+            y[i] = x[i];
+        }
+        for (int i = 0; i < M - 1; ++i) {
+            if (fabs(dl[i]) > fabs(d[i])) {
+                double t0 = d[i];
+                d[i] = dl[i];
+                dl[i] = t0;
+                double t1 = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t1;
+                if (i < M - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = 0.0;
+                }
+                double ty = y[i];
+                y[i] = y[i + 1];
+                y[i + 1] = ty;
+            }
+            if (d[i] == 0.0) d[i] = tiny;
+            double m = dl[i] / d[i];
+            d[i + 1] -= m * du[i];
+            if (i < M - 2) du[i + 1] -= m * du2[i];
+            y[i + 1] -= m * y[i];
+        }
+        if (d[M - 1] == 0.0) d[M - 1] = tiny;
+        for (int i = M - 1; i >= 0; --i) {
+            double s = y[i];
+            if (i + 1 < M) s -= du[i] * x[i + 1];
+            if (i + 2 < M) s -= du2[i] * x[i + 2];
+            x[i] = s / d[i];
+        }
+        double nr = 0.0;
+        for (int i = 0; i < M; ++i) nr += x[i] * x[i];
+        nr = 1.0 / sqrt(nr);
+        for (int i = 0; i < M; ++i) x[i] *= nr;
+    }
+    if (x[0] < 0.0)
+        for (int i = 0; i < M; ++i) x[i] = -x[i];
+}
+
+// Ground-state test on T_M: theta_0, theta_1, the eigenvector s of theta_0
+// (written to svec), and the residual estimate beta[M-1] |s[M-1]|.
+__global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict__ alpha,
+                                                        const double *__restrict__ beta, int M,
+                                                        double tol, double *__restrict__ work,
+                                                        double *__restrict__ svec,
+                                                        GsStatus *__restrict__ status) {
+    __shared__ double lo, hi;
+    double th0 = tridiag_kth(M, alpha, beta, 0, &lo, &hi);
+    double th1 = M > 1 ? tridiag_kth(M, alpha, beta, 1, &lo, &hi) : NAN;
+    if (threadIdx.x == 0) {
+        tridiag_vector(M, alpha, beta, th0, svec, work, work + M, work + 2 * M, work + 3 * M,
+                       work + 4 * M);
+        double est = beta[M - 1] * fabs(svec[M - 1]);
+        status->theta0 = th0;
+        status->theta1 = th1;
+        status->est = est;
+        status->converged = est <= tol * fmax(1.0, fabs(th0)) ? 1 : 0;
+        status->M = M;
+    }
+}
+
+// ---------------------------------------------------------------- engine
+
+size_t engine_bytes(int prec, int nvec, int64_t dim, int maxs) {
+    Carver cv(nullptr);
+    size_t s = prec == QCM_FP64 ? 8 : 4;
+    cv.take<char>(3 * s * (size_t)nvec * dim + 64);
+    int nch = (int)ceil_div(dim, kChunk);
+    cv.take<double>((size_t)nvec * (nch > 0 ? nch : 1));
+    cv.take<double>((size_t)nvec * maxs * 2);
+    cv.take<double>((size_t)nvec * 6);
+    cv.take<int32_t>((size_t)nvec * 2);
+    return cv.off + 256;
+}
+
+int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double btol, int reorth,
+                Carver &cv) {
+    e.op = op;
+    e.prec = prec;
+    e.nvec = nvec;
+    e.dim = op.dim;
+    e.maxs = maxs;
+    e.reorth = reorth;
+    size_t s = prec == QCM_FP64 ? 8 : 4;
+    char *vecs = cv.take<char>(3 * s * (size_t)nvec * e.dim + 64);
+    size_t vb = s * (size_t)nvec * e.dim;
+    e.vbuf[0] = vecs;
+    e.vbuf[1] = vecs + vb;
+    e.vbuf[2] = vecs + 2 * vb;
+    e.nchunks = (int)ceil_div(e.dim, kChunk);
+    if (e.nchunks < 1) e.nchunks = 1;
+    e.partial = cv.take<double>((size_t)nvec * e.nchunks);
+    e.cs.maxs = maxs;
+    e.cs.btol = btol;
+    e.cs.alpha = cv.take<double>((size_t)nvec * maxs);
+    e.cs.beta = cv.take<double>((size_t)nvec * maxs);
+    double *sc = cv.take<double>((size_t)nvec * 6);
+    e.cs.amax = sc;
+    e.cs.inv = sc + nvec;
+    e.cs.corr = sc + 2 * nvec;
+    e.cs.corr2 = sc + 3 * nvec;
+    e.cs.b0sq = sc + 4 * nvec;
+    e.scratch = sc + 5 * nvec;
+    int32_t *ic = cv.take<int32_t>((size_t)nvec * 2);
+    e.cs.len = ic;
+    e.cs.done = ic + nvec;
+    e.ivp = 0;
+    e.iv = 1;
+    e.iw = 2;
+    return QCM_OK;
+}
+
+int engine_reset(Engine &e, hipStream_t s) {
+    QCM_HIP(hipMemsetAsync(e.cs.alpha, 0, sizeof(double) * e.nvec * e.maxs, s));
+    QCM_HIP(hipMemsetAsync(e.cs.beta, 0, sizeof(double) * e.nvec * e.maxs, s));
+    QCM_HIP(hipMemsetAsync(e.cs.amax, 0, sizeof(double) * e.nvec * 6, s));
+    QCM_HIP(hipMemsetAsync(e.cs.len, 0, sizeof(int32_t) * e.nvec * 2, s));
+    size_t sz = (e.prec == QCM_FP64 ? 8 : 4) * (size_t)e.nvec * e.dim;
+    e.ivp = 0;
+    e.iv = 1;
+    e.iw = 2;
+    QCM_HIP(hipMemsetAsync(e.vbuf[e.ivp], 0, sz, s));
+    return QCM_OK;
+}
+
+template <typename T>
+static int step_t(Engine &e, int n, hipStream_t s) {
+    T *vp = (T *)e.vbuf[e.ivp], *v = (T *)e.vbuf[e.iv], *w = (T *)e.vbuf[e.iw];
+    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
+    QCM_TRY(hv_launch(e.op, e.prec, v, w, e.nvec, s));
+    k_sub_prev_dot<T><<<g, 256, 0, s>>>(w, vp, v, e.dim, e.nchunks, e.cs, n, e.partial);
+    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 0, e.cs, n, nullptr);
+    k_sub_cur_norm<T><<<g, 256, 0, s>>>(w, v, e.dim, e.nchunks, e.cs, n, e.partial);
+    if (e.reorth) {
+        // local reorthogonalisation against v_n and v_{n-1}, FP64 dot products
+        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 2, e.cs, n, e.scratch);
+        k_dot_partial<T, T><<<g, 256, 0, s>>>(v, w, e.dim, e.nchunks, e.partial);
+        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 3, e.cs, n, nullptr);
+        k_dot_partial<T, T><<<g, 256, 0, s>>>(vp, w, e.dim, e.nchunks, e.partial);
+        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 4, e.cs, n, nullptr);
+        k_reorth<T><<<g, 256, 0, s>>>(w, v, vp, e.dim, e.cs);
+        k_dot_partial<T, T><<<g, 256, 0, s>>>(w, w, e.dim, e.nchunks, e.partial);
+    }
+    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 1, e.cs, n, nullptr);
+    k_scale<T><<<g, 256, 0, s>>>(w, e.dim, e.cs);
+    QCM_LAUNCH_CHECK();
+    // rotate: v_{n-1} <- v_n, v_n <- w, w <- old v_{n-1}
+    int t = e.ivp;
+    e.ivp = e.iv;
+    e.iv = e.iw;
+    e.iw = t;
+    return QCM_OK;
+}
+
+int engine_step(Engine &e, int n, hipStream_t s) {
+    if (e.prec == QCM_FP64) return step_t<double>(e, n, s);
+    return step_t<float>(e, n, s);
+}
+
+// Normalise the current vectors v (chain start vectors), storing b0sq.
+template <typename T>
+static int normalize_t(Engine &e, hipStream_t s) {
+    T *v = (T *)e.vbuf[e.iv];
+    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
+    k_dot_partial<T, T><<<g, 256, 0, s>>>(v, v, e.dim, e.nchunks, e.partial);
+    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 5, e.cs, 0, nullptr);
+    k_scale<T><<<g, 256, 0, s>>>(v, e.dim, e.cs);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int engine_normalize(Engine &e, hipStream_t s) {
+    if (e.prec == QCM_FP64) return normalize_t<double>(e, s);
+    return normalize_t<float>(e, s);
+}
+
+int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s) {
+    void *v = e.vbuf[e.iv];
+    size_t sz = (e.prec == QCM_FP64 ? 8 : 4) * (size_t)e.dim;
+    if (v0) {
+        QCM_HIP(hipMemcpyAsync(v, v0, sz, hipMemcpyDeviceToDevice, s));
+    } else if (e.prec == QCM_FP64) {
+        k_splitmix<double><<<ceil_div(e.dim, 256), 256, 0, s>>>((double *)v, e.dim, seed);
+    } else {
+        k_splitmix<float><<<ceil_div(e.dim, 256), 256, 0, s>>>((float *)v, e.dim, seed);
+    }
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t s) {
+    const unsigned g = (unsigned)e.nchunks;
+    if (e.prec == QCM_FP64)
+        k_accum<double><<<g, 256, 0, s>>>(psi, (const double *)e.vbuf[e.iv], e.dim, coef, n);
+    else
+        k_accum<float><<<g, 256, 0, s>>>(psi, (const float *)e.vbuf[e.iv], e.dim, coef, n);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
+                   double *svec, GsStatus *status, hipStream_t s) {
+    k_tridiag_status<<<1, 256, 0, s>>>(alpha, beta, M, tol, work, svec, status);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int residual_norm(const HvOp &op, const double *psi, double theta, double *w64, double *partial,
+                  double *out, hipStream_t s) {
+    QCM_TRY(hv_launch(op, QCM_FP64, psi, w64, 1, s));
+    int nch = (int)ceil_div(op.dim, kChunk);
+    k_resid_partial<<<nch, 256, 0, s>>>(w64, psi, theta, op.dim, nch, partial);
+    ChainState dummy{};
+    k_finish<<<1, 256, 0, s>>>(partial, nch, 2, dummy, 0, out);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+}  // namespace qcm
+
+using namespace qcm;
+
+extern "C" void qcm_lanczos_default_opts(qcm_lanczos_opts *o) {
+    if (!o) return;
+    o->max_iter = 600;
+    o->fixed_steps = 0;
+    o->want_vector = 1;
+    o->reorth = 0;
+    o->prec = QCM_FP64;
+    o->check_every = 1;
+    o->tol = 1e-12;
+    o->btol = 1e-13;
+    o->seed = 1;
+    o->d_v0 = nullptr;
+}
+
+extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_lanczos_opts *o,
+                              double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out,
+                              void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!ws_needed || !o) return fail(QCM_EARG, "qcm_lanczos_gs: NULL ws_needed or opts");
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(b, m->L));
+    if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
+        return fail(QCM_EARG, "qcm_lanczos_gs: bad prec %d", o->prec);
+    if (o->max_iter < 1 && o->fixed_steps < 1)
+        return fail(QCM_EARG, "qcm_lanczos_gs: max_iter and fixed_steps both < 1");
+    if (o->want_vector && !d_gs && d_ws)
+        return fail(QCM_EARG, "qcm_lanczos_gs: want_vector needs d_gs");
+    if (b->dim < 1) return fail(QCM_EARG, "qcm_lanczos_gs: empty sector");
+    const int limit = o->fixed_steps > 0 ? o->fixed_steps : o->max_iter;
+    const int every = o->check_every > 0 ? o->check_every : 1;
+    size_t need = hv_setup_bytes(m, b) + engine_bytes(o->prec, 1, b->dim, limit) +
+                  sizeof(double) * (size_t)limit * 6 + 4096 + sizeof(double) * 64;
+    *ws_needed = need;
+    if (!d_ws) return QCM_OK;
+    if (!h_out) return fail(QCM_EARG, "qcm_lanczos_gs: h_out is NULL");
+    if (ws_bytes < need)
+        return fail(QCM_EWORKSPACE, "qcm_lanczos_gs: workspace %zu < %zu", ws_bytes, need);
+    hipStream_t s = as_stream(stream);
+    Carver cv(d_ws);
+    HvOp op;
+    QCM_TRY(hv_setup(m, b, cv, &op, s));
+    Engine e;
+    QCM_TRY(engine_init(e, op, o->prec, 1, limit, o->btol, o->reorth, cv));
+    double *svec = cv.take<double>(limit);
+    double *work = cv.take<double>((size_t)limit * 5);
+    GsStatus *status = cv.take<GsStatus>(1);
+    double *dscal = cv.take<double>(64);
+
+    // first pass: coefficients
+    QCM_TRY(engine_reset(e, s));
+    QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
+    QCM_TRY(engine_normalize(e, s));
+    GsStatus hs{};
+    int M = 0, conv = 0, brk = 0;
+    int32_t done = 0;
+    for (int n = 0; n < limit; ++n) {
+        QCM_TRY(engine_step(e, n, s));
+        M = n + 1;
+        bool last = (n + 1 == limit);
+        bool check = o->fixed_steps > 0 ? false : ((n + 1) % every == 0 || last);
+        // breakdown is checked together with the residual test; with fixed steps
+        // every `every` steps as well
+        if (o->fixed_steps > 0 && ((n + 1) % every == 0 || last)) check = true;
+        if (check) {
+            QCM_HIP(hipMemcpyAsync(&done, e.cs.done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            if (o->fixed_steps <= 0) {
+                QCM_TRY(tridiag_status(e.cs.alpha, e.cs.beta, M, o->tol, work, svec, status, s));
+                QCM_HIP(hipMemcpyAsync(&hs, status, sizeof hs, hipMemcpyDeviceToHost, s));
+            }
+            QCM_HIP(hipStreamSynchronize(s));
+            if (done) {
+                brk = 1;
+                conv = 1;
+                // the chain stopped at len; steps after it carry zero vectors
+                int32_t len = 0;
+                QCM_HIP(hipMemcpy(&len, e.cs.len, sizeof len, hipMemcpyDeviceToHost));
+                M = len;
+                break;
+            }
+            if (o->fixed_steps <= 0 && hs.converged) {
+                conv = 1;
+                break;
+            }
+        }
+    }
+    QCM_TRY(tridiag_status(e.cs.alpha, e.cs.beta, M, o->tol, work, svec, status, s));
+    QCM_HIP(hipMemcpyAsync(&hs, status, sizeof hs, hipMemcpyDeviceToHost, s));
+    QCM_HIP(hipStreamSynchronize(s));
+    if (o->fixed_steps <= 0 && !brk) conv = hs.converged;
+
+    qcm_gs_result r{};
+    r.e0 = hs.theta0;
+    r.residual_est = hs.est;
+    r.theta1 = hs.theta1;
+    r.n_iter = M;
+    r.converged = conv;
+    r.breakdown = brk;
+    r.true_residual = -1.0;
+
+    // the coefficients of the first pass go out before the second pass reruns
+    // (and rewrites, with identical values) the recurrence
+    if (h_alpha) QCM_HIP(hipMemcpy(h_alpha, e.cs.alpha, sizeof(double) * M, hipMemcpyDeviceToHost));
+    if (h_beta) QCM_HIP(hipMemcpy(h_beta, e.cs.beta, sizeof(double) * M, hipMemcpyDeviceToHost));
+
+    if (o->want_vector && d_gs) {
+        // second pass: identical recurrence, psi = sum_n s_n v_n
+        double *psi = (double *)d_gs;
+        QCM_HIP(hipMemsetAsync(psi, 0, sizeof(double) * b->dim, s));
+        QCM_TRY(engine_reset(e, s));
+        QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
+        QCM_TRY(engine_normalize(e, s));
+        for (int n = 0; n < M; ++n) {
+            QCM_TRY(engine_accum(e, psi, svec, n, s));
+            if (n + 1 < M) QCM_TRY(engine_step(e, n, s));
+        }
+        // normalise psi and take the true residual, all FP64
+        int nch = (int)ceil_div(b->dim, kChunk);
+        k_dot_partial<double, double><<<dim3(nch, 1), 256, 0, s>>>(psi, psi, b->dim, nch,
+                                                                   e.partial);
+        ChainState cs1 = e.cs;
+        k_finish<<<1, 256, 0, s>>>(e.partial, nch, 5, cs1, 0, nullptr);
+        k_scale<double><<<dim3(nch, 1), 256, 0, s>>>(psi, b->dim, cs1);
+        QCM_LAUNCH_CHECK();
+        double *w64 = (double *)e.vbuf[0];  // 8*dim bytes: the first two FP32 or one FP64 vector
+        QCM_TRY(residual_norm(op, psi, hs.theta0, w64, e.partial, dscal, s));
+        double r2 = 0.0;
+        QCM_HIP(hipMemcpyAsync(&r2, dscal, sizeof r2, hipMemcpyDeviceToHost, s));
+        QCM_HIP(hipStreamSynchronize(s));
+        r.true_residual = sqrt(r2);
+    }
+    *h_out = r;
+    return QCM_OK;
+}
+
+namespace qcm {
+
+// Normalise the start vectors from norm partials already in e.partial.
+int engine_normalize_from_partials(Engine &e, hipStream_t s) {
+    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
+    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 5, e.cs, 0, nullptr);
+    if (e.prec == QCM_FP64)
+        k_scale<double><<<g, 256, 0, s>>>((double *)e.vbuf[e.iv], e.dim, e.cs);
+    else
+        k_scale<float><<<g, 256, 0, s>>>((float *)e.vbuf[e.iv], e.dim, e.cs);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+}  // namespace qcm

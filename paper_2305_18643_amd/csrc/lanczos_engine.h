@@ -1,0 +1,52 @@
+// Multi-chain Lanczos engine shared by the ground-state and Green-function
+// entry points (internal).
+#pragma once
+
+#include "qcm_internal.h"
+
+namespace qcm {
+
+// Elements per reduction chunk: the fixed first level of every dot product.
+constexpr int kChunk = 8192;
+
+// Per-chain recurrence state, all on the device.  alpha/beta are [nvec][maxs].
+struct ChainState {
+    int maxs;
+    double btol;
+    double *alpha, *beta;
+    double *amax;   // running max |alpha| per chain
+    double *inv;    // 1/beta (or 0 once the chain has stopped), then 1/|phi|
+    double *corr, *corr2;
+    double *b0sq;   // <phi|phi> of the start vector
+    int32_t *len;   // number of steps recorded
+    int32_t *done;  // chain stopped (breakdown or empty start)
+};
+
+struct GsStatus {
+    double theta0, theta1, est;
+    int32_t converged, M;
+};
+
+struct Engine {
+    HvOp op;
+    int prec, nvec, maxs, reorth, nchunks;
+    int64_t dim;
+    void *vbuf[3];
+    int ivp, iv, iw;
+    double *partial;
+    double *scratch;
+    ChainState cs;
+};
+
+size_t engine_bytes(int prec, int nvec, int64_t dim, int maxs);
+int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double btol, int reorth,
+                Carver &cv);
+int engine_reset(Engine &e, hipStream_t s);
+int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s);
+int engine_normalize(Engine &e, hipStream_t s);
+int engine_step(Engine &e, int n, hipStream_t s);
+int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t s);
+int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
+                   double *svec, GsStatus *status, hipStream_t s);
+
+}  // namespace qcm

@@ -1,0 +1,141 @@
+// Internal declarations of the MI355X ED library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qcm.h"
+
+namespace qcm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+#define QCM_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::qcm::fail(QCM_EHIP, "%s failed: %s (%s:%d)", #call,                \
+                               hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+#define QCM_LAUNCH_CHECK()                                                               \
+    do {                                                                                 \
+        hipError_t e_ = hipGetLastError();                                               \
+        if (e_ != hipSuccess)                                                            \
+            return ::qcm::fail(QCM_EHIP, "kernel launch failed: %s (%s:%d)",            \
+                               hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+#define QCM_TRY(expr)                                                                    \
+    do {                                                                                 \
+        int r_ = (expr);                                                                 \
+        if (r_ != QCM_OK) return r_;                                                     \
+    } while (0)
+
+// ---------------------------------------------------------------- binomials
+// C(n, k) by the multiplicative formula; exact in int64 for n <= 32.  Only used
+// while building tables, never in the H.v loops.
+__device__ __host__ inline int64_t binom(int n, int k) {
+    if (n < 0 || k < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// ---------------------------------------------------------------- workspace
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <typename T>
+    T *take(size_t n, size_t align = 256) {
+        off = (off + align - 1) / align * align;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+inline size_t ceil_div(size_t a, size_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- sector
+struct SpinTables {
+    int32_t L, N, l_lo, l_hi;
+    int64_t d;
+    uint32_t *states;
+    int32_t *rank_lo;  // [2^l_lo]
+    int32_t *rank_hi;  // [(l_lo+1) * 2^l_hi]
+};
+
+__device__ __forceinline__ int32_t spin_rank(const int32_t *__restrict__ rlo,
+                                             const int32_t *__restrict__ rhi, int l_lo, int l_hi,
+                                             uint32_t b) {
+    const uint32_t lo_mask = (l_lo >= 32) ? 0xffffffffu : ((1u << l_lo) - 1u);
+    uint32_t lo = b & lo_mask;
+    uint32_t hi = (l_lo >= 32) ? 0u : (b >> l_lo);
+    return rlo[lo] + rhi[(size_t)__popc(lo) << l_hi | hi];
+}
+
+size_t spin_tables_bytes(int L, int N);
+int build_spin_tables(int L, int N, Carver &cv, SpinTables *out, hipStream_t s);
+int check_sector_args(int L, int nup, int ndn);
+void basis_from_tables(const SpinTables &up, const SpinTables &dn, qcm_basis *out);
+SpinTables spin_from_basis(const qcm_basis *b, int spin);
+
+// ---------------------------------------------------------------- Hamiltonian tables
+// Model data on the device and the per-spin hopping lists (ELL layout: slot-major,
+// entry s of state i at [s * d + i]).
+struct ModelDev {
+    int32_t L;
+    int32_t nbond;        // undirected bonds with t_ab != 0, a < b
+    double *t;            // [L*L]
+    int32_t *bond_a;      // [nbond]
+    int32_t *bond_b;      // [nbond]
+    double *bond_t;       // [nbond]
+    double *ulut;         // [nbytes][256]: sum of U_k over set bits of one byte
+    double *tlut;         // [nbytes][256]: sum of t_kk over set bits of one byte
+    int32_t nbytes;       // ceil(L/8)
+    double u_uniform;     // >= 0 if all U_k equal (then U * popcount), else -1
+};
+
+struct HopTables {
+    int64_t d;
+    int32_t width;        // ELL width (max hops per state)
+    int32_t *nh;          // [d] number of hops of each state
+    int32_t *col;         // [width * d]
+    double *coef;         // [width * d]  sign * t_ab
+    double *ediag;        // [d]  sum_k t_kk n_k
+};
+
+size_t model_dev_bytes(int L);
+int upload_model(const qcm_model *m, Carver &cv, ModelDev *md, hipStream_t s);
+int validate_model(const qcm_model *m);
+size_t hop_tables_bytes(const qcm_model *m, int64_t d);
+int build_hop_tables(const ModelDev &md, const SpinTables &st, Carver &cv, HopTables *ht,
+                     hipStream_t s, int nbond_host);
+
+// ---------------------------------------------------------------- H.v
+struct HvOp {
+    ModelDev md;
+    SpinTables up, dn;
+    HopTables hu, hd;
+    int64_t dim;
+};
+// nvec vectors of length dim, consecutive (stride dim).  prec: QCM_FP64/QCM_FP32V.
+int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s);
+size_t hv_scratch_bytes(const HvOp &op, int prec, int nvec);
+size_t hv_setup_bytes(const qcm_model *m, const qcm_basis *b);
+int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipStream_t s);
+int check_basis(const qcm_basis *b, int L);
+
+// ---------------------------------------------------------------- misc
+int count_bonds(const qcm_model *m);
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace qcm

@@ -1,0 +1,125 @@
+"""The C ABI library loads on the CPU, exports every symbol the header
+declares, and rejects bad arguments before touching a GPU (size queries and
+validation errors need no device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2305_18643_amd import _binding as b
+    if not os.path.exists(b.LIB_PATH):
+        from paper_2305_18643_amd import build
+        build.build()
+    return b.load_library()
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "qcm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qcm_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2305_18643_amd import _binding as b
+    syms = header_symbols()
+    assert set(syms) == set(b.EXPORTS), syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_version(lib):
+    assert lib.qcm_version() >= 100
+
+
+def test_basis_size_query_and_range_errors(lib):
+    from paper_2305_18643_amd import _binding as b
+    need = ctypes.c_size_t(0)
+    out = b.Basis()
+    assert lib.qcm_sector_basis(16, 8, 8, None, 0, ctypes.byref(need), ctypes.byref(out), None) == 0
+    assert need.value > 4 * 12870 * 2
+    assert out.d_up == 12870 and out.d_dn == 12870 and out.dim == 165636900
+    assert lib.qcm_sector_basis(33, 1, 1, None, 0, ctypes.byref(need), ctypes.byref(out), None) == b.QCM_ERANGE
+    assert b"outside" in lib.qcm_last_error()
+    assert lib.qcm_sector_basis(4, 5, 1, None, 0, ctypes.byref(need), ctypes.byref(out), None) == b.QCM_ERANGE
+    assert lib.qcm_sector_basis(32, 16, 16, None, 0, ctypes.byref(need), ctypes.byref(out), None) == b.QCM_OK
+    # workspace too small is reported before any launch
+    assert lib.qcm_sector_basis(4, 2, 2, ctypes.c_void_p(1), 8, ctypes.byref(need),
+                                ctypes.byref(out), None) == b.QCM_EWORKSPACE
+
+
+def test_model_validation(lib):
+    from paper_2305_18643_amd import _binding as b
+    need = ctypes.c_size_t(0)
+    bas = b.Basis()
+    assert lib.qcm_sector_basis(4, 2, 2, None, 0, ctypes.byref(need), ctypes.byref(bas), None) == 0
+    t = np.zeros((4, 4))
+    t[0, 1] = 1.0  # not symmetric
+    m = b.HostModel(t, np.zeros(4))
+    rc = lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(bas), 0, None, None, None, 0,
+                    ctypes.byref(need), None)
+    assert rc == b.QCM_EARG and b"symmetric" in lib.qcm_last_error()
+    t[1, 0] = 1.0
+    m = b.HostModel(t, np.zeros(4))
+    # a size-only basis has NULL tables: accepted for the query only
+    rc = lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(bas), 0, None, None, None, 0,
+                    ctypes.byref(need), None)
+    assert rc == b.QCM_EARG  # basis has NULL device tables
+    bad = b.HostModel(np.zeros((5, 5)), np.zeros(5))
+    rc = lib.qcm_hv(ctypes.byref(bad.c), ctypes.byref(bas), 0, None, None, None, 0,
+                    ctypes.byref(need), None)
+    assert rc == b.QCM_EARG and b"differs" in lib.qcm_last_error()
+
+
+def test_lanczos_and_green_option_validation(lib):
+    from paper_2305_18643_amd import _binding as b
+    need = ctypes.c_size_t(0)
+    o = b.LanczosOpts()
+    lib.qcm_lanczos_default_opts(ctypes.byref(o))
+    assert o.max_iter == 600 and o.want_vector == 1 and abs(o.tol - 1e-12) < 1e-30
+    o.prec = 7
+    m = b.HostModel(np.eye(4), np.zeros(4))
+    bas = b.Basis()
+    assert lib.qcm_lanczos_gs(ctypes.byref(m.c), ctypes.byref(bas), ctypes.byref(o), None, None,
+                              None, None, None, 0, ctypes.byref(need), None) == b.QCM_EARG
+    orbs = np.array([0, 0], dtype=np.int32)
+    go = b.GreenOpts(2, orbs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 10, 0, 0, 0, 1e-13)
+    # basis check comes first (sizes of an empty struct are inconsistent)
+    rc = lib.qcm_green_cf(ctypes.byref(m.c), ctypes.byref(bas), None, 0.0, ctypes.byref(go),
+                          None, None, 0, None, None, None, 0, ctypes.byref(need), None)
+    assert rc == b.QCM_EARG
+
+
+def test_cpt_validation(lib):
+    from paper_2305_18643_amd import _binding as b
+    need = ctypes.c_size_t(0)
+    R = np.zeros((4, 3), dtype=np.int32)
+    E = np.eye(3, dtype=np.int32)
+    bonds = (b.Bond * 1)()
+    bonds[0].i, bonds[0].j, bonds[0].t = 0, 9, 1.0
+    k = np.zeros(3)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.qcm_cpt_gk(4, 2, None, R.ctypes.data_as(i32), E.ctypes.data_as(i32), 1, bonds, 1,
+                        k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, 0,
+                        ctypes.byref(need), None)
+    assert rc == b.QCM_EARG and b"out of range" in lib.qcm_last_error()
+    rc = lib.qcm_cpt_gk(40, 2, None, R.ctypes.data_as(i32), E.ctypes.data_as(i32), 0, bonds, 1,
+                        k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, 0,
+                        ctypes.byref(need), None)
+    assert rc == b.QCM_ERANGE
+
+
+def test_product_path_does_not_reference_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2305_18643_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library through the C ABI against the CPU oracle.
+
+Tolerances:
+  * basis, labels: bit-exact;
+  * H.v FP64: |dw_i| <= 64 eps (|H| |v|)_i, the rounding bound of a sum of
+    at most ~64 products (eps = 2^-53);
+  * H.v FP32-vector: one FP32 rounding of the FP64 sum, |dw_i| <= 2^-24 |w_i|
+    plus the FP64 bound;
+  * E0 (FP64): relative 1e-10; G(omega) at eta = 0.1: absolute 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cf
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_18643_amd as q
+    q.load_library()
+    return q
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ---------------------------------------------------------------- basis
+
+BASIS_CASES = [(1, 0, 1), (1, 1, 1), (4, 2, 2), (4, 0, 4), (5, 2, 3), (12, 6, 6), (12, 7, 6),
+               (14, 7, 7), (16, 8, 8), (16, 9, 8), (13, 1, 12), (20, 10, 9), (24, 12, 3),
+               (32, 1, 2), (32, 3, 31), (31, 2, 30)]
+
+
+@pytest.mark.parametrize("L,nup,ndn", BASIS_CASES)
+def test_basis_bit_exact(q, L, nup, ndn):
+    print(f"basis L={L} ({nup},{ndn})", flush=True)
+    b = q.sector_basis(L, nup, ndn)
+    for spin, N in ((0, nup), (1, ndn)):
+        st = b.states(spin).cpu().numpy()
+        ref = oracle.sector_states(L, N).astype(np.int64)
+        assert np.array_equal(st, ref)
+        lo, hi = (x.cpu().numpy().astype(np.int64) for x in b.rank_tables(spin))
+        l_lo = (L + 1) // 2
+        l_hi = L - l_lo
+        m = (1 << l_lo) - 1
+        lab = lo[st & m] + hi[(np.array([bin(x).count("1") for x in (st & m)]) << l_hi) | (st >> l_lo)]
+        assert np.array_equal(lab, np.arange(st.shape[0]))
+    assert b.dim == oracle.binom(L, nup) * oracle.binom(L, ndn)
+
+
+def test_rank_tables_on_random_strings(q):
+    L = 16
+    b = q.sector_basis(L, 8, 8)
+    lo, hi = (x.cpu().numpy().astype(np.int64) for x in b.rank_tables(0))
+    rng = np.random.default_rng(5)
+    for x in rng.integers(0, 1 << L, 500):
+        x = int(x)
+        xl, xh = x & 255, x >> 8
+        assert lo[xl] + hi[(bin(xl).count("1") << 8) | xh] == oracle.rank(x)
+
+
+# ---------------------------------------------------------------- H.v
+
+def _hv_models():
+    out = [synth.plaquette_2x2(), synth.two_site(), synth.rect_cluster(2, 4, U=4.0, mu=1.0),
+           synth.chain(10, U=4.0, mu=2.0, nup=5, ndn=4),
+           synth.random_model(101, 9, 4, 5), synth.random_model(102, 11, 3, 6),
+           synth.random_model(103, 10, 5, 5, uniform_U=True),
+           synth.cluster_3x4(), synth.rect_cluster(3, 3, U=6.0, mu=3.0, nup=5, ndn=4)]
+    rng = np.random.default_rng(18643)
+    out += [synth.impurity_model(rng, nb) for nb in (2, 5, 9)]
+    out.append(synth.rect_cluster(4, 1, U=3.0, mu=0.0, nup=0, ndn=2))
+    out.append(synth.rect_cluster(4, 1, U=3.0, mu=0.0, nup=4, ndn=1))
+    return out
+
+
+@pytest.mark.parametrize("m", _hv_models(), ids=lambda m: f"{m.name}_{m.nup}_{m.ndn}")
+@pytest.mark.parametrize("prec", ["fp64", "fp32v"])
+def test_hv_elementwise(q, m, prec):
+    torch = _torch()
+    print(f"hv {m.name} ({m.nup},{m.ndn}) {prec}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    rng = np.random.default_rng(7)
+    v = rng.uniform(-1, 1, b.dim)
+    if prec == "fp32v":
+        v = v.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    vd = torch.tensor(v, dtype=dt, device="cuda")
+    w = q.hv(m, b, vd).double().cpu().numpy()
+    wo = oracle.hv(m.t, m.U, m.nup, m.ndn, v)
+    bound = oracle.hv_abs_bound(m.t, m.U, m.nup, m.ndn, v)
+    tol = 64 * EPS * bound + 1e-300
+    if prec == "fp32v":
+        tol = tol + 2.0 ** -24 * np.abs(wo)
+    err = np.abs(w - wo)
+    assert np.all(err <= tol), (err.max(), np.argmax(err - tol))
+
+
+def test_hv_4x4_sampled_rows(q):
+    """Full 16-site sector (d = 165,636,900), the configuration bench.py times:
+    the SplitMix64 vector of seed 1, oracle rows computed one by one."""
+    torch = _torch()
+    m = synth.cluster_4x4(8.0)
+    print("hv 4x4 full sector", flush=True)
+    b = q.sector_basis(16, 8, 8)
+    v = oracle.start_vector(1, b.dim)
+    vd = torch.from_numpy(v).to("cuda")
+    w = q.hv(m, b, vd)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, b.dim, 20000), np.arange(64),
+                                     np.arange(b.dim - 64, b.dim),
+                                     12870 * np.arange(0, 12870, 997) + 12869]))
+    wr = w[torch.from_numpy(rows).to("cuda")].cpu().numpy()
+    wo = oracle.hv_rows(m.t, m.U, 8, 8, v, rows)
+    bound = oracle.hv_abs_bound(m.t, m.U, 8, 8, v, rows)
+    assert np.all(np.abs(wr - wo) <= 64 * EPS * bound)
+    # FP32-vector storage on the same rows
+    v32 = vd.float()
+    w32 = q.hv(m, b, v32)
+    wr32 = w32[torch.from_numpy(rows).to("cuda")].double().cpu().numpy()
+    wo32 = oracle.hv_rows(m.t, m.U, 8, 8, v32.cpu().numpy(), rows)
+    assert np.all(np.abs(wr32 - wo32) <= 2.0 ** -24 * np.abs(wo32) + 64 * EPS * bound)
+    del w, w32, vd, v32
+
+
+# ---------------------------------------------------------------- ground state
+
+GS_MODELS = [synth.plaquette_2x2(), synth.two_site(U=8.0), synth.rect_cluster(2, 4, U=4.0, mu=2.0),
+             synth.chain(10, U=4.0, mu=2.0), synth.random_model(201, 8, 4, 3),
+             synth.rect_cluster(3, 3, U=6.0, mu=3.0, nup=5, ndn=4)]
+
+
+@pytest.mark.parametrize("m", GS_MODELS, ids=lambda m: f"{m.name}_{m.nup}_{m.ndn}")
+def test_ground_state_fp64(q, m):
+    print(f"gs {m.name}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    r = q.lanczos_gs(m, b)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    assert r["converged"]
+    assert abs(r["e0"] - ro["e0"]) <= 1e-10 * abs(ro["e0"])
+    psi = r["psi"].cpu().numpy()
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-12
+    assert abs(abs(np.dot(psi, ro["psi"])) - 1.0) < 1e-9
+    assert r["true_residual"] < 1e-6
+    # the first Lanczos coefficients agree before orthogonality is lost
+    k = min(10, r["n_iter"], ro["n_iter"])
+    assert np.allclose(r["alpha"][:k], ro["alpha"][:k], rtol=1e-10, atol=1e-10)
+    assert np.allclose(r["beta"][:k], ro["beta"][:k], rtol=1e-9, atol=1e-10)
+
+
+def test_ground_state_fp32v_reports_error(q):
+    m = synth.chain(10, U=4.0, mu=2.0)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn)
+    r = q.lanczos_gs(m, b, prec="fp32v", reorth=1, tol=1e-7)
+    rel = abs(r["e0"] - ro["e0"]) / abs(ro["e0"])
+    print(f"FP32-vector E0 relative error {rel:.2e}")
+    assert rel < 1e-5
+
+
+def test_fixed_steps_and_breakdown(q):
+    # t = 0: H is diagonal; the Krylov space is exhausted after a few steps
+    L = 4
+    t = np.diag(np.full(L, -3.0))
+    U = np.full(L, 6.0)
+    b = q.sector_basis(L, 2, 2)
+    r = q.lanczos_gs((t, U), b, fixed_steps=50)
+    assert r["breakdown"] and r["n_iter"] < 10
+    assert abs(r["e0"] + 12.0) < 1e-12
+
+
+# ---------------------------------------------------------------- Green function and CPT
+
+Z64 = synth.omega_grid()
+
+
+# Chains are run past convergence: a truncated, unconverged chain without
+# reorthogonalisation is chaotic in the rounding (a 1e-13 change of the ground
+# state moves a 200-step G of the 7-orbital impurity by 4e-3), while converged
+# chains of both sides reach the same Lehmann sum.
+@pytest.mark.parametrize("m,steps", [(synth.plaquette_2x2(), 200), (synth.random_model(301, 6, 3, 2), 400),
+                                     (synth.impurity_model(np.random.default_rng(18643), 3), 600)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_green_function(q, m, steps):
+    print(f"green {m.name}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    r = q.lanczos_gs(m, b)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    orbs = list(range(min(m.L, 4)))
+    g = q.green_cf(m, b, r["psi"], r["e0"], orbs, Z64, max_steps=steps)
+    ch = oracle.green_cf(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, max_steps=steps)
+    Go = cf.green_matrix(ch, len(orbs), Z64, ro["e0"])
+    G = g["G"].cpu().numpy()
+    err = np.abs(G - Go).max()
+    print(f"  max |dG| = {err:.2e}")
+    assert err <= 1e-4
+    # b0^2 of every chain matches the oracle's
+    p = 0
+    for i in range(len(orbs)):
+        for j in range(i, len(orbs)):
+            for part in (0, 1):
+                assert abs(g["coef"][p, part, 0] - ch[(i, j, part)][0]) < 1e-12
+            p += 1
+
+
+def test_cpt_2x2(q):
+    torch = _torch()
+    m = synth.plaquette_2x2()
+    ro = oracle.lanczos_gs(m.t, m.U, 2, 2, want_vector=True)
+    ch = oracle.green_cf(m.t, m.U, 2, 2, ro["psi"], [0, 1, 2, 3])
+    Go = cf.green_matrix(ch, 4, Z64, ro["e0"])
+    R, E, bonds = synth.cpt_square_lattice_2x2()
+    ks = synth.k_grid_2d(16)
+    gp = q.cpt_gk(torch.from_numpy(Go).to("cuda"), R, E, bonds, ks).cpu().numpy()
+    gpo = cf.cpt_periodized(Go, R, E, bonds, ks)
+    assert np.abs(gp - gpo).max() <= 1e-10
