@@ -175,6 +175,7 @@ static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_gre
         int64_t du2 = binom(L, nup2);
         size_t b = spin_tables_bytes(L, nup2) + hop_tables_bytes(m, du2) +
                    engine_bytes(o->prec, npairs, du2 * gs->d_dn, o->max_steps);
+        if (split_applies(m, nup2, du2, gs->d_dn)) b += split_bytes(m, nup2, du2, gs->d_dn);
         if (b > part_max) part_max = b;
     }
     need += part_max;
@@ -273,6 +274,8 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         op.hd = hd;
         op.dim = up2.d * dn.d;
         QCM_TRY(build_hop_tables(md, up2, cv, &op.hu, s, nb));
+        op.split = 0;
+        if (split_applies(m, nup2, up2.d, dn.d)) QCM_TRY(split_prepare(m, op, cv, s));
         Engine e;
         QCM_TRY(engine_init(e, op, o->prec, npairs, maxs, o->btol, o->reorth, cv));
         QCM_TRY(engine_reset(e, s));

@@ -114,7 +114,7 @@ size_t hop_tables_bytes(const qcm_model *m, int64_t d) {
 // direction is allowed: the occupied end moves to the empty end.  The entry
 // for row string x is the column label of the string with the electron moved
 // and the element t_ab times (-1)^(occupied orbitals strictly between a, b).
-__global__ void k_build_hops(int64_t d, int L, int l_lo, int l_hi,
+__global__ void k_build_hops(int64_t d, int rowmajor, int W, int L, int l_lo, int l_hi,
                              const uint32_t *__restrict__ states,
                              const int32_t *__restrict__ rlo, const int32_t *__restrict__ rhi,
                              int nbond, const int32_t *__restrict__ ba,
@@ -134,8 +134,9 @@ __global__ void k_build_hops(int64_t d, int L, int l_lo, int l_hi,
         uint32_t y = x ^ ma ^ mb;
         uint32_t between = ((mb - 1u) & ~(ma | (ma - 1u)));  // a < b: bits a+1..b-1
         int m = __popc(x & between);
-        col[(int64_t)n * d + i] = spin_rank(rlo, rhi, l_lo, l_hi, y);
-        coef[(int64_t)n * d + i] = (m & 1) ? -bt[k] : bt[k];
+        const int64_t at = rowmajor ? i * W + n : (int64_t)n * d + i;
+        col[at] = spin_rank(rlo, rhi, l_lo, l_hi, y);
+        coef[at] = (m & 1) ? -bt[k] : bt[k];
         ++n;
     }
     nh[i] = n;
@@ -145,17 +146,18 @@ __global__ void k_build_hops(int64_t d, int L, int l_lo, int l_hi,
 }
 
 int build_hop_tables(const ModelDev &md, const SpinTables &st, Carver &cv, HopTables *ht,
-                     hipStream_t s, int nbond_host) {
+                     hipStream_t s, int nbond_host, int rowmajor) {
     int W = nbond_host < 1 ? 1 : nbond_host;
     ht->d = st.d;
     ht->width = W;
+    ht->rowmajor = rowmajor;
     ht->nh = cv.take<int32_t>(st.d);
     ht->col = cv.take<int32_t>((size_t)W * st.d);
     ht->coef = cv.take<double>((size_t)W * st.d);
     ht->ediag = cv.take<double>(st.d);
     if (!cv.base) return QCM_OK;
     const int B = 256;
-    k_build_hops<<<ceil_div(st.d, B), B, 0, s>>>(st.d, st.L, st.l_lo, st.l_hi, st.states,
+    k_build_hops<<<ceil_div(st.d, B), B, 0, s>>>(st.d, ht->rowmajor, W, st.L, st.l_lo, st.l_hi, st.states,
                                                   st.rank_lo, st.rank_hi, nbond_host, md.bond_a,
                                                   md.bond_b, md.bond_t, md.tlut, md.nbytes,
                                                   ht->nh, ht->col, ht->coef, ht->ediag);
@@ -282,15 +284,20 @@ static int hv_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipStre
     return QCM_OK;
 }
 
+int hv_split_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s);
+
 int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s) {
     if (op.dim == 0 || nvec == 0) return QCM_OK;
+    if (op.split) return hv_split_launch(op, prec, v, w, nvec, s);
     if (prec == QCM_FP64) return hv_launch_t<double>(op, v, w, nvec, s);
     return hv_launch_t<float>(op, v, w, nvec, s);
 }
 
 // Sizes and set-up shared by every entry point that applies H.
 size_t hv_setup_bytes(const qcm_model *m, const qcm_basis *b) {
-    return model_dev_bytes(m->L) + hop_tables_bytes(m, b->d_up) + hop_tables_bytes(m, b->d_dn);
+    size_t n = model_dev_bytes(m->L) + hop_tables_bytes(m, b->d_up) + hop_tables_bytes(m, b->d_dn);
+    if (split_applies(m, b->n_up, b->d_up, b->d_dn)) n += split_bytes(m, b->n_up, b->d_up, b->d_dn);
+    return n;
 }
 
 int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipStream_t s) {
@@ -301,6 +308,8 @@ int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipSt
     int nb = count_bonds(m);
     QCM_TRY(build_hop_tables(op->md, op->up, cv, &op->hu, s, nb));
     QCM_TRY(build_hop_tables(op->md, op->dn, cv, &op->hd, s, nb));
+    op->split = 0;
+    if (split_applies(m, b->n_up, b->d_up, b->d_dn)) QCM_TRY(split_prepare(m, *op, cv, s));
     return QCM_OK;
 }
 
