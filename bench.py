@@ -35,6 +35,9 @@ def parse():
     p.add_argument("--U", type=float, default=8.0)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="skip FP32-vector and Lanczos figures")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only copy one FP64 sector vector (d doubles) 10 times, for scaling "
+                        "the FETCH_SIZE / WRITE_SIZE counters; prints its own line")
     p.add_argument("--cpu-rows", type=int, default=0,
                    help="rows of the sector the oracle computes for the CPU baseline "
                         "(0: every row, one full product)")
@@ -86,6 +89,14 @@ def main():
     g.manual_seed(1)
     v = torch.rand(d, dtype=torch.float64, device=dev, generator=g) * 2 - 1
     w = torch.empty_like(v)
+    if args.copy_calibration:
+        torch.cuda.synchronize()
+        for _ in range(10):
+            w.copy_(v)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 8 * d,
+                                               "bytes_written_per_copy": 8 * d, "copies": 10}}))
+        return
     ws = None
     # workspace once, reused by every call
     import ctypes

@@ -33,8 +33,8 @@ static int64_t hbinom(int n, int k) { return binom(n, k); }
 struct HostSplit {
     int l_lo, l_hi, nb;
     std::vector<double> coef, e_lo, e_hi;
-    std::vector<uint64_t> hi_ent, x_ent;
-    std::vector<int32_t> rlo, lo_off, hi_off, x_off;
+    std::vector<uint64_t> hi_ent;
+    std::vector<int32_t> rlo, lo_off, hi_off;
     std::vector<uint32_t> lo_ent;
     // team layout
     std::vector<int32_t> cls, llist, hlist, hbase, xbond;
@@ -108,7 +108,6 @@ static bool make_host_split(const qcm_model *m, int N, HostSplit &H) {
     }
     // hi and cross hops, per high half h (group of columns with that high half)
     H.hi_off.assign(nhi + 1, 0);
-    H.x_off.assign(nhi + 1, 0);
     for (int y = 0; y < nhi; ++y) {
         int n_l = N - __builtin_popcount(y);
         if (n_l >= 0 && n_l <= l_lo) {
@@ -125,26 +124,8 @@ static bool make_host_split(const qcm_model *m, int N, HostSplit &H) {
                 uint64_t ci = 2 * k + (between & 1);
                 H.hi_ent.push_back((uint64_t)(uint32_t)(int32_t)d | (ci << 32));
             }
-            for (int k = 0; k < nb; ++k) {
-                int a = ba[k], b = bb[k];
-                if (!(a < l_lo && b >= l_lo)) continue;
-                int qb = b - l_lo;
-                bool hb = (y >> qb) & 1;
-                // dir 0: electron from lo orbital a to hi orbital b (h lacks b, l has a)
-                // dir 1: electron from hi orbital b to lo orbital a (h has b, l lacks a)
-                int dir = hb ? 1 : 0;
-                int n2 = dir == 0 ? n_l - 1 : n_l + 1;
-                if (n2 < 0 || n2 > l_lo) continue;
-                int y2 = y ^ (1 << qb);
-                int64_t base2 = rhi(n2, y2);
-                int par = __builtin_popcount(y & ((1u << qb) - 1u)) & 1;
-                uint64_t meta = (uint64_t)a | ((uint64_t)dir << 5) | ((uint64_t)par << 6) |
-                                ((uint64_t)k << 7);
-                H.x_ent.push_back((uint64_t)(uint32_t)(int32_t)base2 | (meta << 32));
-            }
         }
         H.hi_off[y + 1] = (int32_t)H.hi_ent.size();
-        H.x_off[y + 1] = (int32_t)H.x_ent.size();
         H.max_hi = std::max(H.max_hi, H.hi_off[y + 1] - H.hi_off[y]);
     }
     for (int x = 0; x < nlo; ++x) H.max_lo = std::max(H.max_lo, H.lo_off[x + 1] - H.lo_off[x]);
@@ -208,11 +189,9 @@ static SplitLayout layout_of(const HostSplit &H) {
     o.off_elo = put(H.e_lo.size(), 8);
     o.off_ehi = put(H.e_hi.size(), 8);
     o.off_hient = put(H.hi_ent.size(), 8);
-    o.off_xent = put(H.x_ent.size(), 8);
     o.off_rlo = put(H.rlo.size(), 4);
     o.off_looff = put(H.lo_off.size(), 4);
     o.off_hioff = put(H.hi_off.size(), 4);
-    o.off_xoff = put(H.x_off.size(), 4);
     o.off_loent = put(H.lo_ent.size(), 4);
     o.off_xtab = put(H.xtab.size(), 8);
     o.off_cls = put(H.cls.size(), 4);
@@ -254,150 +233,6 @@ template <>
 struct Vec2<float> {
     using type = float2;
 };
-
-// pass 1: W = K_dn V on column slabs of 64 * E values.
-template <typename T, int E>
-__global__ void __launch_bounds__(256) k_hv_down(const int64_t d_up, const int64_t d_dn,
-                                                 const int32_t *__restrict__ nhd,
-                                                 const int32_t *__restrict__ cold,
-                                                 const double *__restrict__ cfd,
-                                                 const T *__restrict__ v, T *__restrict__ w,
-                                                 const int R, const int64_t nrb,
-                                                 const int64_t total, const int64_t per) {
-    const int64_t p = blockIdx.x;
-    const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
-    if (lg >= total) return;
-    const int64_t slab = lg / nrb, rb = lg - slab * nrb;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t c0 = slab * (64 * E) + (int64_t)lane * E;
-    const int64_t vrow = (int64_t)blockIdx.y * d_up * d_dn;  // vector index (batched)
-    const T *vv = v + vrow;
-    T *ww = w + vrow;
-    for (int k = wave; k < R; k += 4) {
-        const int64_t r = rb * R + k;
-        if (r >= d_dn) break;
-        const int nh = __builtin_amdgcn_readfirstlane(nhd[r]);
-        double acc[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = 0.0;
-        int s = 0;
-        for (; s + 4 <= nh; s += 4) {
-            T x[4][E];
-            double cf[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t eo = (int64_t)(s + u) * d_dn + r;
-                const int64_t jd = cold[eo];
-                cf[u] = cfd[eo];
-                const T *src = vv + jd * d_up + c0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) x[u][e] = (c0 + e < d_up) ? src[e] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[e] = fma(cf[u], (double)x[u][e], acc[e]);
-        }
-        for (; s < nh; ++s) {
-            const int64_t eo = (int64_t)s * d_dn + r;
-            const int64_t jd = cold[eo];
-            const double cf = cfd[eo];
-            const T *src = vv + jd * d_up + c0;
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (c0 + e < d_up) acc[e] = fma(cf, (double)src[e], acc[e]);
-        }
-        T *dst = ww + r * d_up + c0;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (c0 + e < d_up) dst[e] = (T)acc[e];
-    }
-}
-
-// pass 2: W += V K_up^T + D o V, one row at a time in LDS (persistent grid).
-template <typename T>
-__global__ void __launch_bounds__(1024) k_hv_inrow(const int64_t d_up, const int64_t d_dn,
-                                                   const uint32_t *__restrict__ su,
-                                                   const uint32_t *__restrict__ sd,
-                                                   const double *__restrict__ ed,
-                                                   const double *__restrict__ ulut_g,
-                                                   const int nbytes, const double u_uniform,
-                                                   const SplitArgs sp,
-                                                   const unsigned char *__restrict__ blob,
-                                                   const T *__restrict__ v, T *__restrict__ w) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const SplitLayout &lay = sp.lay;
-    // tables
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(blob);
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        for (int k = threadIdx.x; k < lay.bytes / 16; k += blockDim.x) dst[k] = src[k];
-    }
-    const int nlut = u_uniform >= 0.0 ? 0 : nbytes * 256;
-    double *ulut = reinterpret_cast<double *>(smem + lay.bytes);
-    for (int k = threadIdx.x; k < nlut; k += blockDim.x) ulut[k] = ulut_g[k];
-    T *row = reinterpret_cast<T *>(smem + lay.bytes + 8 * nlut);
-    const double *coef = reinterpret_cast<const double *>(smem + lay.off_coef);
-    const double *elo = reinterpret_cast<const double *>(smem + lay.off_elo);
-    const double *ehi = reinterpret_cast<const double *>(smem + lay.off_ehi);
-    const uint64_t *hient = reinterpret_cast<const uint64_t *>(smem + lay.off_hient);
-    const uint64_t *xent = reinterpret_cast<const uint64_t *>(smem + lay.off_xent);
-    const int32_t *rlo = reinterpret_cast<const int32_t *>(smem + lay.off_rlo);
-    const int32_t *looff = reinterpret_cast<const int32_t *>(smem + lay.off_looff);
-    const int32_t *hioff = reinterpret_cast<const int32_t *>(smem + lay.off_hioff);
-    const int32_t *xoff = reinterpret_cast<const int32_t *>(smem + lay.off_xoff);
-    const uint32_t *loent = reinterpret_cast<const uint32_t *>(smem + lay.off_loent);
-    const int64_t vbase = (int64_t)blockIdx.y * d_up * d_dn;
-    const T *vv = v + vbase;
-    T *ww = w + vbase;
-
-    for (int64_t r = blockIdx.x; r < d_dn; r += gridDim.x) {
-        __syncthreads();
-        const T *vrow = vv + r * d_up;
-        for (int64_t k = threadIdx.x; k < d_up; k += blockDim.x) row[k] = vrow[k];
-        __syncthreads();
-        const uint32_t bd = sd[r];
-        const double edn = ed[r];
-        T *wrow = ww + r * d_up;
-        for (int64_t i = threadIdx.x; i < d_up; i += blockDim.x) {
-            const uint32_t b = su[i];
-            const uint32_t h = b >> sp.l_lo, l = b & sp.lo_mask;
-            const uint32_t dbl = b & bd;
-            double diag = elo[l] + ehi[h] + edn;
-            if (u_uniform >= 0.0) {
-                diag += u_uniform * (double)__popc(dbl);
-            } else {
-                for (int byte = 0; byte < nbytes; ++byte)
-                    diag += ulut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
-            }
-            double acc = fma(diag, (double)row[i], (double)wrow[i]);
-            const int ii = (int)i;
-            for (int e = looff[l], e1 = looff[l + 1]; e < e1; ++e) {
-                const uint32_t ent = loent[e];
-                const int dlt = (int)(int16_t)(ent & 0xffffu);
-                acc = fma(coef[ent >> 16], (double)row[ii + dlt], acc);
-            }
-            for (int e = hioff[h], e1 = hioff[h + 1]; e < e1; ++e) {
-                const uint64_t ent = hient[e];
-                const int dlt = (int)(uint32_t)ent;
-                acc = fma(coef[(uint32_t)(ent >> 32)], (double)row[ii + dlt], acc);
-            }
-            for (int e = xoff[h], e1 = xoff[h + 1]; e < e1; ++e) {
-                const uint64_t ent = xent[e];
-                const uint32_t meta = (uint32_t)(ent >> 32);
-                const int a = meta & 31, dir = (meta >> 5) & 1, par = (meta >> 6) & 1;
-                const int has = (l >> a) & 1;
-                if (has == dir) continue;
-                const uint32_t l2 = l ^ (1u << a);
-                const int tgt = (int)(uint32_t)ent + rlo[l2];
-                const int sg = par ^ (__popc(l >> (a + 1)) & 1);
-                acc = fma(coef[2 * (meta >> 7) + sg], (double)row[tgt], acc);
-            }
-            wrow[i] = (T)acc;
-        }
-    }
-}
 
 // pass A of the team layout: W = V K_up^T + D o V, one row at a time in LDS.
 // Threads are grouped in teams that share one low half l: the hops inside l
@@ -448,7 +283,7 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_team(
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int idx = tid + k * NT;
-            xr[k] = (r < d_dn && idx < dup) ? src[idx] : T(0);
+            xr[k] = (r < d_dn && idx < dup) ? __builtin_nontemporal_load(src + idx) : T(0);
         }
     }
     for (; r < d_dn; r += gridDim.x) {
@@ -465,7 +300,7 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_team(
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
                 const int idx = tid + k * NT;
-                if (idx < dup) xr[k] = src[idx];
+                if (idx < dup) xr[k] = __builtin_nontemporal_load(src + idx);
             }
         }
         const uint32_t bd = sd[r];
@@ -537,7 +372,7 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_team(
                             }
                         }
                     }
-                    wrow[i] = (T)acc;
+                    __builtin_nontemporal_store((T)acc, wrow + i);
                 }
             }
         }
@@ -555,55 +390,64 @@ __global__ void k_row_offsets(int64_t d_dn, int W, int64_t d_up, const int32_t *
     if (e < d_dn * W) off[e] = (int64_t)col[e] * d_up;
 }
 
-template <typename T, int E>
+template <typename T, int RI>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
     const int64_t *__restrict__ offs, const double *__restrict__ cfd, const T *__restrict__ v,
     T *__restrict__ w, const int R, const int64_t nrb, const int64_t total, const int64_t per) {
     const int64_t p = blockIdx.x;
-    const int64_t lg = (p & 7) * per + (p >> 3);
+    const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
     if (lg >= total) return;
     const int64_t slab = lg / nrb, rb = lg - slab * nrb;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t c0 = slab * (64 * E) + (int64_t)lane * E;
+    const int64_t c0 = slab * 64 + lane;
+    const bool cok = c0 < d_up;
     const int64_t vb = (int64_t)blockIdx.y * d_up * d_dn;
     const T *vv = v + vb;
     T *ww = w + vb;
-    for (int k = wave; k < R; k += 4) {
-        const int64_t r = rb * R + k;
-        if (r >= d_dn) break;
-        const int nh = nhd[r];
-        const int64_t *ol = offs + r * W;
-        const double *cfl = cfd + r * W;
-        T *dst = ww + r * d_up + c0;
-        double acc[E];
+    // RI rows of the wave are worked on together: their hopping lists are
+    // wave-uniform (scalar loads), 8 neighbour segments of each in flight
+    for (int k = wave * RI; k < R; k += 4 * RI) {
+        int64_t rr[RI];
+        int nh[RI];
+        double acc[RI];
+        int nmax = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = (c0 + e < d_up) ? (double)dst[e] : 0.0;
-        for (int s0 = 0; s0 < nh; s0 += 8) {
-            int64_t jo[8];
-            double cf[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool ok = s0 + u < nh;
-                jo[u] = ok ? ol[s0 + u] : 0;
-                cf[u] = ok ? cfl[s0 + u] : 0.0;
-            }
-            T x[8][E];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const T *src = vv + jo[u] + c0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) x[u][e] = (s0 + u < nh && c0 + e < d_up) ? src[e] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int e = 0; e < E; ++e) acc[e] = fma(cf[u], (double)x[u][e], acc[e]);
+        for (int q = 0; q < RI; ++q) {
+            const int64_t r = rb * R + k + q;
+            const bool ok = r < d_dn;
+            rr[q] = ok ? r : rb * R + k;
+            nh[q] = ok ? nhd[rr[q]] : 0;
+            nmax = nh[q] > nmax ? nh[q] : nmax;
+            acc[q] = (ok && cok) ? (double)ww[rr[q] * d_up + c0] : 0.0;
         }
+        if (rb * R + k >= d_dn) break;
+        for (int s0 = 0; s0 < nmax; s0 += 8) {
+            T x[RI][8];
+            double cf[RI][8];
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (c0 + e < d_up) dst[e] = (T)acc[e];
+            for (int q = 0; q < RI; ++q) {
+                const int64_t *ol = offs + rr[q] * W;
+                const double *cl = cfd + rr[q] * W;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool ok = s0 + u < nh[q];
+                    const int64_t jo = ok ? ol[s0 + u] : 0;
+                    cf[q][u] = ok ? cl[s0 + u] : 0.0;
+                    x[q][u] = (ok && cok) ? vv[jo + c0] : T(0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RI; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[q] = fma(cf[q][u], (double)x[q][u], acc[q]);
+        }
+        if (cok) {
+#pragma unroll
+            for (int q = 0; q < RI; ++q)
+                if (rb * R + k + q < d_dn) ww[rr[q] * d_up + c0] = (T)acc[q];
+        }
     }
 }
 
@@ -627,11 +471,9 @@ int build_split_tables(const qcm_model *m, int N, Carver &cv, SplitTables *st, h
     cp(lay.off_elo, H.e_lo.data(), 8 * H.e_lo.size());
     cp(lay.off_ehi, H.e_hi.data(), 8 * H.e_hi.size());
     cp(lay.off_hient, H.hi_ent.data(), 8 * H.hi_ent.size());
-    cp(lay.off_xent, H.x_ent.data(), 8 * H.x_ent.size());
     cp(lay.off_rlo, H.rlo.data(), 4 * H.rlo.size());
     cp(lay.off_looff, H.lo_off.data(), 4 * H.lo_off.size());
     cp(lay.off_hioff, H.hi_off.data(), 4 * H.hi_off.size());
-    cp(lay.off_xoff, H.x_off.data(), 4 * H.x_off.size());
     cp(lay.off_loent, H.lo_ent.data(), 4 * H.lo_ent.size());
     cp(lay.off_xtab, H.xtab.data(), 8 * H.xtab.size());
     cp(lay.off_cls, H.cls.data(), 4 * H.cls.size());
@@ -649,43 +491,6 @@ size_t hv2_lds_bytes(const SplitTables &st, int prec, int64_t d_up, int nbytes, 
     return (size_t)st.lay.bytes + lut + s * d_up;
 }
 
-template <typename T>
-static int hv2_launch_t(const HvOp &op, const SplitTables &st, const void *v, void *w, int nvec,
-                        hipStream_t s) {
-    const int64_t d_up = op.up.d, d_dn = op.dn.d;
-    // pass 1
-    constexpr int E = sizeof(T) == 8 ? 1 : 2;
-    const int R = 16;
-    const int64_t nslab = (d_up + 64 * E - 1) / (64 * E);
-    const int64_t nrb = (d_dn + R - 1) / R;
-    const int64_t total = nslab * nrb;
-    const int64_t per = (total + 7) / 8;
-    dim3 g1((unsigned)(8 * per), (unsigned)nvec);
-    k_hv_down<T, E><<<g1, 256, 0, s>>>(d_up, d_dn, op.hd.nh, op.hd.col, op.hd.coef,
-                                       (const T *)v, (T *)w, R, nrb, total, per);
-    QCM_LAUNCH_CHECK();
-    // pass 2
-    SplitArgs sa;
-    sa.l_lo = st.l_lo;
-    sa.lo_mask = (1u << st.l_lo) - 1u;
-    sa.lay = st.lay;
-    const size_t lds = hv2_lds_bytes(st, sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V, d_up,
-                                     op.md.nbytes, op.md.u_uniform);
-    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
-    int64_t g2x = std::min<int64_t>(d_dn, 256 * per_cu);
-    dim3 g2((unsigned)g2x, (unsigned)nvec);
-    k_hv_inrow<T><<<g2, 1024, lds, s>>>(d_up, d_dn, op.up.states, op.dn.states, op.hd.ediag,
-                                        op.md.ulut, op.md.nbytes, op.md.u_uniform, sa,
-                                        (const unsigned char *)st.blob, (const T *)v, (T *)w);
-    QCM_LAUNCH_CHECK();
-    return QCM_OK;
-}
-
-int hv2_launch(const HvOp &op, const SplitTables &st, int prec, const void *v, void *w, int nvec,
-               hipStream_t s) {
-    if (prec == QCM_FP64) return hv2_launch_t<double>(op, st, v, w, nvec, s);
-    return hv2_launch_t<float>(op, st, v, w, nvec, s);
-}
 
 
 template <typename T, int KS, int MAXLO, int MAXXB>
@@ -722,14 +527,13 @@ static int hv3_launch_t(const HvOp &op, const SplitTables &st, const HopTables &
 #undef QCM_TEAM
     QCM_LAUNCH_CHECK();
     // pass B: row mixing, accumulates into W
-    constexpr int E = sizeof(T) == 8 ? 1 : 2;
     const int R = 16;
-    const int64_t nslab = (d_up + 64 * E - 1) / (64 * E);
+    const int64_t nslab = (d_up + 63) / 64;
     const int64_t nrb = (d_dn + R - 1) / R;
     const int64_t total = nslab * nrb;
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
-    k_hv_down_acc<T, E><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
+    k_hv_down_acc<T, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
                                            hd_rm.coef, (const T *)v, (T *)w, R, nrb, total, per);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
@@ -802,5 +606,7 @@ int hv_split_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, 
     st.blob = op.split_blob;
     return hv3_launch(op, st, op.hd_rm, prec, v, w, nvec, s);
 }
+
+
 
 }  // namespace qcm

@@ -164,8 +164,7 @@ namespace qcm {
 //  - cross hops move it between the halves: target = base(h') + rlo[l'].
 // Everything is small (2^(L/2) entries) and is staged into LDS.
 struct SplitLayout {
-    int32_t off_coef, off_elo, off_ehi, off_hient, off_xent, off_rlo, off_looff, off_hioff,
-        off_xoff, off_loent, bytes;
+    int32_t off_coef, off_elo, off_ehi, off_hient, off_rlo, off_looff, off_hioff, off_loent, bytes;
     // team layout (one low half per thread, high halves looped)
     int32_t off_cls, off_llist, off_hlist, off_hbase, off_xbond, off_xtab;
     int32_t ncls, nxb, max_lo, max_hi, zero_coef;
@@ -174,9 +173,8 @@ struct SplitLayout {
 //   coef[2*nbond]        t_b and -t_b
 //   e_lo[2^l_lo], e_hi[2^l_hi]   sum of t_kk over the set bits of l, of h
 //   hi_ent               (uint32)(int32 label shift) | (coef index << 32)
-//   x_ent                (uint32) base(h') | (a | dir << 5 | parity << 6 | bond << 7) << 32
 //   rlo[2^l_lo]          label of the low half
-//   lo_off, hi_off, x_off  CSR offsets per l, per h, per h
+//   lo_off, hi_off       CSR offsets per l, per h
 //   lo_ent               (int16 label shift) | (coef index << 16)
 struct SplitTables {
     int32_t l_lo, l_hi, nbond;
@@ -188,8 +186,6 @@ struct SplitTables {
 bool split_tables_size(const qcm_model *m, int N, size_t *bytes);
 int build_split_tables(const qcm_model *m, int N, Carver &cv, SplitTables *st, hipStream_t s);
 size_t hv2_lds_bytes(const SplitTables &st, int prec, int64_t d_up, int nbytes, double u_uniform);
-int hv2_launch(const HvOp &op, const SplitTables &st, int prec, const void *v, void *w, int nvec,
-               hipStream_t s);
 int build_row_offsets(HopTables &ht, int64_t d_up, Carver &cv, hipStream_t s);
 int hv3_launch(const HvOp &op, const SplitTables &st, const HopTables &hd_rm, int prec,
                const void *v, void *w, int nvec, hipStream_t s);
