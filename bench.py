@@ -41,6 +41,13 @@ def parse():
     p.add_argument("--cpu-rows", type=int, default=0,
                    help="rows of the sector the oracle computes for the CPU baseline "
                         "(0: every row, one full product)")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-solve figures")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving figures")
+    p.add_argument("--batch-count", type=int, default=256, help="batched solves (seed 18643)")
+    p.add_argument("--serve-count", type=int, default=60, help="serving requests per rate")
+    p.add_argument("--serve-rates", default="1,2,4",
+                   help="arrival rates as multiples of the one-at-a-time FP64 rate")
+    p.add_argument("--serve-budget-gib", type=float, default=64.0, help="engine pool (GiB)")
     return p.parse_args()
 
 
@@ -153,6 +160,11 @@ def main():
             out[f"lanczos_{prec}"] = {"steps": r["n_iter"], "s_per_step": round(dt / r["n_iter"], 5),
                                       "theta0_after_10": r["e0"]}
 
+    if not args.no_batch:
+        out["batched"] = batched_section(args, torch, q, synth, np)
+    if not args.no_serve:
+        out["serving"] = serving_section(args, torch, q, synth, np)
+
     if not args.no_cpu:
         import oracle
         nrows = d if args.cpu_rows <= 0 else min(args.cpu_rows, d)
@@ -170,6 +182,136 @@ def main():
                                          f"16 bytes per row like the GPU figure"}
         del vh
     print(json.dumps(out), flush=True)
+
+
+Z_GRID = None
+
+
+def _z(synth):
+    global Z_GRID
+    if Z_GRID is None:
+        Z_GRID = synth.omega_grid()
+    return Z_GRID
+
+
+def solve_single_fp64(q, m, z, gf_steps, stream=None):
+    """One request through the single-solve calls in plain FP64."""
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    r = q.lanczos_gs((m.t, m.U), b)
+    g = q.green_cf((m.t, m.U), b, r["psi"], r["e0"], [0, 1, 2, 3], z, max_steps=gf_steps)
+    return r["e0"], g["G"]
+
+
+def engine_opts_for(prec):
+    # residual test: the engine's automatic tolerance (1e-12 in FP64, 1e-7
+    # with FP32 vectors, whose rounding floors the residual estimate)
+    if prec == "fp64":
+        return dict(prec="fp64", reorth=0)
+    return dict(prec="fp32v", reorth=1)
+
+
+def batched_section(args, torch, q, synth, np):
+    """256 impurity solves (4-site cluster + 2..10 bath orbitals, seed 18643):
+    ground state to convergence plus the 4x4 cluster G with 100-floor chains
+    on the 64-point grid.  Engine in FP32V and FP64 with every solve in flight
+    at once, against the same solves run one at a time through the
+    single-solve calls in FP64."""
+    z = _z(synth)
+    ms = synth.batched_solves(18643, args.batch_count)
+    out = {"workload": f"{len(ms)} impurity solves, seed 18643, n = 6..14 orbitals, GS + 4x4 G "
+                       "(M_G = 100, 64 frequencies)"}
+    res = {}
+    for prec in ("fp32v", "fp64"):
+        specs = [q.JobSpec((m.t, m.U), m.nup, m.ndn, orbs=range(4), tag=i) for i, m in enumerate(ms)]
+        kw = dict(gf_steps=100, z=z, max_jobs=len(ms), **engine_opts_for(prec))
+        need = q.batch_bytes(specs, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr = q.batch_solve(specs, ws_bytes=need, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = rr
+        out[f"engine_{prec}"] = {"s": round(dt, 3), "solves_per_s": round(len(ms) / dt, 2),
+                                 "pool_GB": round(need / 1e9, 2),
+                                 "gs_steps_mean": round(float(np.mean([r["n_iter"] for r in rr])), 1)}
+        print(f"batched engine {prec}: {dt:.2f} s", file=sys.stderr, flush=True)
+    # accuracy of FP32V against the FP64 engine (itself pinned to the oracle)
+    e64 = np.array([r["e0"] for r in res["fp64"]])
+    e32 = np.array([r["e0"] for r in res["fp32v"]])
+    dG = max(float(np.abs(a["G"] - b["G"]).max()) for a, b in zip(res["fp32v"], res["fp64"]))
+    out["fp32v_vs_fp64"] = {"max_rel_dE0": float(np.max(np.abs(e32 - e64) / np.abs(e64))),
+                            "max_abs_dG": dG}
+    # baseline: the same solves one at a time, FP64 single-solve calls
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base = []
+    for i, m in enumerate(ms):
+        base.append(solve_single_fp64(q, m, z, 100))
+        if (i + 1) % 32 == 0:
+            print(f"  one-at-a-time fp64: {i + 1} solves, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["one_at_a_time_fp64"] = {"s": round(dt, 3), "solves_per_s": round(len(ms) / dt, 2)}
+    out["speedup_fp32v_engine"] = round(dt / out["engine_fp32v"]["s"], 2)
+    out["speedup_fp64_engine"] = round(dt / out["engine_fp64"]["s"], 2)
+    # the FP64 engine equals the single-solve calls bit for bit
+    out["fp64_engine_equals_single_calls"] = bool(all(
+        r["e0"] == e0 and np.array_equal(r["G"], G.cpu().numpy())
+        for r, (e0, G) in zip(res["fp64"], base)))
+    print(f"batched one-at-a-time fp64: {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def serving_section(args, torch, q, synth, np):
+    """Poisson streams of serving requests (seed 2305: 4..14-orbital chains
+    and ladders, GS + 4x4 G, M_G = 100) at multiples of the one-at-a-time
+    FP64 rate R1, through the continuously batched FP32V engine with a pool
+    budget; the baseline is the FIFO one-at-a-time FP64 queue on the same
+    arrivals, from each request's measured service time."""
+    from paper_2305_18643_amd import serving
+    z = _z(synth)
+    n = args.serve_count
+    reqs = synth.serving_requests(2305, n)
+    # service time of each request alone, FP64 single-solve calls
+    svc = []
+    solve_single_fp64(q, reqs[0], z, 100)   # warm-up
+    for i, m in enumerate(reqs):
+        if i % 20 == 0:
+            print(f"  serving baseline: request {i}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve_single_fp64(q, m, z, 100)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+    svc = np.array(svc)
+    r1 = n / svc.sum()
+    out = {"workload": f"{n} requests per rate, seed 2305, n = 4..14 orbitals, GS + 4x4 G "
+                       "(M_G = 100), Poisson arrivals",
+           "R1_fp64_one_at_a_time_solves_per_s": round(r1, 3),
+           "budget_GiB": args.serve_budget_gib, "rates": []}
+    budget = int(args.serve_budget_gib * (1 << 30))
+    eng = q.Engine(budget, gf_steps=100, z=z, max_jobs=256, **engine_opts_for("fp32v"))
+    for k, mult in enumerate(float(x) for x in args.serve_rates.split(",")):
+        lam = mult * r1
+        arr = serving.poisson_arrivals(lam, n, seed=2305 + k)
+        specs = [q.JobSpec((m.t, m.U), m.nup, m.ndn, orbs=range(4), tag=i)
+                 for i, m in enumerate(reqs)]
+        rep = serving.serve(eng, specs, arr)
+        base = serving.fifo_one_at_a_time(svc, arr)
+        out["rates"].append({
+            "x_R1": mult, "rate_per_s": round(lam, 3),
+            "engine_fp32v": {"p50_s": round(rep.percentile(50), 4),
+                             "p99_s": round(rep.percentile(99), 4),
+                             "solves_per_s": round(rep.throughput(), 3),
+                             "max_in_flight": rep.max_in_flight},
+            "fifo_fp64": {"p50_s": round(serving.nearest_rank(base, 50), 4),
+                          "p99_s": round(serving.nearest_rank(base, 99), 4),
+                          "solves_per_s": round(n / (arr[-1] + base[-1]), 3)}})
+        print(f"serving x{mult}: p99 {rep.percentile(99):.3f} s", file=sys.stderr, flush=True)
+    out["peak_pool_GB"] = round(eng.info()["peak_in_use"] / 1e9, 3)
+    eng.close()
+    return out
 
 
 if __name__ == "__main__":

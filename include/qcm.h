@@ -256,6 +256,132 @@ int qcm_cpt_gk(int32_t L, int32_t n_z, const double *d_Gc, const int32_t *h_R,
                const double *h_k, double *d_Gper, void *d_ws, size_t ws_bytes,
                size_t *ws_needed, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched and continuously served solves.
+ *
+ * A job is a model, a sector and (optionally) a block of orbitals: the
+ * engine computes its ground state exactly as qcm_lanczos_gs does (two
+ * passes, true residual) and then the Green-function chains of that block as
+ * qcm_green_cf does, and evaluates G on the engine's frequency grid.  Many
+ * jobs of different sizes are in flight at once: every round advances each
+ * admitted job by one Lanczos step, with one set of launches covering all of
+ * them.  A job's results depend only on the job (not on the other jobs in
+ * flight), and equal those of the single-solve calls with the same options.
+ *
+ * Memory: the caller hands the engine one device pool at creation; the
+ * engine keeps its tables at the start of the pool and gives each admitted
+ * job one block of it (first fit), returned when the job completes.  A job is
+ * admitted only if a slot and a large enough block are free: this is the
+ * admission by memory budget.  The engine also allocates a small pinned host
+ * buffer (hipHostMalloc) for its per-round tables, freed by
+ * qcm_engine_destroy.  An engine is used by one host thread at a time.
+ * Limits: every up-spin sector of a job (N_up and, with orbitals, N_up +- 1)
+ * has at most 8192 strings (every sector of up to 15 orbitals qualifies);
+ * larger sectors are for the single-solve calls.
+ * ------------------------------------------------------------------------ */
+
+typedef struct qcm_engine qcm_engine;   /* opaque */
+
+typedef struct qcm_engine_opts {
+    int32_t prec;            /* QCM_FP64 or QCM_FP32V storage of every vector */
+    int32_t reorth;          /* local reorthogonalisation in every chain (0/1) */
+    int32_t max_iter;        /* ground-state step cap (residual test every step) */
+    int32_t gs_fixed_steps;  /* > 0: exactly this many ground-state steps
+                                (fewer only on breakdown), no residual test */
+    int32_t gf_steps;        /* continued-fraction floors per chain (M_G) */
+    int32_t max_jobs;        /* jobs in flight at once (slots), 1..65536 */
+    double tol;              /* residual test, as in qcm_lanczos_opts; <= 0: automatic,
+                                1e-12 with QCM_FP64 and 1e-7 with QCM_FP32V (FP32
+                                storage floors the residual estimate near 1e-7) */
+    double btol;             /* breakdown threshold, as in qcm_lanczos_opts */
+    int32_t n_z;             /* frequencies of the grid (0: no G evaluation) */
+    int32_t pad;
+    const double *h_z;       /* host complex [n_z] as (re, im); copied at creation */
+} qcm_engine_opts;
+
+/* Defaults: FP32V with reorthogonalisation, max_iter 600, gf_steps 100,
+ * automatic tol (0), btol 1e-13, max_jobs 256, no grid. */
+int qcm_engine_default_opts(qcm_engine_opts *o);
+
+typedef struct qcm_job {
+    qcm_model model;         /* host; copied at submission */
+    int32_t n_up, n_dn;      /* ground-state sector */
+    int32_t n_orb;           /* orbitals of the G block (0: ground state only) */
+    int32_t pad;
+    const int32_t *orbs;     /* host [n_orb], distinct; copied */
+    uint64_t seed;           /* SplitMix64 seed of the start vector */
+    int64_t tag;             /* caller's identifier, returned in the result */
+    double *h_G;             /* host complex128 [n_z][n_orb][n_orb] or NULL */
+    double *h_coef;          /* host [n_pairs][2][1 + 2*gf_steps] or NULL (layout of
+                                qcm_green_cf) */
+    int32_t *h_len;          /* host [n_pairs][2] or NULL */
+    double *d_psi;           /* device double[dim] or NULL: receives the ground state */
+} qcm_job;
+
+typedef struct qcm_job_result {
+    int64_t tag;
+    double e0, theta1, residual_est, true_residual;   /* as in qcm_gs_result */
+    int32_t n_iter, converged, breakdown;
+    int32_t status;          /* QCM_OK */
+    int64_t bytes;           /* pool bytes the job held */
+    int32_t rounds;          /* rounds from admission to completion */
+    int32_t pad;
+} qcm_job_result;
+
+typedef struct qcm_engine_stats {
+    int64_t pool_bytes, header_bytes, in_use, peak_in_use, largest_free, rounds;
+    int32_t active, finished;   /* jobs in flight; results waiting for poll */
+} qcm_engine_stats;
+
+/*
+ * qcm_engine_create — an engine over the device pool d_pool (256-byte
+ * aligned, pool_bytes long), enqueueing on `stream`.  *out receives the
+ * handle.  Errors: QCM_EARG, QCM_EWORKSPACE (pool smaller than the tables),
+ * QCM_EHIP.
+ */
+int qcm_engine_create(const qcm_engine_opts *o, void *d_pool, size_t pool_bytes, void *stream,
+                      qcm_engine **out);
+
+/* Waits for the stream, drops unfinished jobs, frees the host side. */
+int qcm_engine_destroy(qcm_engine *e);
+
+/* Pool bytes a job would hold under options o (validates the job). */
+int qcm_engine_job_bytes(const qcm_engine_opts *o, const qcm_job *j, size_t *bytes);
+
+/*
+ * qcm_engine_submit — admit a job: copies it, builds its tables and start
+ * vector (enqueued).  QCM_EWORKSPACE if no slot or no pool block is free now
+ * (nothing is done; submit again after some jobs complete); QCM_EARG /
+ * QCM_ERANGE for an invalid job.  The host buffers h_G, h_coef, h_len and
+ * the device buffer d_psi must stay valid until the job's result is polled.
+ */
+int qcm_engine_submit(qcm_engine *e, const qcm_job *j);
+
+/*
+ * qcm_engine_step — run up to `rounds` rounds (stops early when no job is in
+ * flight).  Completed jobs have their outputs written and their results
+ * queued for qcm_engine_poll.  *n_active (may be NULL) receives the number of
+ * jobs still in flight.  Synchronises the stream after every round.
+ */
+int qcm_engine_step(qcm_engine *e, int32_t rounds, int32_t *n_active);
+
+/* Up to max_out completed results, oldest first; *n_out receives the count. */
+int qcm_engine_poll(qcm_engine *e, int32_t max_out, qcm_job_result *h_res, int32_t *n_out);
+
+/* Pool occupancy and counters. */
+int qcm_engine_info(const qcm_engine *e, qcm_engine_stats *out);
+
+/*
+ * qcm_batch_solve — solve n_jobs jobs through an engine built in d_ws,
+ * admitting them in order as memory allows, and write result i of job i to
+ * h_res[i].  With d_ws == NULL, *ws_needed receives the bytes that hold every
+ * job at once (any workspace that holds the engine tables and the largest
+ * job works, with fewer jobs in flight).  Synchronises the stream.
+ */
+int qcm_batch_solve(const qcm_engine_opts *o, int32_t n_jobs, const qcm_job *jobs,
+                    qcm_job_result *h_res, void *d_ws, size_t ws_bytes, size_t *ws_needed,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,9 +69,42 @@ class Bond(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("t", ctypes.c_double)]
 
 
+class EngineOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("gs_fixed_steps", ctypes.c_int32),
+                ("gf_steps", ctypes.c_int32), ("max_jobs", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("btol", ctypes.c_double),
+                ("n_z", ctypes.c_int32), ("pad", ctypes.c_int32), ("h_z", _c_d)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("model", Model), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("n_orb", ctypes.c_int32), ("pad", ctypes.c_int32), ("orbs", _c_i32),
+                ("seed", ctypes.c_uint64), ("tag", ctypes.c_int64), ("h_G", _c_d),
+                ("h_coef", _c_d), ("h_len", _c_i32), ("d_psi", ctypes.c_void_p)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("e0", ctypes.c_double), ("theta1", ctypes.c_double),
+                ("residual_est", ctypes.c_double), ("true_residual", ctypes.c_double),
+                ("n_iter", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("bytes", ctypes.c_int64), ("rounds", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class EngineStats(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("header_bytes", ctypes.c_int64),
+                ("in_use", ctypes.c_int64), ("peak_in_use", ctypes.c_int64),
+                ("largest_free", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("active", ctypes.c_int32), ("finished", ctypes.c_int32)]
+
+
 # every symbol declared in include/qcm.h
 EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
-           "qcm_lanczos_default_opts", "qcm_lanczos_gs", "qcm_green_cf", "qcm_cpt_gk"]
+           "qcm_lanczos_default_opts", "qcm_lanczos_gs", "qcm_green_cf", "qcm_cpt_gk",
+           "qcm_engine_default_opts", "qcm_engine_create", "qcm_engine_destroy",
+           "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
+           "qcm_engine_info", "qcm_batch_solve"]
 
 _lib = None
 
@@ -108,6 +141,26 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_cpt_gk.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, _c_i32, _c_i32,
                                ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, _c_d, vp,
                                vp, sz, _c_sz, vp]
+    P = ctypes.POINTER
+    lib.qcm_engine_default_opts.restype = ctypes.c_int
+    lib.qcm_engine_default_opts.argtypes = [P(EngineOpts)]
+    lib.qcm_engine_create.restype = ctypes.c_int
+    lib.qcm_engine_create.argtypes = [P(EngineOpts), vp, sz, vp, P(vp)]
+    lib.qcm_engine_destroy.restype = ctypes.c_int
+    lib.qcm_engine_destroy.argtypes = [vp]
+    lib.qcm_engine_job_bytes.restype = ctypes.c_int
+    lib.qcm_engine_job_bytes.argtypes = [P(EngineOpts), P(Job), _c_sz]
+    lib.qcm_engine_submit.restype = ctypes.c_int
+    lib.qcm_engine_submit.argtypes = [vp, P(Job)]
+    lib.qcm_engine_step.restype = ctypes.c_int
+    lib.qcm_engine_step.argtypes = [vp, ctypes.c_int32, _c_i32]
+    lib.qcm_engine_poll.restype = ctypes.c_int
+    lib.qcm_engine_poll.argtypes = [vp, ctypes.c_int32, P(JobResult), _c_i32]
+    lib.qcm_engine_info.restype = ctypes.c_int
+    lib.qcm_engine_info.argtypes = [vp, P(EngineStats)]
+    lib.qcm_batch_solve.restype = ctypes.c_int
+    lib.qcm_batch_solve.argtypes = [P(EngineOpts), ctypes.c_int32, P(Job), P(JobResult), vp, sz,
+                                    _c_sz, vp]
     _lib = lib
     return lib
 
@@ -330,3 +383,159 @@ def cpt_gk(Gc, R, E, bonds, ks, z=None, stream=None):
                           ks.ctypes.data_as(_c_d), ctypes.c_void_p(out.data_ptr()), _ptr(ws),
                           ws.numel(), ctypes.byref(need), _stream(torch, stream)))
     return out
+
+
+# ---------------------------------------------------------------- batched / served solves
+
+def engine_opts(*, prec="fp32v", reorth=None, max_iter=600, gs_fixed_steps=0, gf_steps=100,
+                tol=0.0, btol=1e-13, max_jobs=256, z=()):
+    """EngineOpts plus the frequency array it points to (keep both alive)."""
+    o = EngineOpts()
+    lib = load_library()
+    _check(lib.qcm_engine_default_opts(ctypes.byref(o)))
+    o.prec = PREC[prec]
+    o.reorth = (1 if o.prec == QCM_FP32V else 0) if reorth is None else int(reorth)
+    o.max_iter, o.gs_fixed_steps, o.gf_steps = max_iter, gs_fixed_steps, gf_steps
+    o.tol, o.btol, o.max_jobs = tol, btol, max_jobs
+    zc = np.asarray(z, dtype=np.complex128).ravel()
+    zz = np.ascontiguousarray(np.stack([zc.real, zc.imag], axis=-1).ravel())
+    o.n_z = zc.shape[0]
+    o.h_z = zz.ctypes.data_as(_c_d) if zc.shape[0] else None
+    return o, zz
+
+
+class JobSpec:
+    """One solve: model (t, U), sector, G orbitals, seed.  Holds the host
+    buffers the library writes the job's outputs into."""
+
+    def __init__(self, model, n_up, n_dn, orbs=(), seed=1, tag=0, psi=None):
+        self.model = as_model(model)
+        self.n_up, self.n_dn = int(n_up), int(n_dn)
+        self.orbs = np.ascontiguousarray(orbs, dtype=np.int32).ravel()
+        self.seed, self.tag, self.psi = int(seed), int(tag), psi
+        self.G = self.coef = self.len = None
+
+    def c_job(self, n_z: int, gf_steps: int, ctag: int) -> Job:
+        n = self.orbs.shape[0]
+        npairs = n * (n + 1) // 2
+        self.G = np.zeros((max(n_z, 1), n, n), dtype=np.complex128)
+        self.coef = np.zeros((npairs, 2, 1 + 2 * gf_steps))
+        self.len = np.zeros((npairs, 2), dtype=np.int32)
+        j = Job()
+        j.model = self.model.c
+        j.n_up, j.n_dn, j.n_orb = self.n_up, self.n_dn, n
+        j.orbs = self.orbs.ctypes.data_as(_c_i32) if n else None
+        j.seed, j.tag = self.seed, ctag
+        if n:
+            j.h_G = self.G.ctypes.data_as(_c_d) if n_z else None
+            j.h_coef = self.coef.ctypes.data_as(_c_d)
+            j.h_len = self.len.ctypes.data_as(_c_i32)
+        j.d_psi = self.psi.data_ptr() if self.psi is not None else None
+        return j
+
+    def result(self, r: JobResult, n_z: int) -> dict:
+        return dict(tag=self.tag, e0=r.e0, theta1=r.theta1, residual_est=r.residual_est,
+                    true_residual=r.true_residual, n_iter=r.n_iter, converged=bool(r.converged),
+                    breakdown=bool(r.breakdown), bytes=r.bytes, rounds=r.rounds,
+                    G=self.G[:n_z] if self.orbs.shape[0] else None, coef=self.coef, len=self.len,
+                    psi=self.psi)
+
+
+class Engine:
+    """A continuously batched solver over one device pool (qcm_engine_*)."""
+
+    def __init__(self, pool_bytes: int, *, device="cuda", stream=None, **opts):
+        torch = _torch()
+        self.lib = load_library()
+        self.o, self._z = engine_opts(**opts)
+        self.pool = _workspace(torch, pool_bytes, device)
+        self.stream = stream
+        self.h = ctypes.c_void_p()
+        _check(self.lib.qcm_engine_create(ctypes.byref(self.o), _ptr(self.pool), self.pool.numel(),
+                                          _stream(torch, stream), ctypes.byref(self.h)))
+        self._jobs = {}
+        self._next = 0
+
+    def job_bytes(self, spec: JobSpec) -> int:
+        need = ctypes.c_size_t(0)
+        j = spec.c_job(self.o.n_z, self.o.gf_steps, 0)
+        _check(self.lib.qcm_engine_job_bytes(ctypes.byref(self.o), ctypes.byref(j),
+                                             ctypes.byref(need)))
+        return need.value
+
+    def submit(self, spec: JobSpec) -> bool:
+        """Admit the job if a slot and pool memory are free; False otherwise."""
+        ctag = self._next
+        j = spec.c_job(self.o.n_z, self.o.gf_steps, ctag)
+        rc = self.lib.qcm_engine_submit(self.h, ctypes.byref(j))
+        if rc == QCM_EWORKSPACE:
+            return False
+        _check(rc)
+        self._jobs[ctag] = (spec, j)
+        self._next += 1
+        return True
+
+    def step(self, rounds: int = 1) -> int:
+        n = ctypes.c_int32(0)
+        _check(self.lib.qcm_engine_step(self.h, rounds, ctypes.byref(n)))
+        return n.value
+
+    def poll(self) -> list:
+        out = []
+        buf = (JobResult * 64)()
+        while True:
+            k = ctypes.c_int32(0)
+            _check(self.lib.qcm_engine_poll(self.h, 64, buf, ctypes.byref(k)))
+            for i in range(k.value):
+                spec, _ = self._jobs.pop(buf[i].tag)
+                out.append(spec.result(buf[i], self.o.n_z))
+            if k.value < 64:
+                return out
+
+    def info(self) -> dict:
+        st = EngineStats()
+        _check(self.lib.qcm_engine_info(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in EngineStats._fields_}
+
+    def close(self):
+        if self.h:
+            _check(self.lib.qcm_engine_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_solve(specs, *, ws_bytes=None, device="cuda", stream=None, **opts) -> list:
+    """Solve every JobSpec through qcm_batch_solve; results in input order."""
+    torch = _torch()
+    lib = load_library()
+    o, zz = engine_opts(**opts)
+    n = len(specs)
+    jobs = (Job * max(n, 1))()
+    for i, sp in enumerate(specs):
+        jobs[i] = sp.c_job(o.n_z, o.gf_steps, i)
+    res = (JobResult * max(n, 1))()
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_batch_solve(ctypes.byref(o), n, jobs, res, None, 0, ctypes.byref(need), None))
+    nb = need.value if ws_bytes is None else int(ws_bytes)
+    ws = _workspace(torch, nb, device)
+    _check(lib.qcm_batch_solve(ctypes.byref(o), n, jobs, res, _ptr(ws), ws.numel(),
+                               ctypes.byref(need), _stream(torch, stream)))
+    return [specs[i].result(res[i], o.n_z) for i in range(n)]
+
+
+def batch_bytes(specs, **opts) -> int:
+    """Workspace bytes qcm_batch_solve needs to hold every job at once."""
+    lib = load_library()
+    o, zz = engine_opts(**opts)
+    n = len(specs)
+    jobs = (Job * max(n, 1))()
+    for i, sp in enumerate(specs):
+        jobs[i] = sp.c_job(o.n_z, o.gf_steps, i)
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_batch_solve(ctypes.byref(o), n, jobs, None, None, 0, ctypes.byref(need), None))
+    return need.value

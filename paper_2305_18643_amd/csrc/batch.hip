@@ -1,0 +1,1172 @@
+// Batched and continuously served ED solves: many independent jobs (a model
+// and a sector each) in flight on one GPU at once.
+//
+// A job is one ground-state solve followed by its Green-function chains
+// (paper: section "Exact diagonalizations", subsections "The Lanczos
+// algorithm for the ground state" and "The Lanczos algorithm for the Green
+// function"), run through four phases:
+//   GS1  the Lanczos recurrence until the residual test on T_M is met;
+//   GS2  the identical recurrence replayed, psi = sum_n s_n v_n, then psi is
+//        normalised and its true residual taken;
+//   GF   the electron and hole chains of every orbital pair, both parts at
+//        once (each part is one multi-chain group in its own sector);
+//   end  continued fractions evaluated on the frequency grid, results copied
+//        to the caller's host buffers, device memory returned to the pool.
+//
+// The engine advances every admitted job by one Lanczos step per round.  A
+// round is a fixed sequence of launches whatever the number of jobs: each
+// launch covers the work of all jobs through a table of groups (one group =
+// the chains of one job in one sector) and per-launch prefix sums over the
+// groups' blocks, chunks or chains; a workgroup finds its group by binary
+// search.  Jobs join and leave between rounds, so a request that arrives
+// while others run is admitted as soon as a slot and pool memory are free
+// (continuous batching).
+//
+// Every kernel reproduces, element by element and chunk by chunk, the
+// arithmetic of the single-solve path (same FP64 accumulation order in the
+// product, same fixed-chunk two-level sums, same tridiagonal solver), so the
+// result of a job is bitwise independent of which other jobs share its
+// rounds and equals what the single-solve calls return.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "lanczos_device.h"
+
+namespace qcm {
+
+// Longest row of V a product block stages in LDS (up-spin strings of one
+// sector).  Jobs with a longer up-spin sector use the single-solve calls.
+constexpr int64_t kMaxRow = 8192;
+// Elements of V staged per product block when rows are short.
+constexpr int64_t kBlockElems = 2048;
+
+// ---------------------------------------------------------------- round tables
+
+// One group: the nvec chains of one job in one sector, at step n.
+struct BGroup {
+    int64_t d_up, d_dn, dim;
+    const uint32_t *su, *sd;
+    const double *eu, *ed;
+    const int32_t *nhu, *nhd, *colu, *cold;
+    const double *cfu, *cfd;
+    const double *ulut;
+    double u_uniform;
+    int32_t nbytes;
+    int32_t rows;      // rows of V per product block
+    int32_t nblk;      // product blocks per vector
+    int32_t nvec, nchunks, n;
+    const void *vp;    // v_{n-1} [nvec][dim]
+    const void *v;     // v_n
+    void *w;           // the new vector
+    double *partial;   // [nvec][nchunks]
+    ChainState cs;
+};
+
+// psi += svec[n] * v_n of one replaying ground-state chain
+struct BAcc {
+    const void *v;
+    double *psi;
+    const double *svec;
+    int64_t dim;
+    int32_t nchunks, n;
+};
+
+// per-job end-of-round test and status gathering
+struct BCtl {
+    int32_t test;   // run the ground-state test on T_m
+    int32_t m;
+    double tol;
+    const double *alpha, *beta;
+    double *work, *svec;
+    GsStatus *status;
+    const int32_t *done0, *done1;
+    int32_t n0, n1;
+    const int32_t *len0;
+};
+
+struct BStat {
+    GsStatus gs;
+    int32_t all_done;
+    int32_t len0;
+    int32_t pad[2];
+};
+
+__device__ __forceinline__ int find_group(const int64_t *__restrict__ begin, int ng, int64_t x) {
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// w = H v for every vector of every group.  A block holds `rows` whole rows
+// of V in LDS (the in-row term gathers there), streams the neighbour rows of
+// the row-mixing term from global memory and computes the diagonal from the
+// two strings.  The sum runs in the order of the single-sector kernel:
+// diagonal, up hops in list order, down hops in list order, all FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_hv(const BGroup *__restrict__ G,
+                                             const int64_t *__restrict__ begin, int ng) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int g = find_group(begin, ng, blockIdx.x);
+    const BGroup &q = G[g];
+    const int64_t local = (int64_t)blockIdx.x - begin[g];
+    const int64_t vec = local / q.nblk;
+    const int64_t rb = local - vec * q.nblk;
+    const int64_t d_up = q.d_up;
+    const int64_t row0 = rb * q.rows;
+    const int64_t nr = min((int64_t)q.rows, q.d_dn - row0);
+    const int nlut = q.u_uniform >= 0.0 ? 0 : q.nbytes * 256;
+    double *lut = reinterpret_cast<double *>(smem_raw);
+    T *row = reinterpret_cast<T *>(smem_raw + sizeof(double) * nlut);
+    const T *v = (const T *)q.v + vec * q.dim;
+    T *w = (T *)q.w + vec * q.dim;
+    for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = q.ulut[k];
+    const int64_t nel = nr * d_up;
+    const T *vblk = v + row0 * d_up;
+    for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
+    __syncthreads();
+    const uint32_t du = (uint32_t)d_up;
+    for (int64_t e = threadIdx.x; e < nel; e += 256) {
+        const uint32_t r = (uint32_t)e / du;
+        const uint32_t iu = (uint32_t)e - r * du;
+        const int64_t idn = row0 + r;
+        const uint32_t bu = q.su[iu];
+        const uint32_t bd = q.sd[idn];
+        const uint32_t dbl = bu & bd;
+        double diag = q.eu[iu] + q.ed[idn];
+        if (q.u_uniform >= 0.0) {
+            diag += q.u_uniform * (double)__popc(dbl);
+        } else {
+            for (int byte = 0; byte < q.nbytes; ++byte)
+                diag += lut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
+        }
+        const T *rrow = row + (int64_t)r * d_up;
+        double acc = diag * (double)rrow[iu];
+        const int nhu = q.nhu[iu];
+        for (int s = 0; s < nhu; ++s) {
+            const int64_t ee = (int64_t)s * d_up + iu;
+            acc = fma(q.cfu[ee], (double)rrow[q.colu[ee]], acc);
+        }
+        const int nhd = q.nhd[idn];
+        for (int s = 0; s < nhd; ++s) {
+            const int64_t ee = (int64_t)s * q.d_dn + idn;
+            acc = fma(q.cfd[ee], (double)v[(int64_t)q.cold[ee] * d_up + iu], acc);
+        }
+        w[idn * d_up + iu] = (T)acc;
+    }
+}
+
+// chunk c of vector `vec` of group g for the chunked kernels
+struct ChunkAt {
+    int g;
+    int64_t vec, base;
+};
+__device__ __forceinline__ ChunkAt chunk_at(const BGroup *__restrict__ G,
+                                            const int64_t *__restrict__ begin, int ng) {
+    ChunkAt r;
+    r.g = find_group(begin, ng, blockIdx.x);
+    const int64_t local = (int64_t)blockIdx.x - begin[r.g];
+    r.vec = local / G[r.g].nchunks;
+    r.base = (local - r.vec * G[r.g].nchunks) * kChunk;
+    return r;
+}
+
+// w -= beta_{n-1} v_{n-1} (n > 0); partial <v_n, w>
+template <typename T>
+__global__ void __launch_bounds__(256) kb_sub_prev_dot(const BGroup *__restrict__ G,
+                                                       const int64_t *__restrict__ begin, int ng) {
+    __shared__ double sh[256];
+    const ChunkAt at = chunk_at(G, begin, ng);
+    const BGroup &q = G[at.g];
+    const int n = q.n;
+    const double b = n > 0 ? q.cs.beta[at.vec * q.cs.maxs + n - 1] : 0.0;
+    const int64_t off = at.vec * q.dim;
+    T *w = (T *)q.w + off;
+    const T *vp = (const T *)q.vp + off;
+    const T *v = (const T *)q.v + off;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) {
+            double x = ldd(w + i);
+            if (n > 0) {
+                x = fma(-b, ldd(vp + i), x);
+                st(w + i, x);
+                x = ldd(w + i);
+            }
+            acc = fma(ldd(v + i), x, acc);
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
+}
+
+// w -= alpha_n v_n; partial <w, w>
+template <typename T>
+__global__ void __launch_bounds__(256) kb_sub_cur_norm(const BGroup *__restrict__ G,
+                                                       const int64_t *__restrict__ begin, int ng) {
+    __shared__ double sh[256];
+    const ChunkAt at = chunk_at(G, begin, ng);
+    const BGroup &q = G[at.g];
+    const double a = q.cs.alpha[at.vec * q.cs.maxs + q.n];
+    const int64_t off = at.vec * q.dim;
+    T *w = (T *)q.w + off;
+    const T *v = (const T *)q.v + off;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) {
+            double x = fma(-a, ldd(v + i), ldd(w + i));
+            st(w + i, x);
+            x = ldd(w + i);
+            acc = fma(x, x, acc);
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
+}
+
+// partial <x, w> with x = v_n (which 0), v_{n-1} (1) or w (2)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_dot(const BGroup *__restrict__ G,
+                                              const int64_t *__restrict__ begin, int ng,
+                                              int which) {
+    __shared__ double sh[256];
+    const ChunkAt at = chunk_at(G, begin, ng);
+    const BGroup &q = G[at.g];
+    const int64_t off = at.vec * q.dim;
+    const T *w = (const T *)q.w + off;
+    const T *x = which == 0 ? (const T *)q.v + off : which == 1 ? (const T *)q.vp + off : w;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) acc = fma(ldd(x + i), ldd(w + i), acc);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
+}
+
+// w -= corr v_n + corr2 v_{n-1}
+template <typename T>
+__global__ void __launch_bounds__(256) kb_reorth(const BGroup *__restrict__ G,
+                                                 const int64_t *__restrict__ begin, int ng) {
+    const ChunkAt at = chunk_at(G, begin, ng);
+    const BGroup &q = G[at.g];
+    const double c1 = q.cs.corr[at.vec], c2 = q.cs.corr2[at.vec];
+    const int64_t off = at.vec * q.dim;
+    T *w = (T *)q.w + off;
+    const T *v = (const T *)q.v + off;
+    const T *vp = (const T *)q.vp + off;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) {
+            double x = ldd(w + i);
+            x = fma(-c1, ldd(v + i), x);
+            x = fma(-c2, ldd(vp + i), x);
+            st(w + i, x);
+        }
+    }
+}
+
+// w *= 1/beta_n (0 once the chain has stopped)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_scale(const BGroup *__restrict__ G,
+                                                const int64_t *__restrict__ begin, int ng) {
+    const ChunkAt at = chunk_at(G, begin, ng);
+    const BGroup &q = G[at.g];
+    const double s = q.cs.inv[at.vec];
+    T *w = (T *)q.w + at.vec * q.dim;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) st(w + i, ldd(w + i) * s);
+    }
+}
+
+// Chunk sums of each chain and the recurrence bookkeeping (modes as in the
+// single-solve engine: 0 alpha, 1 beta and breakdown, 3 alpha correction,
+// 4 second correction).
+__global__ void __launch_bounds__(256) kb_finish(const BGroup *__restrict__ G,
+                                                 const int64_t *__restrict__ begin, int ng,
+                                                 int mode) {
+    __shared__ double sh[256];
+    const int g = find_group(begin, ng, blockIdx.x);
+    const BGroup &q = G[g];
+    const int c = (int)((int64_t)blockIdx.x - begin[g]);
+    const double *partial = q.partial + (int64_t)c * q.nchunks;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < q.nchunks; k += 256) acc += partial[k];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    const ChainState &cs = q.cs;
+    const int n = q.n;
+    switch (mode) {
+        case 0: {
+            cs.alpha[(int64_t)c * cs.maxs + n] = s;
+            double a = fabs(s);
+            if (a > cs.amax[c]) cs.amax[c] = a;
+            break;
+        }
+        case 1: {
+            double b = sqrt(s);
+            cs.beta[(int64_t)c * cs.maxs + n] = b;
+            if (!cs.done[c]) {
+                double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
+                if (!(b >= cs.btol * am)) cs.done[c] = 1;
+                cs.len[c] = n + 1;
+            }
+            cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
+            break;
+        }
+        case 3:
+            cs.alpha[(int64_t)c * cs.maxs + n] += s;
+            cs.corr[c] = s;
+            break;
+        case 4:
+            cs.corr2[c] = s;
+            break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_accum(const BAcc *__restrict__ A,
+                                                const int64_t *__restrict__ begin, int na) {
+    const int g = find_group(begin, na, blockIdx.x);
+    const BAcc &q = A[g];
+    const double s = q.svec[q.n];
+    const int64_t base = ((int64_t)blockIdx.x - begin[g]) * kChunk;
+    const T *v = (const T *)q.v;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = base + k;
+        if (i < q.dim) q.psi[i] = fma(s, ldd(v + i), q.psi[i]);
+    }
+}
+
+__global__ void __launch_bounds__(256) kb_control(const BCtl *__restrict__ C,
+                                                  BStat *__restrict__ out) {
+    const BCtl &c = C[blockIdx.x];
+    if (c.test) tridiag_status_block(c.alpha, c.beta, c.m, c.tol, c.work, c.svec, c.status);
+    if (threadIdx.x == 0) {
+        BStat r;
+        r.gs = *c.status;
+        int all = 1;
+        for (int k = 0; k < c.n0; ++k) all &= c.done0[k] != 0;
+        for (int k = 0; k < c.n1; ++k) all &= c.done1[k] != 0;
+        r.all_done = all;
+        r.len0 = c.len0 ? *c.len0 : 0;
+        r.pad[0] = r.pad[1] = 0;
+        out[blockIdx.x] = r;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+enum { PH_GS1 = 0, PH_GS2 = 1, PH_GF = 2 };
+
+struct Part {
+    int valid = 0;
+    SpinTables up{};
+    HopTables hu{};
+    Engine e{};
+    int32_t rows = 1, nblk = 0;
+};
+
+struct Job {
+    qcm_job d{};
+    std::vector<double> t, U;
+    std::vector<int32_t> orbs, ops, pidx;
+    int npairs = 0;
+    size_t off = 0, bytes = 0;
+    int phase = PH_GS1, n = 0, M = 0, conv = 0, brk = 0;
+    int64_t round0 = 0;
+    ModelDev md{};
+    SpinTables dn{};
+    HopTables hd{};
+    Part gs, gf[2];
+    double *psi = nullptr, *svec = nullptr, *work = nullptr, *dscal = nullptr;
+    GsStatus *status = nullptr;
+    double *coef = nullptr, *F = nullptr, *G = nullptr;
+    int32_t *len = nullptr, *ops_d = nullptr, *pidx_d = nullptr;
+    BStat last{};
+    // host copies taken at the end
+    GsStatus fin_gs{};
+    double fin_r2 = 0.0;
+};
+
+}  // namespace qcm
+
+using namespace qcm;
+
+struct qcm_engine {
+    qcm_engine_opts o{};
+    std::vector<double> z;
+    char *pool = nullptr;
+    size_t pool_bytes = 0, hdr = 0;
+    hipStream_t s = nullptr;
+    std::map<size_t, size_t> free_;  // offset -> bytes
+    size_t in_use = 0, peak = 0;
+    int64_t rounds = 0;
+    std::vector<Job *> active;
+    std::deque<qcm_job_result> finished;
+    // round tables: pinned host copy and its device image at the pool start
+    char *h_tab = nullptr, *d_tab = nullptr;
+    size_t tab_bytes = 0;
+    BStat *h_stat = nullptr, *d_stat = nullptr;
+    double *d_z = nullptr;
+    int max_groups = 0;
+};
+
+namespace qcm {
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static int check_engine_opts(const qcm_engine_opts *o) {
+    if (!o) return fail(QCM_EARG, "engine options are NULL");
+    if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
+        return fail(QCM_EARG, "engine: bad prec %d", o->prec);
+    if (o->max_iter < 1 && o->gs_fixed_steps < 1)
+        return fail(QCM_EARG, "engine: max_iter and gs_fixed_steps both < 1");
+    if (o->gf_steps < 1) return fail(QCM_EARG, "engine: gf_steps < 1");
+    if (o->max_jobs < 1 || o->max_jobs > 65536)
+        return fail(QCM_EARG, "engine: max_jobs %d outside 1..65536", o->max_jobs);
+    if (o->n_z < 0 || (o->n_z > 0 && !o->h_z)) return fail(QCM_EARG, "engine: bad frequency grid");
+    return QCM_OK;
+}
+
+static int gs_limit(const qcm_engine_opts &o) {
+    return o.gs_fixed_steps > 0 ? o.gs_fixed_steps : o.max_iter;
+}
+
+// table layout inside h_tab / d_tab
+struct TabLayout {
+    size_t groups, accs, hvb, chb, cnb, acb, ctl, bytes;
+};
+static TabLayout tab_layout(int max_jobs) {
+    TabLayout t;
+    const int mg = 2 * max_jobs;
+    Carver cv(nullptr);
+    t.groups = (cv.take<BGroup>(mg), cv.off - sizeof(BGroup) * mg);
+    t.accs = (cv.take<BAcc>(max_jobs), cv.off - sizeof(BAcc) * max_jobs);
+    t.hvb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
+    t.chb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
+    t.cnb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
+    t.acb = (cv.take<int64_t>(max_jobs + 1), cv.off - sizeof(int64_t) * (max_jobs + 1));
+    t.ctl = (cv.take<BCtl>(max_jobs), cv.off - sizeof(BCtl) * max_jobs);
+    t.bytes = round_up(cv.off, 256);
+    return t;
+}
+
+static size_t header_bytes(const qcm_engine_opts &o) {
+    TabLayout t = tab_layout(o.max_jobs);
+    return t.bytes + round_up(sizeof(BStat) * o.max_jobs, 256) +
+           round_up(sizeof(double) * 2 * (o.n_z > 0 ? o.n_z : 1), 256);
+}
+
+static int check_job(const qcm_engine_opts &o, const qcm_job *j) {
+    if (!j) return fail(QCM_EARG, "job is NULL");
+    QCM_TRY(validate_model(&j->model));
+    const int L = j->model.L;
+    QCM_TRY(check_sector_args(L, j->n_up, j->n_dn));
+    if (j->n_orb < 0 || j->n_orb > L || (j->n_orb > 0 && !j->orbs))
+        return fail(QCM_EARG, "job: bad orbital list");
+    for (int i = 0; i < j->n_orb; ++i) {
+        if (j->orbs[i] < 0 || j->orbs[i] >= L)
+            return fail(QCM_EARG, "job: orbital %d out of range", j->orbs[i]);
+        for (int k = 0; k < i; ++k)
+            if (j->orbs[k] == j->orbs[i]) return fail(QCM_EARG, "job: repeated orbital");
+    }
+    int nups[3] = {j->n_up, j->n_orb > 0 ? j->n_up + 1 : -1, j->n_orb > 0 ? j->n_up - 1 : -1};
+    for (int k = 0; k < 3; ++k) {
+        if (nups[k] < 0 || nups[k] > L) continue;
+        if (binom(L, nups[k]) > kMaxRow)
+            return fail(QCM_ERANGE,
+                        "job: up-spin sector of %lld strings exceeds the engine's row limit %lld "
+                        "(use the single-solve calls)",
+                        (long long)binom(L, nups[k]), (long long)kMaxRow);
+    }
+    (void)o;
+    return QCM_OK;
+}
+
+static void part_shape(Part &p, int64_t d_up, int64_t d_dn) {
+    int64_t r = kBlockElems / d_up;
+    if (r < 1) r = 1;
+    if (r > d_dn) r = d_dn;
+    p.rows = (int32_t)r;
+    p.nblk = (int32_t)ceil_div(d_dn, r);
+}
+
+static HvOp part_op(const Job &j, const Part &p) {
+    HvOp op;
+    op.md = j.md;
+    op.up = p.up;
+    op.dn = j.dn;
+    op.hu = p.hu;
+    op.hd = j.hd;
+    op.dim = p.up.d * j.dn.d;
+    op.split = 0;
+    return op;
+}
+
+// Lays the job out from cv (sizes only when cv.base is NULL) and, when
+// building, enqueues the table construction.
+static int job_layout(const qcm_engine_opts &o, Job &j, Carver &cv, hipStream_t s) {
+    const qcm_model *m = &j.d.model;
+    const int L = m->L;
+    const int nb = count_bonds(m);
+    const int prec = o.prec;
+    QCM_TRY(upload_model(m, cv, &j.md, s));
+    QCM_TRY(build_spin_tables(L, j.d.n_dn, cv, &j.dn, s));
+    QCM_TRY(build_hop_tables(j.md, j.dn, cv, &j.hd, s, nb));
+    QCM_TRY(build_spin_tables(L, j.d.n_up, cv, &j.gs.up, s));
+    QCM_TRY(build_hop_tables(j.md, j.gs.up, cv, &j.gs.hu, s, nb));
+    j.gs.valid = 1;
+    part_shape(j.gs, j.gs.up.d, j.dn.d);
+    for (int p = 0; p < 2; ++p) {
+        Part &q = j.gf[p];
+        const int nup2 = p == 0 ? j.d.n_up + 1 : j.d.n_up - 1;
+        q.valid = j.npairs > 0 && nup2 >= 0 && nup2 <= L;
+        if (!q.valid) continue;
+        QCM_TRY(build_spin_tables(L, nup2, cv, &q.up, s));
+        QCM_TRY(build_hop_tables(j.md, q.up, cv, &q.hu, s, nb));
+        part_shape(q, q.up.d, j.dn.d);
+    }
+    const int64_t dim = j.gs.up.d * j.dn.d;
+    const int lim = gs_limit(o);
+    j.psi = cv.take<double>(dim);
+    j.svec = cv.take<double>(lim);
+    j.work = cv.take<double>((size_t)lim * 5);
+    j.status = cv.take<GsStatus>(1);
+    j.dscal = cv.take<double>(64);
+    const int n = j.d.n_orb;
+    const int stride = 1 + 2 * o.gf_steps;
+    const int nz = o.n_z > 0 ? o.n_z : 1;
+    if (j.npairs > 0) {
+        j.coef = cv.take<double>((size_t)j.npairs * 2 * stride);
+        j.len = cv.take<int32_t>((size_t)j.npairs * 2);
+        j.ops_d = cv.take<int32_t>((size_t)j.npairs * 2);
+        j.pidx_d = cv.take<int32_t>((size_t)n * n);
+        j.F = cv.take<double>(2 * (size_t)nz * j.npairs);
+        j.G = cv.take<double>(2 * (size_t)nz * n * n);
+    }
+    // vectors and chain state: the ground-state chain and the Green-function
+    // chains never live at the same time and share one area
+    const size_t area = cv.off;
+    Carver c1(cv.base);
+    c1.off = area;
+    QCM_TRY(engine_init(j.gs.e, part_op(j, j.gs), prec, 1, lim, o.btol, o.reorth, c1));
+    size_t end = c1.off;
+    Carver c2(cv.base);
+    c2.off = area;
+    for (int p = 0; p < 2; ++p)
+        if (j.gf[p].valid)
+            QCM_TRY(engine_init(j.gf[p].e, part_op(j, j.gf[p]), prec, j.npairs, o.gf_steps,
+                                o.btol, o.reorth, c2));
+    cv.off = std::max(end, c2.off);
+    if (cv.base && j.npairs > 0) {
+        QCM_HIP(hipMemcpyAsync(j.ops_d, j.ops.data(), sizeof(int32_t) * j.ops.size(),
+                               hipMemcpyHostToDevice, s));
+        QCM_HIP(hipMemcpyAsync(j.pidx_d, j.pidx.data(), sizeof(int32_t) * j.pidx.size(),
+                               hipMemcpyHostToDevice, s));
+    }
+    return QCM_OK;
+}
+
+static Job *make_job(const qcm_job *src) {
+    Job *j = new Job();
+    j->d = *src;
+    const int L = src->model.L;
+    j->t.assign(src->model.t, src->model.t + (size_t)L * L);
+    j->U.assign(src->model.U, src->model.U + L);
+    j->d.model.t = j->t.data();
+    j->d.model.U = j->U.data();
+    const int n = src->n_orb;
+    j->orbs.assign(src->orbs, src->orbs + n);
+    j->d.orbs = j->orbs.data();
+    j->npairs = n * (n + 1) / 2;
+    j->ops.assign(2 * (size_t)j->npairs, -1);
+    j->pidx.assign((size_t)n * n, 0);
+    int p = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            j->ops[2 * p] = j->orbs[a];
+            j->ops[2 * p + 1] = a == b ? -1 : j->orbs[b];
+            j->pidx[a * n + b] = p;
+            j->pidx[b * n + a] = p;
+            ++p;
+        }
+    return j;
+}
+
+static size_t job_bytes_of(const qcm_engine_opts &o, Job &j) {
+    Carver cv(nullptr);
+    job_layout(o, j, cv, nullptr);
+    return round_up(cv.off, 256) + 256;
+}
+
+// ---------------------------------------------------------------- pool
+
+static bool pool_alloc(qcm_engine *E, size_t bytes, size_t *off) {
+    for (auto it = E->free_.begin(); it != E->free_.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            size_t rest = it->second - bytes;
+            size_t at = it->first + bytes;
+            E->free_.erase(it);
+            if (rest > 0) E->free_[at] = rest;
+            E->in_use += bytes;
+            E->peak = std::max(E->peak, E->in_use);
+            return true;
+        }
+    }
+    return false;
+}
+
+static void pool_free(qcm_engine *E, size_t off, size_t bytes) {
+    E->in_use -= bytes;
+    auto it = E->free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != E->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        E->free_.erase(nx);
+    }
+    if (it != E->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            E->free_.erase(it);
+        }
+    }
+}
+
+static size_t pool_largest(const qcm_engine *E) {
+    size_t m = 0;
+    for (auto &kv : E->free_) m = std::max(m, kv.second);
+    return m;
+}
+
+// ---------------------------------------------------------------- phases
+
+static int start_gs(qcm_engine *E, Job &j, int pass) {
+    hipStream_t s = E->s;
+    if (pass == 1) QCM_HIP(hipMemsetAsync(j.psi, 0, sizeof(double) * j.gs.e.dim, s));
+    QCM_TRY(engine_reset(j.gs.e, s));
+    QCM_TRY(engine_seed(j.gs.e, j.d.seed, nullptr, s));
+    QCM_TRY(engine_normalize(j.gs.e, s));
+    j.phase = pass == 0 ? PH_GS1 : PH_GS2;
+    j.n = 0;
+    return QCM_OK;
+}
+
+static int start_gf(qcm_engine *E, Job &j) {
+    hipStream_t s = E->s;
+    for (int p = 0; p < 2; ++p) {
+        Part &q = j.gf[p];
+        if (!q.valid) continue;
+        QCM_TRY(engine_reset(q.e, s));
+        QCM_TRY(apply_ops_launch(q.e, j.psi, j.gs.up.d, j.gs.up, q.up, p, j.ops_d, s));
+        QCM_TRY(engine_normalize_from_partials(q.e, s));
+    }
+    j.phase = PH_GF;
+    j.n = 0;
+    return QCM_OK;
+}
+
+// end of the ground-state replay: psi normalised, its true residual
+static int finish_gs(qcm_engine *E, Job &j) {
+    QCM_TRY(psi_finalize(j.gs.e, j.psi, E->s));
+    double *w64 = (double *)j.gs.e.vbuf[0];
+    QCM_TRY(residual_norm(part_op(j, j.gs), j.psi, j.last.gs.theta0, w64, j.gs.e.partial,
+                          j.dscal, E->s));
+    return QCM_OK;
+}
+
+// enqueue the end of a job: coefficients, G on the grid, copies to the host
+static int finish_job(qcm_engine *E, Job &j) {
+    hipStream_t s = E->s;
+    const int stride = 1 + 2 * E->o.gf_steps;
+    if (j.npairs > 0) {
+        for (int p = 0; p < 2; ++p)
+            QCM_TRY(green_store(j.gf[p].valid ? &j.gf[p].e : nullptr, j.npairs, p, j.coef, j.len,
+                                stride, s));
+        QCM_TRY(green_eval(j.coef, j.len, j.d.n_orb, E->o.gf_steps, E->o.n_z, E->d_z,
+                           j.last.gs.theta0, j.pidx_d, j.F, j.G, s));
+        const int n = j.d.n_orb;
+        if (j.d.h_G && E->o.n_z > 0)
+            QCM_HIP(hipMemcpyAsync(j.d.h_G, j.G, sizeof(double) * 2 * E->o.n_z * n * n,
+                                   hipMemcpyDeviceToHost, s));
+        if (j.d.h_coef)
+            QCM_HIP(hipMemcpyAsync(j.d.h_coef, j.coef, sizeof(double) * j.npairs * 2 * stride,
+                                   hipMemcpyDeviceToHost, s));
+        if (j.d.h_len)
+            QCM_HIP(hipMemcpyAsync(j.d.h_len, j.len, sizeof(int32_t) * j.npairs * 2,
+                                   hipMemcpyDeviceToHost, s));
+    }
+    if (j.d.d_psi)
+        QCM_HIP(hipMemcpyAsync(j.d.d_psi, j.psi, sizeof(double) * j.gs.e.dim,
+                               hipMemcpyDeviceToDevice, s));
+    QCM_HIP(hipMemcpyAsync(&j.fin_gs, j.status, sizeof(GsStatus), hipMemcpyDeviceToHost, s));
+    QCM_HIP(hipMemcpyAsync(&j.fin_r2, j.dscal, sizeof(double), hipMemcpyDeviceToHost, s));
+    return QCM_OK;
+}
+
+static void rotate(Engine &e) {
+    int t = e.ivp;
+    e.ivp = e.iv;
+    e.iv = e.iw;
+    e.iw = t;
+}
+
+static void fill_group(BGroup &g, const Job &j, const Part &p, int n) {
+    const Engine &e = p.e;
+    g.d_up = p.up.d;
+    g.d_dn = j.dn.d;
+    g.dim = e.dim;
+    g.su = p.up.states;
+    g.sd = j.dn.states;
+    g.eu = p.hu.ediag;
+    g.ed = j.hd.ediag;
+    g.nhu = p.hu.nh;
+    g.nhd = j.hd.nh;
+    g.colu = p.hu.col;
+    g.cold = j.hd.col;
+    g.cfu = p.hu.coef;
+    g.cfd = j.hd.coef;
+    g.ulut = j.md.ulut;
+    g.u_uniform = j.md.u_uniform;
+    g.nbytes = j.md.nbytes;
+    g.rows = p.rows;
+    g.nblk = p.nblk;
+    g.nvec = e.nvec;
+    g.nchunks = e.nchunks;
+    g.n = n;
+    g.vp = e.vbuf[e.ivp];
+    g.v = e.vbuf[e.iv];
+    g.w = e.vbuf[e.iw];
+    g.partial = e.partial;
+    g.cs = e.cs;
+}
+
+template <typename T>
+static int launch_round(qcm_engine *E, int ng, int na, int nc, size_t lds, const TabLayout &tl,
+                        const int64_t *hvb, const int64_t *chb, const int64_t *cnb,
+                        const int64_t *acb) {
+    hipStream_t s = E->s;
+    const BGroup *G = (const BGroup *)(E->d_tab + tl.groups);
+    const BAcc *A = (const BAcc *)(E->d_tab + tl.accs);
+    const int64_t *dhv = (const int64_t *)(E->d_tab + tl.hvb);
+    const int64_t *dch = (const int64_t *)(E->d_tab + tl.chb);
+    const int64_t *dcn = (const int64_t *)(E->d_tab + tl.cnb);
+    const int64_t *dac = (const int64_t *)(E->d_tab + tl.acb);
+    const BCtl *C = (const BCtl *)(E->d_tab + tl.ctl);
+    if (na > 0 && acb[na] > 0) kb_accum<T><<<(unsigned)acb[na], 256, 0, s>>>(A, dac, na);
+    if (ng > 0) {
+        const unsigned nh = (unsigned)hvb[ng], nk = (unsigned)chb[ng], nn = (unsigned)cnb[ng];
+        kb_hv<T><<<nh, 256, lds, s>>>(G, dhv, ng);
+        kb_sub_prev_dot<T><<<nk, 256, 0, s>>>(G, dch, ng);
+        kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 0);
+        kb_sub_cur_norm<T><<<nk, 256, 0, s>>>(G, dch, ng);
+        if (E->o.reorth) {
+            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 0);
+            kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 3);
+            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 1);
+            kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 4);
+            kb_reorth<T><<<nk, 256, 0, s>>>(G, dch, ng);
+            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 2);
+        }
+        kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 1);
+        kb_scale<T><<<nk, 256, 0, s>>>(G, dch, ng);
+    }
+    if (nc > 0) kb_control<<<nc, 256, 0, s>>>(C, E->d_stat);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+static int complete(qcm_engine *E, Job &j) {
+    qcm_job_result r{};
+    r.tag = j.d.tag;
+    r.e0 = j.fin_gs.theta0;
+    r.theta1 = j.fin_gs.theta1;
+    r.residual_est = j.fin_gs.est;
+    r.true_residual = sqrt(j.fin_r2);
+    r.n_iter = j.M;
+    r.converged = j.conv;
+    r.breakdown = j.brk;
+    r.status = QCM_OK;
+    r.bytes = (int64_t)j.bytes;
+    r.rounds = (int32_t)(E->rounds - j.round0);
+    E->finished.push_back(r);
+    pool_free(E, j.off, j.bytes);
+    return QCM_OK;
+}
+
+// One round: every active job advances one step of its phase.
+static int run_round(qcm_engine *E) {
+    const qcm_engine_opts &o = E->o;
+    const TabLayout tl = tab_layout(o.max_jobs);
+    BGroup *G = (BGroup *)(E->h_tab + tl.groups);
+    BAcc *A = (BAcc *)(E->h_tab + tl.accs);
+    int64_t *hvb = (int64_t *)(E->h_tab + tl.hvb);
+    int64_t *chb = (int64_t *)(E->h_tab + tl.chb);
+    int64_t *cnb = (int64_t *)(E->h_tab + tl.cnb);
+    int64_t *acb = (int64_t *)(E->h_tab + tl.acb);
+    BCtl *C = (BCtl *)(E->h_tab + tl.ctl);
+    const size_t s = o.prec == QCM_FP64 ? 8 : 4;
+    const int lim = gs_limit(o);
+    int ng = 0, na = 0, nc = 0;
+    size_t lds = 0;
+    hvb[0] = chb[0] = cnb[0] = acb[0] = 0;
+    auto add_group = [&](const Job &j, const Part &p) {
+        fill_group(G[ng], j, p, j.n);
+        const size_t lut = j.md.u_uniform >= 0.0 ? 0 : sizeof(double) * 256 * j.md.nbytes;
+        lds = std::max(lds, lut + s * (size_t)p.rows * (size_t)p.up.d);
+        hvb[ng + 1] = hvb[ng] + (int64_t)p.e.nvec * p.nblk;
+        chb[ng + 1] = chb[ng] + (int64_t)p.e.nvec * p.e.nchunks;
+        cnb[ng + 1] = cnb[ng] + p.e.nvec;
+        ++ng;
+    };
+    for (Job *jp : E->active) {
+        Job &j = *jp;
+        BCtl &c = C[nc++];
+        memset(&c, 0, sizeof c);
+        c.status = j.status;
+        c.tol = o.tol;
+        if (j.phase == PH_GS1) {
+            add_group(j, j.gs);
+            c.test = (o.gs_fixed_steps <= 0) ? 1 : 0;
+            c.m = j.n + 1;
+            c.alpha = j.gs.e.cs.alpha;
+            c.beta = j.gs.e.cs.beta;
+            c.work = j.work;
+            c.svec = j.svec;
+            c.done0 = j.gs.e.cs.done;
+            c.n0 = 1;
+            c.len0 = j.gs.e.cs.len;
+        } else if (j.phase == PH_GS2) {
+            BAcc &a = A[na];
+            a.v = j.gs.e.vbuf[j.gs.e.iv];
+            a.psi = j.psi;
+            a.svec = j.svec;
+            a.dim = j.gs.e.dim;
+            a.nchunks = j.gs.e.nchunks;
+            a.n = j.n;
+            acb[na + 1] = acb[na] + j.gs.e.nchunks;
+            ++na;
+            if (j.n + 1 < j.M) add_group(j, j.gs);
+        } else {
+            for (int p = 0; p < 2; ++p)
+                if (j.gf[p].valid) add_group(j, j.gf[p]);
+            if (j.gf[0].valid) {
+                c.done0 = j.gf[0].e.cs.done;
+                c.n0 = j.npairs;
+            }
+            if (j.gf[1].valid) {
+                c.done1 = j.gf[1].e.cs.done;
+                c.n1 = j.npairs;
+            }
+        }
+    }
+    QCM_HIP(hipMemcpyAsync(E->d_tab, E->h_tab, tl.bytes, hipMemcpyHostToDevice, E->s));
+    if (o.prec == QCM_FP64)
+        QCM_TRY(launch_round<double>(E, ng, na, nc, lds, tl, hvb, chb, cnb, acb));
+    else
+        QCM_TRY(launch_round<float>(E, ng, na, nc, lds, tl, hvb, chb, cnb, acb));
+    QCM_HIP(hipMemcpyAsync(E->h_stat, E->d_stat, sizeof(BStat) * nc, hipMemcpyDeviceToHost, E->s));
+    QCM_HIP(hipStreamSynchronize(E->s));
+    ++E->rounds;
+
+    // transitions, in the order of the single-solve calls
+    std::vector<Job *> ending;
+    std::vector<Job *> still;
+    int k = 0;
+    for (Job *jp : E->active) {
+        Job &j = *jp;
+        j.last = E->h_stat[k++];
+        bool ends = false;
+        if (j.phase == PH_GS1) {
+            rotate(j.gs.e);
+            const bool last = j.n + 1 == lim;
+            bool stop = false;
+            if (j.last.all_done) {
+                j.brk = 1;
+                j.conv = 1;
+                j.M = j.last.len0;
+                stop = true;
+            } else if (o.gs_fixed_steps <= 0 && j.last.gs.converged) {
+                j.conv = 1;
+                j.M = j.n + 1;
+                stop = true;
+            } else if (last) {
+                j.M = lim;
+                j.conv = o.gs_fixed_steps <= 0 ? j.last.gs.converged : 0;
+                stop = true;
+            }
+            if (stop) {
+                QCM_TRY(tridiag_status(j.gs.e.cs.alpha, j.gs.e.cs.beta, j.M, o.tol, j.work,
+                                       j.svec, j.status, E->s));
+                QCM_TRY(start_gs(E, j, 1));
+            } else {
+                ++j.n;
+            }
+        } else if (j.phase == PH_GS2) {
+            if (j.n + 1 < j.M) rotate(j.gs.e);
+            ++j.n;
+            if (j.n == j.M) {
+                QCM_TRY(finish_gs(E, j));
+                if (j.npairs > 0)
+                    QCM_TRY(start_gf(E, j));
+                else
+                    ends = true;
+            }
+        } else {
+            for (int p = 0; p < 2; ++p)
+                if (j.gf[p].valid) rotate(j.gf[p].e);
+            ++j.n;
+            if (j.n == o.gf_steps || j.last.all_done) ends = true;
+        }
+        if (ends) {
+            QCM_TRY(finish_job(E, j));
+            ending.push_back(jp);
+        } else {
+            still.push_back(jp);
+        }
+    }
+    if (!ending.empty()) {
+        QCM_HIP(hipStreamSynchronize(E->s));
+        for (Job *jp : ending) {
+            QCM_TRY(complete(E, *jp));
+            delete jp;
+        }
+    }
+    E->active.swap(still);
+    return QCM_OK;
+}
+
+}  // namespace qcm
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" int qcm_engine_default_opts(qcm_engine_opts *o) {
+    if (!o) return fail(QCM_EARG, "qcm_engine_default_opts: NULL");
+    memset(o, 0, sizeof *o);
+    o->prec = QCM_FP32V;
+    o->reorth = 1;
+    o->max_iter = 600;
+    o->gs_fixed_steps = 0;
+    o->gf_steps = 100;
+    o->tol = 0.0;
+    o->btol = 1e-13;
+    o->max_jobs = 256;
+    o->n_z = 0;
+    o->h_z = nullptr;
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_create(const qcm_engine_opts *o, void *d_pool, size_t pool_bytes,
+                                 void *stream, qcm_engine **out) {
+    if (!out) return fail(QCM_EARG, "qcm_engine_create: out is NULL");
+    *out = nullptr;
+    QCM_TRY(check_engine_opts(o));
+    if (!d_pool) return fail(QCM_EARG, "qcm_engine_create: pool is NULL");
+    if (((uintptr_t)d_pool) % 256 != 0)
+        return fail(QCM_EARG, "qcm_engine_create: pool is not 256-byte aligned");
+    const size_t hdr = header_bytes(*o);
+    if (pool_bytes < hdr + 256)
+        return fail(QCM_EWORKSPACE, "qcm_engine_create: pool %zu < %zu bytes", pool_bytes,
+                    hdr + 256);
+    qcm_engine *E = new qcm_engine();
+    E->o = *o;
+    if (!(E->o.tol > 0.0)) E->o.tol = o->prec == QCM_FP64 ? 1e-12 : 1e-7;
+    if (o->n_z > 0) E->z.assign(o->h_z, o->h_z + 2 * (size_t)o->n_z);
+    E->o.h_z = E->z.data();
+    E->pool = (char *)d_pool;
+    E->pool_bytes = pool_bytes;
+    E->s = as_stream(stream);
+    const TabLayout tl = tab_layout(o->max_jobs);
+    E->tab_bytes = tl.bytes;
+    E->d_tab = E->pool;
+    E->d_stat = (BStat *)(E->pool + tl.bytes);
+    E->d_z = (double *)(E->pool + tl.bytes + round_up(sizeof(BStat) * o->max_jobs, 256));
+    E->hdr = hdr;
+    const size_t usable = (pool_bytes - hdr) / 256 * 256;
+    E->free_[hdr] = usable;
+    hipError_t e1 = hipHostMalloc((void **)&E->h_tab, tl.bytes, hipHostMallocDefault);
+    hipError_t e2 = e1 == hipSuccess ? hipHostMalloc((void **)&E->h_stat,
+                                                     sizeof(BStat) * o->max_jobs,
+                                                     hipHostMallocDefault)
+                                     : e1;
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (E->h_tab) (void)hipHostFree(E->h_tab);
+        delete E;
+        return fail(QCM_EHIP, "qcm_engine_create: pinned host allocation failed: %s",
+                    hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    memset(E->h_tab, 0, tl.bytes);
+    if (o->n_z > 0) {
+        hipError_t e3 = hipMemcpyAsync(E->d_z, E->z.data(), sizeof(double) * 2 * o->n_z,
+                                       hipMemcpyHostToDevice, E->s);
+        if (e3 != hipSuccess) {
+            (void)hipHostFree(E->h_tab);
+            (void)hipHostFree(E->h_stat);
+            delete E;
+            return fail(QCM_EHIP, "qcm_engine_create: %s", hipGetErrorString(e3));
+        }
+    }
+    *out = E;
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_destroy(qcm_engine *E) {
+    if (!E) return QCM_OK;
+    hipError_t e = hipStreamSynchronize(E->s);
+    for (Job *j : E->active) delete j;
+    if (E->h_tab) (void)hipHostFree(E->h_tab);
+    if (E->h_stat) (void)hipHostFree(E->h_stat);
+    delete E;
+    if (e != hipSuccess) return fail(QCM_EHIP, "qcm_engine_destroy: %s", hipGetErrorString(e));
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_job_bytes(const qcm_engine_opts *o, const qcm_job *j, size_t *bytes) {
+    if (!bytes) return fail(QCM_EARG, "qcm_engine_job_bytes: bytes is NULL");
+    QCM_TRY(check_engine_opts(o));
+    QCM_TRY(check_job(*o, j));
+    Job *x = make_job(j);
+    *bytes = job_bytes_of(*o, *x);
+    delete x;
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_submit(qcm_engine *E, const qcm_job *j) {
+    if (!E) return fail(QCM_EARG, "qcm_engine_submit: engine is NULL");
+    QCM_TRY(check_job(E->o, j));
+    if ((int)E->active.size() >= E->o.max_jobs)
+        return fail(QCM_EWORKSPACE, "qcm_engine_submit: all %d slots busy", E->o.max_jobs);
+    Job *x = make_job(j);
+    const size_t bytes = job_bytes_of(E->o, *x);
+    size_t off = 0;
+    if (!pool_alloc(E, bytes, &off)) {
+        delete x;
+        return fail(QCM_EWORKSPACE, "qcm_engine_submit: job needs %zu bytes, largest free block %zu",
+                    bytes, pool_largest(E));
+    }
+    x->off = off;
+    x->bytes = bytes;
+    x->round0 = E->rounds;
+    Carver cv(E->pool + off);
+    int rc = job_layout(E->o, *x, cv, E->s);
+    if (rc == QCM_OK) {
+        hipError_t e = hipMemsetAsync(x->status, 0, sizeof(GsStatus), E->s);
+        if (e != hipSuccess) rc = fail(QCM_EHIP, "qcm_engine_submit: %s", hipGetErrorString(e));
+    }
+    if (rc == QCM_OK) rc = start_gs(E, *x, 0);
+    if (rc != QCM_OK) {
+        pool_free(E, off, bytes);
+        delete x;
+        return rc;
+    }
+    E->active.push_back(x);
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_step(qcm_engine *E, int32_t rounds, int32_t *n_active) {
+    if (!E) return fail(QCM_EARG, "qcm_engine_step: engine is NULL");
+    if (rounds < 0) return fail(QCM_EARG, "qcm_engine_step: rounds < 0");
+    for (int r = 0; r < rounds && !E->active.empty(); ++r) QCM_TRY(run_round(E));
+    if (n_active) *n_active = (int32_t)E->active.size();
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_poll(qcm_engine *E, int32_t max_out, qcm_job_result *h_res,
+                               int32_t *n_out) {
+    if (!E || !n_out || max_out < 0 || (max_out > 0 && !h_res))
+        return fail(QCM_EARG, "qcm_engine_poll: bad arguments");
+    int k = 0;
+    while (k < max_out && !E->finished.empty()) {
+        h_res[k++] = E->finished.front();
+        E->finished.pop_front();
+    }
+    *n_out = k;
+    return QCM_OK;
+}
+
+extern "C" int qcm_engine_info(const qcm_engine *E, qcm_engine_stats *out) {
+    if (!E || !out) return fail(QCM_EARG, "qcm_engine_info: bad arguments");
+    out->pool_bytes = (int64_t)E->pool_bytes;
+    out->header_bytes = (int64_t)E->hdr;
+    out->in_use = (int64_t)E->in_use;
+    out->peak_in_use = (int64_t)E->peak;
+    out->largest_free = (int64_t)pool_largest(E);
+    out->rounds = E->rounds;
+    out->active = (int32_t)E->active.size();
+    out->finished = (int32_t)E->finished.size();
+    return QCM_OK;
+}
+
+extern "C" int qcm_batch_solve(const qcm_engine_opts *o, int32_t n_jobs, const qcm_job *jobs,
+                               qcm_job_result *h_res, void *d_ws, size_t ws_bytes,
+                               size_t *ws_needed, void *stream) {
+    if (!ws_needed) return fail(QCM_EARG, "qcm_batch_solve: ws_needed is NULL");
+    QCM_TRY(check_engine_opts(o));
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(QCM_EARG, "qcm_batch_solve: bad jobs");
+    size_t sum = 0, big = 0;
+    std::vector<size_t> bytes(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        QCM_TRY(check_job(*o, &jobs[i]));
+        Job *x = make_job(&jobs[i]);
+        bytes[i] = job_bytes_of(*o, *x);
+        delete x;
+        sum += bytes[i];
+        big = std::max(big, bytes[i]);
+    }
+    const size_t hdr = header_bytes(*o) + 256;
+    *ws_needed = hdr + sum;
+    if (!d_ws) return QCM_OK;
+    if (!h_res) return fail(QCM_EARG, "qcm_batch_solve: h_res is NULL");
+    if (ws_bytes < hdr + big)
+        return fail(QCM_EWORKSPACE, "qcm_batch_solve: workspace %zu < %zu (largest job)", ws_bytes,
+                    hdr + big);
+    qcm_engine *E = nullptr;
+    QCM_TRY(qcm_engine_create(o, d_ws, ws_bytes, stream, &E));
+    int rc = QCM_OK;
+    int next = 0, got = 0;
+    std::vector<qcm_job_result> res(64);
+    while (got < n_jobs && rc == QCM_OK) {
+        // admit in order while the next job fits
+        while (next < n_jobs && (int)E->active.size() < E->o.max_jobs &&
+               pool_largest(E) >= bytes[next]) {
+            qcm_job jj = jobs[next];
+            jj.tag = next;
+            rc = qcm_engine_submit(E, &jj);
+            if (rc != QCM_OK) break;
+            ++next;
+        }
+        if (rc != QCM_OK) break;
+        if (E->active.empty()) {
+            rc = fail(QCM_EWORKSPACE, "qcm_batch_solve: job %d does not fit the workspace", next);
+            break;
+        }
+        rc = run_round(E);
+        while (rc == QCM_OK && !E->finished.empty()) {
+            qcm_job_result r = E->finished.front();
+            E->finished.pop_front();
+            const int idx = (int)r.tag;
+            r.tag = jobs[idx].tag;
+            h_res[idx] = r;
+            ++got;
+        }
+    }
+    int rc2 = qcm_engine_destroy(E);
+    return rc != QCM_OK ? rc : rc2;
+}

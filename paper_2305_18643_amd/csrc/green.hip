@@ -12,11 +12,9 @@
 #include <math.h>
 #include <string.h>
 
-#include "lanczos_engine.h"
+#include "lanczos_device.h"
 
 namespace qcm {
-
-int engine_normalize_from_partials(Engine &e, hipStream_t s);
 
 struct PairOps {
     int32_t mu[2];
@@ -95,34 +93,6 @@ __global__ void k_zero_coef(int npairs, int part, double *__restrict__ coef,
     if (threadIdx.x == 0) len[c * 2 + part] = 0;
 }
 
-struct cplx {
-    double re, im;
-};
-
-// One continued fraction at z, bottom floor first.  part 0 (electron):
-// b0sq / (z + E0 - a0 - b1^2/(z + E0 - a1 - ...)); part 1 (hole):
-// b0sq / (z - E0 + a0 - b1^2/(z - E0 + a1 - ...)).
-__device__ cplx cf_value(const double *__restrict__ co, int len, int maxs, cplx z, double e0,
-                         int part) {
-    cplx r{0.0, 0.0};
-    if (len <= 0 || co[0] == 0.0) return r;
-    const double sg = part == 0 ? 1.0 : -1.0;
-    const double zr = part == 0 ? z.re + e0 : z.re - e0;
-    const double zi = z.im;
-    const double *a = co + 1, *b2 = co + 1 + maxs;
-    double gr = zr - sg * a[len - 1], gi = zi;
-    for (int n = len - 2; n >= 0; --n) {
-        double den = gr * gr + gi * gi;
-        double qr = b2[n] * gr / den, qi = -b2[n] * gi / den;  // b2 / g
-        gr = zr - sg * a[n] - qr;
-        gi = zi - qi;
-    }
-    double den = gr * gr + gi * gi;
-    r.re = co[0] * gr / den;
-    r.im = -co[0] * gi / den;
-    return r;
-}
-
 // F[z][p] = G_e + G_h of pair p
 __global__ void k_cf_pairs(const double *__restrict__ coef, const int32_t *__restrict__ len,
                            int npairs, int maxs, int nz, const double *__restrict__ zs, double e0,
@@ -157,6 +127,50 @@ __global__ void k_cf_combine(const double *__restrict__ F, const int32_t *__rest
     }
     G[2 * e] = re;
     G[2 * e + 1] = im;
+}
+
+// Start vectors of the chains of one part into the current vectors of e,
+// with their norm partials in e.partial (kind 0: creation, 1: annihilation).
+int apply_ops_launch(Engine &e, const double *psi, int64_t d_src_up, const SpinTables &src_up,
+                     const SpinTables &tgt_up, int kind, const int32_t *ops, hipStream_t s) {
+    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
+    if (e.prec == QCM_FP64)
+        k_apply_ops<double><<<g, 256, 0, s>>>(psi, d_src_up, src_up.rank_lo, src_up.rank_hi,
+                                              src_up.l_lo, src_up.l_hi, tgt_up.states, tgt_up.d,
+                                              e.dim, kind, ops, (double *)e.vbuf[e.iv], e.nchunks,
+                                              e.partial);
+    else
+        k_apply_ops<float><<<g, 256, 0, s>>>(psi, d_src_up, src_up.rank_lo, src_up.rank_hi,
+                                             src_up.l_lo, src_up.l_hi, tgt_up.states, tgt_up.d,
+                                             e.dim, kind, ops, (float *)e.vbuf[e.iv], e.nchunks,
+                                             e.partial);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+// Coefficients of part `part` of every pair into coef/len; e == NULL (the
+// part's sector does not exist) stores empty chains.
+int green_store(const Engine *e, int npairs, int part, double *coef, int32_t *len, int stride,
+                hipStream_t s) {
+    if (e)
+        k_store_coef<<<npairs, 256, 0, s>>>(e->cs, npairs, part, coef, len, stride);
+    else
+        k_zero_coef<<<npairs, 256, 0, s>>>(npairs, part, coef, len, stride);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+// G[z][i][j] from the stored chains (F: scratch [nz][npairs] complex).
+int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, const double *zd,
+               double e0, const int32_t *pidx, double *F, double *G, hipStream_t s) {
+    const int npairs = n * (n + 1) / 2;
+    if (nz <= 0) return QCM_OK;
+    int64_t tot = (int64_t)nz * npairs;
+    k_cf_pairs<<<ceil_div(tot, 256), 256, 0, s>>>(coef, len, npairs, maxs, nz, zd, e0, F);
+    int64_t tot2 = (int64_t)nz * n * n;
+    k_cf_combine<<<ceil_div(tot2, 256), 256, 0, s>>>(F, pidx, n, npairs, nz, G);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
 }
 
 }  // namespace qcm
@@ -260,8 +274,7 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
     for (int part = 0; part < 2; ++part) {
         const int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
         if (nup2 < 0 || nup2 > L) {
-            k_zero_coef<<<npairs, 256, 0, s>>>(npairs, part, coef, lenv, stride);
-            QCM_LAUNCH_CHECK();
+            QCM_TRY(green_store(nullptr, npairs, part, coef, lenv, stride, s));
             continue;
         }
         cv.off = part_base;
@@ -279,18 +292,7 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         Engine e;
         QCM_TRY(engine_init(e, op, o->prec, npairs, maxs, o->btol, o->reorth, cv));
         QCM_TRY(engine_reset(e, s));
-        const dim3 g((unsigned)e.nchunks, (unsigned)npairs);
-        if (o->prec == QCM_FP64)
-            k_apply_ops<double><<<g, 256, 0, s>>>(d_gs, gs->d_up, upg.rank_lo, upg.rank_hi,
-                                                  upg.l_lo, upg.l_hi, up2.states, up2.d, op.dim,
-                                                  part, ops_d, (double *)e.vbuf[e.iv], e.nchunks,
-                                                  e.partial);
-        else
-            k_apply_ops<float><<<g, 256, 0, s>>>(d_gs, gs->d_up, upg.rank_lo, upg.rank_hi,
-                                                 upg.l_lo, upg.l_hi, up2.states, up2.d, op.dim,
-                                                 part, ops_d, (float *)e.vbuf[e.iv], e.nchunks,
-                                                 e.partial);
-        QCM_LAUNCH_CHECK();
+        QCM_TRY(apply_ops_launch(e, d_gs, gs->d_up, upg, up2, part, ops_d, s));
         QCM_TRY(engine_normalize_from_partials(e, s));
         std::vector<int32_t> done(npairs);
         for (int step = 0; step < maxs; ++step) {
@@ -304,16 +306,9 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
                 if (all) break;
             }
         }
-        k_store_coef<<<npairs, 256, 0, s>>>(e.cs, npairs, part, coef, lenv, stride);
-        QCM_LAUNCH_CHECK();
+        QCM_TRY(green_store(&e, npairs, part, coef, lenv, stride, s));
     }
-    if (n_z > 0) {
-        int64_t tot = (int64_t)n_z * npairs;
-        k_cf_pairs<<<ceil_div(tot, 256), 256, 0, s>>>(coef, lenv, npairs, maxs, n_z, z_d, e0, F);
-        int64_t tot2 = (int64_t)n_z * n * n;
-        k_cf_combine<<<ceil_div(tot2, 256), 256, 0, s>>>(F, pidx_d, n, npairs, n_z, d_G);
-        QCM_LAUNCH_CHECK();
-    }
+    QCM_TRY(green_eval(coef, lenv, n, maxs, n_z, z_d, e0, pidx_d, F, d_G, s));
     if (h_coef)
         QCM_HIP(hipMemcpyAsync(h_coef, coef, sizeof(double) * npairs * 2 * stride,
                                hipMemcpyDeviceToHost, s));

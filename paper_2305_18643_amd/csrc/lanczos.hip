@@ -12,30 +12,11 @@
 // inputs, never on launch shapes or on other work sharing the GPU.
 #include <math.h>
 
-#include "lanczos_engine.h"
+#include "lanczos_device.h"
 
 namespace qcm {
 
 // ---------------------------------------------------------------- reductions
-
-template <typename T>
-__device__ __forceinline__ double ldd(const T *p) {
-    return (double)*p;
-}
-
-__device__ __forceinline__ double block_sum(double x, double *sh) {
-    // 256 threads, fixed tree
-    const int t = threadIdx.x;
-    sh[t] = x;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) sh[t] += sh[t + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
 
 // partial[c][chunk] = sum over the chunk of x*y (vector c)
 template <typename TX, typename TY>
@@ -116,11 +97,6 @@ __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ parti
 }
 
 // ---------------------------------------------------------------- vector updates
-
-template <typename T>
-__device__ __forceinline__ void st(T *p, double x) {
-    *p = (T)x;
-}
 
 // w -= beta[c][n-1] * vp  (n > 0), and partial <v, w>
 template <typename T>
@@ -262,117 +238,6 @@ __global__ void __launch_bounds__(256) k_resid_partial(const double *__restrict_
 
 // ---------------------------------------------------------------- tridiagonal
 
-// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots)
-__device__ int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b,
-                           double x) {
-    int cnt = 0;
-    double q = 1.0;
-    for (int i = 0; i < M; ++i) {
-        double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
-        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
-        if (q == 0.0) q = -1e-300;
-        cnt += q < 0.0;
-    }
-    return cnt;
-}
-
-// k-th smallest eigenvalue by 256-way multisection: every thread tests one
-// point of the current bracket; 9 rounds narrow it by 257^9.
-__device__ double tridiag_kth(int M, const double *a, const double *b, int k, double *sh_lo,
-                              double *sh_hi) {
-    const int t = threadIdx.x;
-    __shared__ int cnts[256];
-    if (t == 0) {
-        double lo = a[0], hi = a[0];
-        for (int i = 0; i < M; ++i) {
-            double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < M - 1 ? fabs(b[i]) : 0.0);
-            lo = fmin(lo, a[i] - r);
-            hi = fmax(hi, a[i] + r);
-        }
-        double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
-        *sh_lo = lo - pad;
-        *sh_hi = hi + pad;
-    }
-    __syncthreads();
-    for (int round = 0; round < 10; ++round) {
-        double lo = *sh_lo, hi = *sh_hi;
-        double x = lo + (hi - lo) * (double)(t + 1) / 257.0;
-        cnts[t] = sturm_below(M, a, b, x);
-        __syncthreads();
-        if (t == 0) {
-            // first point with more than k eigenvalues below it
-            int j = 256;
-            for (int q = 0; q < 256; ++q)
-                if (cnts[q] > k) {
-                    j = q;
-                    break;
-                }
-            double nlo = j == 0 ? lo : lo + (hi - lo) * (double)j / 257.0;
-            double nhi = j == 256 ? hi : lo + (hi - lo) * (double)(j + 1) / 257.0;
-            *sh_lo = nlo;
-            *sh_hi = nhi;
-        }
-        __syncthreads();
-    }
-    double r = 0.5 * (*sh_lo + *sh_hi);
-    __syncthreads();
-    return r;
-}
-
-// Eigenvector for theta by inverse iteration; Gaussian elimination with
-// row pivoting on the tridiagonal (T - theta).  One thread.
-__device__ void tridiag_vector(int M, const double *a, const double *b, double theta, double *x,
-                               double *d, double *du, double *du2, double *dl, double *y) {
-    double scale = 1.0;
-    for (int i = 0; i < M; ++i) scale = fmax(scale, fabs(a[i]));
-    const double tiny = 1e-15 * scale;
-    for (int i = 0; i < M; ++i) x[i] = 1.0;
-    for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i < M; ++i) {
-            d[i] = a[i] - theta;
-            du[i] = i < M - 1 ? b[i] : 0.0;
-            dl[i] = i < M - 1 ? b[i] : 0.0;
-            du2[i] = 0.0;
-            y[i] = x[i];
-        }
-        for (int i = 0; i < M - 1; ++i) {
-            if (fabs(dl[i]) > fabs(d[i])) {
-                double t0 = d[i];
-                d[i] = dl[i];
-                dl[i] = t0;
-                double t1 = du[i];
-                du[i] = d[i + 1];
-                d[i + 1] = t1;
-                if (i < M - 2) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = 0.0;
-                }
-                double ty = y[i];
-                y[i] = y[i + 1];
-                y[i + 1] = ty;
-            }
-            if (d[i] == 0.0) d[i] = tiny;
-            double m = dl[i] / d[i];
-            d[i + 1] -= m * du[i];
-            if (i < M - 2) du[i + 1] -= m * du2[i];
-            y[i + 1] -= m * y[i];
-        }
-        if (d[M - 1] == 0.0) d[M - 1] = tiny;
-        for (int i = M - 1; i >= 0; --i) {
-            double s = y[i];
-            if (i + 1 < M) s -= du[i] * x[i + 1];
-            if (i + 2 < M) s -= du2[i] * x[i + 2];
-            x[i] = s / d[i];
-        }
-        double nr = 0.0;
-        for (int i = 0; i < M; ++i) nr += x[i] * x[i];
-        nr = 1.0 / sqrt(nr);
-        for (int i = 0; i < M; ++i) x[i] *= nr;
-    }
-    if (x[0] < 0.0)
-        for (int i = 0; i < M; ++i) x[i] = -x[i];
-}
-
 // Ground-state test on T_M: theta_0, theta_1, the eigenvector s of theta_0
 // (written to svec), and the residual estimate beta[M-1] |s[M-1]|.
 __global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict__ alpha,
@@ -380,19 +245,7 @@ __global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict
                                                         double tol, double *__restrict__ work,
                                                         double *__restrict__ svec,
                                                         GsStatus *__restrict__ status) {
-    __shared__ double lo, hi;
-    double th0 = tridiag_kth(M, alpha, beta, 0, &lo, &hi);
-    double th1 = M > 1 ? tridiag_kth(M, alpha, beta, 1, &lo, &hi) : NAN;
-    if (threadIdx.x == 0) {
-        tridiag_vector(M, alpha, beta, th0, svec, work, work + M, work + 2 * M, work + 3 * M,
-                       work + 4 * M);
-        double est = beta[M - 1] * fabs(svec[M - 1]);
-        status->theta0 = th0;
-        status->theta1 = th1;
-        status->est = est;
-        status->converged = est <= tol * fmax(1.0, fabs(th0)) ? 1 : 0;
-        status->M = M;
-    }
+    tridiag_status_block(alpha, beta, M, tol, work, svec, status);
 }
 
 // ---------------------------------------------------------------- engine
@@ -541,6 +394,18 @@ int tridiag_status(const double *alpha, const double *beta, int M, double tol, d
     return QCM_OK;
 }
 
+// psi /= |psi| (FP64), through the chain state of chain 0 of e.
+int psi_finalize(Engine &e, double *psi, hipStream_t s) {
+    const int64_t dim = e.dim;
+    int nch = (int)ceil_div(dim, kChunk);
+    k_dot_partial<double, double><<<dim3(nch, 1), 256, 0, s>>>(psi, psi, dim, nch, e.partial);
+    ChainState cs1 = e.cs;
+    k_finish<<<1, 256, 0, s>>>(e.partial, nch, 5, cs1, 0, nullptr);
+    k_scale<double><<<dim3(nch, 1), 256, 0, s>>>(psi, dim, cs1);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
 int residual_norm(const HvOp &op, const double *psi, double theta, double *w64, double *partial,
                   double *out, hipStream_t s) {
     QCM_TRY(hv_launch(op, QCM_FP64, psi, w64, 1, s));
@@ -671,13 +536,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
             if (n + 1 < M) QCM_TRY(engine_step(e, n, s));
         }
         // normalise psi and take the true residual, all FP64
-        int nch = (int)ceil_div(b->dim, kChunk);
-        k_dot_partial<double, double><<<dim3(nch, 1), 256, 0, s>>>(psi, psi, b->dim, nch,
-                                                                   e.partial);
-        ChainState cs1 = e.cs;
-        k_finish<<<1, 256, 0, s>>>(e.partial, nch, 5, cs1, 0, nullptr);
-        k_scale<double><<<dim3(nch, 1), 256, 0, s>>>(psi, b->dim, cs1);
-        QCM_LAUNCH_CHECK();
+        QCM_TRY(psi_finalize(e, psi, s));
         double *w64 = (double *)e.vbuf[0];  // 8*dim bytes: the first two FP32 or one FP64 vector
         QCM_TRY(residual_norm(op, psi, hs.theta0, w64, e.partial, dscal, s));
         double r2 = 0.0;

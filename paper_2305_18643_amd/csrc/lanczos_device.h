@@ -1,0 +1,197 @@
+// Device helpers shared by the single-solve and the batched Lanczos kernels
+// (internal).  Both paths call exactly these functions, so a chain gives the
+// same bits whichever path runs it.
+#pragma once
+
+#include <math.h>
+
+#include "lanczos_engine.h"
+
+namespace qcm {
+
+template <typename T>
+__device__ __forceinline__ double ldd(const T *p) {
+    return (double)*p;
+}
+
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+    // 256 threads, fixed tree
+    const int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st(T *p, double x) {
+    *p = (T)x;
+}
+
+// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots)
+__device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b,
+                           double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < M; ++i) {
+        double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// k-th smallest eigenvalue by 256-way multisection: every thread tests one
+// point of the current bracket; 10 rounds narrow it by 257^10.
+__device__ inline double tridiag_kth(int M, const double *a, const double *b, int k, double *sh_lo,
+                              double *sh_hi) {
+    const int t = threadIdx.x;
+    __shared__ int cnts[256];
+    if (t == 0) {
+        double lo = a[0], hi = a[0];
+        for (int i = 0; i < M; ++i) {
+            double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < M - 1 ? fabs(b[i]) : 0.0);
+            lo = fmin(lo, a[i] - r);
+            hi = fmax(hi, a[i] + r);
+        }
+        double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
+        *sh_lo = lo - pad;
+        *sh_hi = hi + pad;
+    }
+    __syncthreads();
+    for (int round = 0; round < 10; ++round) {
+        double lo = *sh_lo, hi = *sh_hi;
+        double x = lo + (hi - lo) * (double)(t + 1) / 257.0;
+        cnts[t] = sturm_below(M, a, b, x);
+        __syncthreads();
+        if (t == 0) {
+            // first point with more than k eigenvalues below it
+            int j = 256;
+            for (int q = 0; q < 256; ++q)
+                if (cnts[q] > k) {
+                    j = q;
+                    break;
+                }
+            double nlo = j == 0 ? lo : lo + (hi - lo) * (double)j / 257.0;
+            double nhi = j == 256 ? hi : lo + (hi - lo) * (double)(j + 1) / 257.0;
+            *sh_lo = nlo;
+            *sh_hi = nhi;
+        }
+        __syncthreads();
+    }
+    double r = 0.5 * (*sh_lo + *sh_hi);
+    __syncthreads();
+    return r;
+}
+
+// Eigenvector for theta by inverse iteration; Gaussian elimination with
+// row pivoting on the tridiagonal (T - theta).  One thread.
+__device__ inline void tridiag_vector(int M, const double *a, const double *b, double theta, double *x,
+                               double *d, double *du, double *du2, double *dl, double *y) {
+    double scale = 1.0;
+    for (int i = 0; i < M; ++i) scale = fmax(scale, fabs(a[i]));
+    const double tiny = 1e-15 * scale;
+    for (int i = 0; i < M; ++i) x[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i < M; ++i) {
+            d[i] = a[i] - theta;
+            du[i] = i < M - 1 ? b[i] : 0.0;
+            dl[i] = i < M - 1 ? b[i] : 0.0;
+            du2[i] = 0.0;
+            y[i] = x[i];
+        }
+        for (int i = 0; i < M - 1; ++i) {
+            if (fabs(dl[i]) > fabs(d[i])) {
+                double t0 = d[i];
+                d[i] = dl[i];
+                dl[i] = t0;
+                double t1 = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t1;
+                if (i < M - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = 0.0;
+                }
+                double ty = y[i];
+                y[i] = y[i + 1];
+                y[i + 1] = ty;
+            }
+            if (d[i] == 0.0) d[i] = tiny;
+            double m = dl[i] / d[i];
+            d[i + 1] -= m * du[i];
+            if (i < M - 2) du[i + 1] -= m * du2[i];
+            y[i + 1] -= m * y[i];
+        }
+        if (d[M - 1] == 0.0) d[M - 1] = tiny;
+        for (int i = M - 1; i >= 0; --i) {
+            double s = y[i];
+            if (i + 1 < M) s -= du[i] * x[i + 1];
+            if (i + 2 < M) s -= du2[i] * x[i + 2];
+            x[i] = s / d[i];
+        }
+        double nr = 0.0;
+        for (int i = 0; i < M; ++i) nr += x[i] * x[i];
+        nr = 1.0 / sqrt(nr);
+        for (int i = 0; i < M; ++i) x[i] *= nr;
+    }
+    if (x[0] < 0.0)
+        for (int i = 0; i < M; ++i) x[i] = -x[i];
+}
+
+// The ground-state test of one workgroup (256 threads) on T_M: theta_0,
+// theta_1, the eigenvector of theta_0 in svec, residual estimate
+// beta[M-1] |s[M-1]| and the convergence flag, written to *status.
+__device__ inline void tridiag_status_block(const double *__restrict__ alpha,
+                                            const double *__restrict__ beta, int M, double tol,
+                                            double *__restrict__ work, double *__restrict__ svec,
+                                            GsStatus *__restrict__ status) {
+    __shared__ double lo, hi;
+    double th0 = tridiag_kth(M, alpha, beta, 0, &lo, &hi);
+    double th1 = M > 1 ? tridiag_kth(M, alpha, beta, 1, &lo, &hi) : NAN;
+    if (threadIdx.x == 0) {
+        tridiag_vector(M, alpha, beta, th0, svec, work, work + M, work + 2 * M, work + 3 * M,
+                       work + 4 * M);
+        double est = beta[M - 1] * fabs(svec[M - 1]);
+        status->theta0 = th0;
+        status->theta1 = th1;
+        status->est = est;
+        status->converged = est <= tol * fmax(1.0, fabs(th0)) ? 1 : 0;
+        status->M = M;
+    }
+}
+
+struct cplx {
+    double re, im;
+};
+
+// One continued fraction at z, bottom floor first.  part 0 (electron):
+// b0sq / (z + E0 - a0 - b1^2/(z + E0 - a1 - ...)); part 1 (hole):
+// b0sq / (z - E0 + a0 - b1^2/(z - E0 + a1 - ...)).
+__device__ inline cplx cf_value(const double *__restrict__ co, int len, int maxs, cplx z, double e0,
+                         int part) {
+    cplx r{0.0, 0.0};
+    if (len <= 0 || co[0] == 0.0) return r;
+    const double sg = part == 0 ? 1.0 : -1.0;
+    const double zr = part == 0 ? z.re + e0 : z.re - e0;
+    const double zi = z.im;
+    const double *a = co + 1, *b2 = co + 1 + maxs;
+    double gr = zr - sg * a[len - 1], gi = zi;
+    for (int n = len - 2; n >= 0; --n) {
+        double den = gr * gr + gi * gi;
+        double qr = b2[n] * gr / den, qi = -b2[n] * gi / den;  // b2 / g
+        gr = zr - sg * a[n] - qr;
+        gi = zi - qi;
+    }
+    double den = gr * gr + gi * gi;
+    r.re = co[0] * gr / den;
+    r.im = -co[0] * gi / den;
+    return r;
+}
+
+}  // namespace qcm

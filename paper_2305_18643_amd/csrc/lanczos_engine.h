@@ -46,6 +46,18 @@ int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s);
 int engine_normalize(Engine &e, hipStream_t s);
 int engine_step(Engine &e, int n, hipStream_t s);
 int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t s);
+int engine_normalize_from_partials(Engine &e, hipStream_t s);
+int psi_finalize(Engine &e, double *psi, hipStream_t s);
+// |H psi - theta psi| into *out (device), FP64; w64 holds dim doubles
+int residual_norm(const HvOp &op, const double *psi, double theta, double *w64, double *partial,
+                  double *out, hipStream_t s);
+// Green-function pieces (green.hip)
+int apply_ops_launch(Engine &e, const double *psi, int64_t d_src_up, const SpinTables &src_up,
+                     const SpinTables &tgt_up, int kind, const int32_t *ops, hipStream_t s);
+int green_store(const Engine *e, int npairs, int part, double *coef, int32_t *len, int stride,
+                hipStream_t s);
+int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, const double *zd,
+               double e0, const int32_t *pidx, double *F, double *G, hipStream_t s);
 int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
                    double *svec, GsStatus *status, hipStream_t s);
 

@@ -1,0 +1,208 @@
+"""GPU tests of the batched / served solve engine (qcm_engine_*, qcm_batch_solve).
+
+What is checked:
+  * a job run by the engine gives bitwise the results of the single-solve
+    calls (qcm_lanczos_gs + qcm_green_cf) with the same options, in FP64 and
+    in FP32-vector mode: E0, iteration count, ground state, every chain
+    coefficient and G on the grid;
+  * a job's results are bitwise the same alone and in a mix of other jobs
+    admitted before, with and after it (continuous batching);
+  * admission by memory: a pool that holds only a few jobs admits the rest
+    as earlier ones complete, never exceeds the pool, and gives bitwise the
+    results of a pool that holds everything;
+  * parity with the CPU oracle: E0 relative 1e-10 (FP64), G absolute 1e-4 at
+    eta = 0.1 on chains that exhaust their Krylov space; the FP32-vector
+    errors are printed and bounded (E0 relative 1e-6, G absolute 5e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cf
+
+pytestmark = pytest.mark.gpu
+
+Z = synth.omega_grid()
+ORBS = [0, 1, 2, 3]
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_18643_amd as q
+    q.load_library()
+    return q
+
+
+def _small_batched(count, max_L=10):
+    out = []
+    for m in synth.batched_solves(18643, 256):
+        if m.L <= max_L:
+            out.append(m)
+        if len(out) == count:
+            break
+    return out
+
+
+def _mixed_models():
+    ms = _small_batched(5, max_L=9)
+    ms.append(synth.random_model(401, 7, 3, 4))          # non-uniform U, odd sector
+    ms.append(synth.serving_requests(2305, 40)[3])
+    ms.append(synth.plaquette_2x2())
+    return ms
+
+
+def _spec(q, m, tag, psi=False, orbs=ORBS):
+    import torch
+    p = torch.zeros(oracle.binom(m.L, m.nup) * oracle.binom(m.L, m.ndn), dtype=torch.float64,
+                    device="cuda") if psi else None
+    return q.JobSpec((m.t, m.U), m.nup, m.ndn, orbs=orbs, seed=1, tag=tag, psi=p)
+
+
+def _run_all(eng, specs):
+    for s in specs:
+        assert eng.submit(s)
+    out = {}
+    while True:
+        n = eng.step(16)
+        for r in eng.poll():
+            out[r["tag"]] = r
+        if n == 0:
+            break
+    for r in eng.poll():
+        out[r["tag"]] = r
+    return out
+
+
+def _same(a, b):
+    assert a["e0"] == b["e0"]
+    assert a["n_iter"] == b["n_iter"]
+    assert np.array_equal(a["len"], b["len"])
+    assert np.array_equal(a["coef"], b["coef"])
+    assert np.array_equal(a["G"], b["G"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32v"])
+def test_engine_equals_single_calls(q, prec):
+    models = _mixed_models()
+    reorth = 1 if prec == "fp32v" else 0
+    tol = 1e-12 if prec == "fp64" else 1e-7
+    steps = 60
+    print(f"engine vs single calls, {prec}, {len(models)} jobs", flush=True)
+    eng = q.Engine(1 << 30, prec=prec, reorth=reorth, gf_steps=steps, max_jobs=8, z=Z, tol=tol)
+    specs = [_spec(q, m, i, psi=True) for i, m in enumerate(models)]
+    res = _run_all(eng, specs)
+    eng.close()
+    assert sorted(res) == list(range(len(models)))
+    for i, m in enumerate(models):
+        b = q.sector_basis(m.L, m.nup, m.ndn)
+        r = q.lanczos_gs((m.t, m.U), b, prec=prec, reorth=reorth, tol=tol)
+        g = q.green_cf((m.t, m.U), b, r["psi"], r["e0"], ORBS, Z, max_steps=steps, prec=prec,
+                       reorth=reorth)
+        e = res[i]
+        print(f"  job {i} {m.name} L={m.L}: n_iter {e['n_iter']} e0 {e['e0']:.12f}", flush=True)
+        assert e["e0"] == r["e0"] and e["n_iter"] == r["n_iter"]
+        assert e["converged"] == r["converged"] and e["breakdown"] == r["breakdown"]
+        assert e["true_residual"] == r["true_residual"]
+        assert np.array_equal(e["psi"].cpu().numpy(), r["psi"].cpu().numpy())
+        assert np.array_equal(e["len"], g["len"])
+        assert np.array_equal(e["coef"], g["coef"])
+        assert np.array_equal(e["G"], g["G"].cpu().numpy())
+
+
+def test_alone_vs_mix(q):
+    ms = synth.batched_solves(18643, 256)
+    target = [m for m in ms if m.L == 10][0]
+    others = [m for m in ms if m.L <= 11][:12]
+    kw = dict(prec="fp32v", reorth=1, gf_steps=50, z=Z)
+    print("alone", flush=True)
+    eng = q.Engine(1 << 30, max_jobs=1, **kw)
+    alone = _run_all(eng, [_spec(q, target, 0)])[0]
+    eng.close()
+    print("in the mix", flush=True)
+    eng = q.Engine(1 << 31, max_jobs=16, **kw)
+    specs = [_spec(q, m, 100 + i) for i, m in enumerate(others)]
+    got = {}
+    for s in specs[:5]:
+        assert eng.submit(s)
+    eng.step(7)
+    assert eng.submit(_spec(q, target, 0))
+    eng.step(3)
+    for s in specs[5:]:
+        assert eng.submit(s)
+    while eng.step(8):
+        for r in eng.poll():
+            got[r["tag"]] = r
+    for r in eng.poll():
+        got[r["tag"]] = r
+    eng.close()
+    assert len(got) == len(specs) + 1
+    _same(alone, got[0])
+    print(f"  identical: e0 {alone['e0']:.12f}, {alone['n_iter']} steps", flush=True)
+
+
+def test_admission_by_memory(q):
+    from paper_2305_18643_amd import serving
+    models = _small_batched(10, max_L=10)
+    kw = dict(prec="fp32v", reorth=1, gf_steps=40, z=Z, max_jobs=32)
+    big = q.Engine(1 << 31, **kw)
+    ref = _run_all(big, [_spec(q, m, i) for i, m in enumerate(models)])
+    sizes = [big.job_bytes(_spec(q, m, 0)) for m in models]
+    hdr = big.info()["header_bytes"]
+    big.close()
+    pool = hdr + 256 + int(2.5 * max(sizes))
+    print(f"pool {pool} bytes, jobs {min(sizes)}..{max(sizes)} bytes", flush=True)
+    eng = q.Engine(pool, **kw)
+    rep = serving.serve(eng, [_spec(q, m, i) for i, m in enumerate(models)], np.zeros(len(models)))
+    info = eng.info()
+    eng.close()
+    print(f"  max in flight {rep.max_in_flight}, blocked ticks {rep.head_blocked}, "
+          f"peak {info['peak_in_use']} of {info['pool_bytes']}", flush=True)
+    assert rep.head_blocked > 0 and rep.max_in_flight < len(models)
+    assert info["peak_in_use"] + info["header_bytes"] <= info["pool_bytes"]
+    for i in range(len(models)):
+        _same(ref[i], rep.results[i])
+
+
+def test_batch_solve_limited_workspace(q):
+    models = _small_batched(8, max_L=10)
+    kw = dict(prec="fp64", gf_steps=30, z=Z)
+    specs = [_spec(q, m, 7 * i) for i, m in enumerate(models)]
+    need = q.batch_bytes(specs, **kw)
+    print(f"batch of {len(models)}: {need} bytes for all at once", flush=True)
+    full = q.batch_solve(specs, **kw)
+    specs2 = [_spec(q, m, 7 * i) for i, m in enumerate(models)]
+    part = q.batch_solve(specs2, ws_bytes=need // 3, **kw)
+    for a, b in zip(full, part):
+        assert a["tag"] == b["tag"]
+        _same(a, b)
+
+
+def test_engine_oracle_parity(q):
+    ms = _small_batched(6, max_L=9)
+    # the 6-orbital jobs run their chains to exhaustion (sectors of <= 300 states)
+    six = [m for m in synth.batched_solves(18643, 256) if m.L == 6][:3]
+    steps = 320
+    for prec in ("fp64", "fp32v"):
+        eng = q.Engine(1 << 30, prec=prec, gf_steps=steps, max_jobs=16, z=Z)
+        res = _run_all(eng, [_spec(q, m, i) for i, m in enumerate(ms + six)])
+        eng.close()
+        for i, m in enumerate(ms + six):
+            ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+            e = res[i]
+            rel = abs(e["e0"] - ro["e0"]) / abs(ro["e0"])
+            line = f"  {prec} {m.name} ({m.nup},{m.ndn}): E0 rel err {rel:.1e}"
+            if prec == "fp64":
+                assert rel <= 1e-10
+            else:
+                assert rel <= 1e-6
+            if m.L == 6:
+                ch = oracle.green_cf(m.t, m.U, m.nup, m.ndn, ro["psi"], ORBS, max_steps=steps)
+                Go = cf.green_matrix(ch, 4, Z, ro["e0"])
+                err = np.abs(e["G"] - Go).max()
+                line += f", max |dG| {err:.1e}"
+                assert err <= (1e-4 if prec == "fp64" else 5e-3)
+            print(line, flush=True)
