@@ -51,6 +51,27 @@ def parse():
     return p.parse_args()
 
 
+def measured_traffic(U: float):
+    """HBM bytes per product from the committed counter summary, or None when
+    the product kernels changed since the counters were taken (source hash)
+    or the workload differs from the one counted (U = 8)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hv_4x4_fp64_hbm_traffic.txt")
+    if U != 8.0 or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("hv.hip", "hv_split.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2305_18643_amd", "csrc", f), "rb").read())
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_hv"])
+
+
 def time_calls(torch, fn, steps, warmup, stream):
     for _ in range(warmup):
         fn()
@@ -132,7 +153,8 @@ def main():
                    "sites": 16, "n_up": 8, "n_dn": 8, "dim": d, "prec": "fp64",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.U),
                      "kernel": "H.v (k_hv_inrow_team + k_hv_down_acc)",
                      "bytes_per_launch": bytes_alg},
     }
