@@ -35,46 +35,15 @@
 #include <map>
 #include <vector>
 
-#include "lanczos_device.h"
+#include "lanczos_step.h"
 
 namespace qcm {
 
 // Longest row of V a product block stages in LDS (up-spin strings of one
 // sector).  Jobs with a longer up-spin sector use the single-solve calls.
 constexpr int64_t kMaxRow = 8192;
-// Elements of V staged per product block when rows are short.
-constexpr int64_t kBlockElems = 2048;
 
 // ---------------------------------------------------------------- round tables
-
-// One group: the nvec chains of one job in one sector, at step n.
-struct BGroup {
-    int64_t d_up, d_dn, dim;
-    const uint32_t *su, *sd;
-    const double *eu, *ed;
-    const int32_t *nhu, *nhd, *colu, *cold;
-    const double *cfu, *cfd;
-    const double *ulut;
-    double u_uniform;
-    int32_t nbytes;
-    int32_t rows;      // rows of V per product block
-    int32_t nblk;      // product blocks per vector
-    int32_t nvec, nchunks, n;
-    const void *vp;    // v_{n-1} [nvec][dim]
-    const void *v;     // v_n
-    void *w;           // the new vector
-    double *partial;   // [nvec][nchunks]
-    ChainState cs;
-};
-
-// psi += svec[n] * v_n of one replaying ground-state chain
-struct BAcc {
-    const void *v;
-    double *psi;
-    const double *svec;
-    int64_t dim;
-    int32_t nchunks, n;
-};
 
 // per-job end-of-round test and status gathering
 struct BCtl {
@@ -96,262 +65,7 @@ struct BStat {
     int32_t pad[2];
 };
 
-__device__ __forceinline__ int find_group(const int64_t *__restrict__ begin, int ng, int64_t x) {
-    int lo = 0, hi = ng - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (begin[mid] <= x)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------- kernels
-
-// w = H v for every vector of every group.  A block holds `rows` whole rows
-// of V in LDS (the in-row term gathers there), streams the neighbour rows of
-// the row-mixing term from global memory and computes the diagonal from the
-// two strings.  The sum runs in the order of the single-sector kernel:
-// diagonal, up hops in list order, down hops in list order, all FP64.
-template <typename T>
-__global__ void __launch_bounds__(256) kb_hv(const BGroup *__restrict__ G,
-                                             const int64_t *__restrict__ begin, int ng) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int g = find_group(begin, ng, blockIdx.x);
-    const BGroup &q = G[g];
-    const int64_t local = (int64_t)blockIdx.x - begin[g];
-    const int64_t vec = local / q.nblk;
-    const int64_t rb = local - vec * q.nblk;
-    const int64_t d_up = q.d_up;
-    const int64_t row0 = rb * q.rows;
-    const int64_t nr = min((int64_t)q.rows, q.d_dn - row0);
-    const int nlut = q.u_uniform >= 0.0 ? 0 : q.nbytes * 256;
-    double *lut = reinterpret_cast<double *>(smem_raw);
-    T *row = reinterpret_cast<T *>(smem_raw + sizeof(double) * nlut);
-    const T *v = (const T *)q.v + vec * q.dim;
-    T *w = (T *)q.w + vec * q.dim;
-    for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = q.ulut[k];
-    const int64_t nel = nr * d_up;
-    const T *vblk = v + row0 * d_up;
-    for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
-    __syncthreads();
-    const uint32_t du = (uint32_t)d_up;
-    for (int64_t e = threadIdx.x; e < nel; e += 256) {
-        const uint32_t r = (uint32_t)e / du;
-        const uint32_t iu = (uint32_t)e - r * du;
-        const int64_t idn = row0 + r;
-        const uint32_t bu = q.su[iu];
-        const uint32_t bd = q.sd[idn];
-        const uint32_t dbl = bu & bd;
-        double diag = q.eu[iu] + q.ed[idn];
-        if (q.u_uniform >= 0.0) {
-            diag += q.u_uniform * (double)__popc(dbl);
-        } else {
-            for (int byte = 0; byte < q.nbytes; ++byte)
-                diag += lut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
-        }
-        const T *rrow = row + (int64_t)r * d_up;
-        double acc = diag * (double)rrow[iu];
-        const int nhu = q.nhu[iu];
-        for (int s = 0; s < nhu; ++s) {
-            const int64_t ee = (int64_t)s * d_up + iu;
-            acc = fma(q.cfu[ee], (double)rrow[q.colu[ee]], acc);
-        }
-        const int nhd = q.nhd[idn];
-        for (int s = 0; s < nhd; ++s) {
-            const int64_t ee = (int64_t)s * q.d_dn + idn;
-            acc = fma(q.cfd[ee], (double)v[(int64_t)q.cold[ee] * d_up + iu], acc);
-        }
-        w[idn * d_up + iu] = (T)acc;
-    }
-}
-
-// chunk c of vector `vec` of group g for the chunked kernels
-struct ChunkAt {
-    int g;
-    int64_t vec, base;
-};
-__device__ __forceinline__ ChunkAt chunk_at(const BGroup *__restrict__ G,
-                                            const int64_t *__restrict__ begin, int ng) {
-    ChunkAt r;
-    r.g = find_group(begin, ng, blockIdx.x);
-    const int64_t local = (int64_t)blockIdx.x - begin[r.g];
-    r.vec = local / G[r.g].nchunks;
-    r.base = (local - r.vec * G[r.g].nchunks) * kChunk;
-    return r;
-}
-
-// w -= beta_{n-1} v_{n-1} (n > 0); partial <v_n, w>
-template <typename T>
-__global__ void __launch_bounds__(256) kb_sub_prev_dot(const BGroup *__restrict__ G,
-                                                       const int64_t *__restrict__ begin, int ng) {
-    __shared__ double sh[256];
-    const ChunkAt at = chunk_at(G, begin, ng);
-    const BGroup &q = G[at.g];
-    const int n = q.n;
-    const double b = n > 0 ? q.cs.beta[at.vec * q.cs.maxs + n - 1] : 0.0;
-    const int64_t off = at.vec * q.dim;
-    T *w = (T *)q.w + off;
-    const T *vp = (const T *)q.vp + off;
-    const T *v = (const T *)q.v + off;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = at.base + k;
-        if (i < q.dim) {
-            double x = ldd(w + i);
-            if (n > 0) {
-                x = fma(-b, ldd(vp + i), x);
-                st(w + i, x);
-                x = ldd(w + i);
-            }
-            acc = fma(ldd(v + i), x, acc);
-        }
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
-}
-
-// w -= alpha_n v_n; partial <w, w>
-template <typename T>
-__global__ void __launch_bounds__(256) kb_sub_cur_norm(const BGroup *__restrict__ G,
-                                                       const int64_t *__restrict__ begin, int ng) {
-    __shared__ double sh[256];
-    const ChunkAt at = chunk_at(G, begin, ng);
-    const BGroup &q = G[at.g];
-    const double a = q.cs.alpha[at.vec * q.cs.maxs + q.n];
-    const int64_t off = at.vec * q.dim;
-    T *w = (T *)q.w + off;
-    const T *v = (const T *)q.v + off;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = at.base + k;
-        if (i < q.dim) {
-            double x = fma(-a, ldd(v + i), ldd(w + i));
-            st(w + i, x);
-            x = ldd(w + i);
-            acc = fma(x, x, acc);
-        }
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
-}
-
-// partial <x, w> with x = v_n (which 0), v_{n-1} (1) or w (2)
-template <typename T>
-__global__ void __launch_bounds__(256) kb_dot(const BGroup *__restrict__ G,
-                                              const int64_t *__restrict__ begin, int ng,
-                                              int which) {
-    __shared__ double sh[256];
-    const ChunkAt at = chunk_at(G, begin, ng);
-    const BGroup &q = G[at.g];
-    const int64_t off = at.vec * q.dim;
-    const T *w = (const T *)q.w + off;
-    const T *x = which == 0 ? (const T *)q.v + off : which == 1 ? (const T *)q.vp + off : w;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = at.base + k;
-        if (i < q.dim) acc = fma(ldd(x + i), ldd(w + i), acc);
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) q.partial[at.vec * q.nchunks + at.base / kChunk] = s;
-}
-
-// w -= corr v_n + corr2 v_{n-1}
-template <typename T>
-__global__ void __launch_bounds__(256) kb_reorth(const BGroup *__restrict__ G,
-                                                 const int64_t *__restrict__ begin, int ng) {
-    const ChunkAt at = chunk_at(G, begin, ng);
-    const BGroup &q = G[at.g];
-    const double c1 = q.cs.corr[at.vec], c2 = q.cs.corr2[at.vec];
-    const int64_t off = at.vec * q.dim;
-    T *w = (T *)q.w + off;
-    const T *v = (const T *)q.v + off;
-    const T *vp = (const T *)q.vp + off;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = at.base + k;
-        if (i < q.dim) {
-            double x = ldd(w + i);
-            x = fma(-c1, ldd(v + i), x);
-            x = fma(-c2, ldd(vp + i), x);
-            st(w + i, x);
-        }
-    }
-}
-
-// w *= 1/beta_n (0 once the chain has stopped)
-template <typename T>
-__global__ void __launch_bounds__(256) kb_scale(const BGroup *__restrict__ G,
-                                                const int64_t *__restrict__ begin, int ng) {
-    const ChunkAt at = chunk_at(G, begin, ng);
-    const BGroup &q = G[at.g];
-    const double s = q.cs.inv[at.vec];
-    T *w = (T *)q.w + at.vec * q.dim;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = at.base + k;
-        if (i < q.dim) st(w + i, ldd(w + i) * s);
-    }
-}
-
-// Chunk sums of each chain and the recurrence bookkeeping (modes as in the
-// single-solve engine: 0 alpha, 1 beta and breakdown, 3 alpha correction,
-// 4 second correction).
-__global__ void __launch_bounds__(256) kb_finish(const BGroup *__restrict__ G,
-                                                 const int64_t *__restrict__ begin, int ng,
-                                                 int mode) {
-    __shared__ double sh[256];
-    const int g = find_group(begin, ng, blockIdx.x);
-    const BGroup &q = G[g];
-    const int c = (int)((int64_t)blockIdx.x - begin[g]);
-    const double *partial = q.partial + (int64_t)c * q.nchunks;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < q.nchunks; k += 256) acc += partial[k];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x != 0) return;
-    const ChainState &cs = q.cs;
-    const int n = q.n;
-    switch (mode) {
-        case 0: {
-            cs.alpha[(int64_t)c * cs.maxs + n] = s;
-            double a = fabs(s);
-            if (a > cs.amax[c]) cs.amax[c] = a;
-            break;
-        }
-        case 1: {
-            double b = sqrt(s);
-            cs.beta[(int64_t)c * cs.maxs + n] = b;
-            if (!cs.done[c]) {
-                double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
-                if (!(b >= cs.btol * am)) cs.done[c] = 1;
-                cs.len[c] = n + 1;
-            }
-            cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
-            break;
-        }
-        case 3:
-            cs.alpha[(int64_t)c * cs.maxs + n] += s;
-            cs.corr[c] = s;
-            break;
-        case 4:
-            cs.corr2[c] = s;
-            break;
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) kb_accum(const BAcc *__restrict__ A,
-                                                const int64_t *__restrict__ begin, int na) {
-    const int g = find_group(begin, na, blockIdx.x);
-    const BAcc &q = A[g];
-    const double s = q.svec[q.n];
-    const int64_t base = ((int64_t)blockIdx.x - begin[g]) * kChunk;
-    const T *v = (const T *)q.v;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        const int64_t i = base + k;
-        if (i < q.dim) q.psi[i] = fma(s, ldd(v + i), q.psi[i]);
-    }
-}
 
 __global__ void __launch_bounds__(256) kb_control(const BCtl *__restrict__ C,
                                                   BStat *__restrict__ out) {
@@ -379,7 +93,6 @@ struct Part {
     SpinTables up{};
     HopTables hu{};
     Engine e{};
-    int32_t rows = 1, nblk = 0;
 };
 
 struct Job {
@@ -457,7 +170,7 @@ static TabLayout tab_layout(int max_jobs) {
     const int mg = 2 * max_jobs;
     Carver cv(nullptr);
     t.groups = (cv.take<BGroup>(mg), cv.off - sizeof(BGroup) * mg);
-    t.accs = (cv.take<BAcc>(max_jobs), cv.off - sizeof(BAcc) * max_jobs);
+    t.accs = (cv.take<BGroup>(max_jobs), cv.off - sizeof(BGroup) * max_jobs);
     t.hvb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
     t.chb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
     t.cnb = (cv.take<int64_t>(mg + 1), cv.off - sizeof(int64_t) * (mg + 1));
@@ -499,14 +212,6 @@ static int check_job(const qcm_engine_opts &o, const qcm_job *j) {
     return QCM_OK;
 }
 
-static void part_shape(Part &p, int64_t d_up, int64_t d_dn) {
-    int64_t r = kBlockElems / d_up;
-    if (r < 1) r = 1;
-    if (r > d_dn) r = d_dn;
-    p.rows = (int32_t)r;
-    p.nblk = (int32_t)ceil_div(d_dn, r);
-}
-
 static HvOp part_op(const Job &j, const Part &p) {
     HvOp op;
     op.md = j.md;
@@ -532,7 +237,6 @@ static int job_layout(const qcm_engine_opts &o, Job &j, Carver &cv, hipStream_t 
     QCM_TRY(build_spin_tables(L, j.d.n_up, cv, &j.gs.up, s));
     QCM_TRY(build_hop_tables(j.md, j.gs.up, cv, &j.gs.hu, s, nb));
     j.gs.valid = 1;
-    part_shape(j.gs, j.gs.up.d, j.dn.d);
     for (int p = 0; p < 2; ++p) {
         Part &q = j.gf[p];
         const int nup2 = p == 0 ? j.d.n_up + 1 : j.d.n_up - 1;
@@ -540,7 +244,6 @@ static int job_layout(const qcm_engine_opts &o, Job &j, Carver &cv, hipStream_t 
         if (!q.valid) continue;
         QCM_TRY(build_spin_tables(L, nup2, cv, &q.up, s));
         QCM_TRY(build_hop_tables(j.md, q.up, cv, &q.hu, s, nb));
-        part_shape(q, q.up.d, j.dn.d);
     }
     const int64_t dim = j.gs.up.d * j.dn.d;
     const int lim = gs_limit(o);
@@ -728,65 +431,26 @@ static void rotate(Engine &e) {
     e.iw = t;
 }
 
-static void fill_group(BGroup &g, const Job &j, const Part &p, int n) {
-    const Engine &e = p.e;
-    g.d_up = p.up.d;
-    g.d_dn = j.dn.d;
-    g.dim = e.dim;
-    g.su = p.up.states;
-    g.sd = j.dn.states;
-    g.eu = p.hu.ediag;
-    g.ed = j.hd.ediag;
-    g.nhu = p.hu.nh;
-    g.nhd = j.hd.nh;
-    g.colu = p.hu.col;
-    g.cold = j.hd.col;
-    g.cfu = p.hu.coef;
-    g.cfd = j.hd.coef;
-    g.ulut = j.md.ulut;
-    g.u_uniform = j.md.u_uniform;
-    g.nbytes = j.md.nbytes;
-    g.rows = p.rows;
-    g.nblk = p.nblk;
-    g.nvec = e.nvec;
-    g.nchunks = e.nchunks;
-    g.n = n;
-    g.vp = e.vbuf[e.ivp];
-    g.v = e.vbuf[e.iv];
-    g.w = e.vbuf[e.iw];
-    g.partial = e.partial;
-    g.cs = e.cs;
-}
-
 template <typename T>
 static int launch_round(qcm_engine *E, int ng, int na, int nc, size_t lds, const TabLayout &tl,
                         const int64_t *hvb, const int64_t *chb, const int64_t *cnb,
                         const int64_t *acb) {
     hipStream_t s = E->s;
     const BGroup *G = (const BGroup *)(E->d_tab + tl.groups);
-    const BAcc *A = (const BAcc *)(E->d_tab + tl.accs);
-    const int64_t *dhv = (const int64_t *)(E->d_tab + tl.hvb);
-    const int64_t *dch = (const int64_t *)(E->d_tab + tl.chb);
-    const int64_t *dcn = (const int64_t *)(E->d_tab + tl.cnb);
-    const int64_t *dac = (const int64_t *)(E->d_tab + tl.acb);
+    const BGroup *A = (const BGroup *)(E->d_tab + tl.accs);
+    const TabSrc hv{G, (const int64_t *)(E->d_tab + tl.hvb), ng};
+    const TabSrc ch{G, (const int64_t *)(E->d_tab + tl.chb), ng};
+    const TabSrc cn{G, (const int64_t *)(E->d_tab + tl.cnb), ng};
+    const TabSrc ac{A, (const int64_t *)(E->d_tab + tl.acb), na};
     const BCtl *C = (const BCtl *)(E->d_tab + tl.ctl);
-    if (na > 0 && acb[na] > 0) kb_accum<T><<<(unsigned)acb[na], 256, 0, s>>>(A, dac, na);
+    if (na > 0 && acb[na] > 0) ks_accum<T, TabSrc><<<(unsigned)acb[na], 256, 0, s>>>(ac);
     if (ng > 0) {
         const unsigned nh = (unsigned)hvb[ng], nk = (unsigned)chb[ng], nn = (unsigned)cnb[ng];
-        kb_hv<T><<<nh, 256, lds, s>>>(G, dhv, ng);
-        kb_sub_prev_dot<T><<<nk, 256, 0, s>>>(G, dch, ng);
-        kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 0);
-        kb_sub_cur_norm<T><<<nk, 256, 0, s>>>(G, dch, ng);
-        if (E->o.reorth) {
-            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 0);
-            kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 3);
-            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 1);
-            kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 4);
-            kb_reorth<T><<<nk, 256, 0, s>>>(G, dch, ng);
-            kb_dot<T><<<nk, 256, 0, s>>>(G, dch, ng, 2);
-        }
-        kb_finish<<<nn, 256, 0, s>>>(G, dcn, ng, 1);
-        kb_scale<T><<<nk, 256, 0, s>>>(G, dch, ng);
+        ks_hv<T, TabSrc><<<nh, 256, lds, s>>>(hv);
+        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 0);
+        ks_norm<T, TabSrc><<<nk, 256, 0, s>>>(ch);
+        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 1);
+        ks_update<T, TabSrc><<<nk, 256, 0, s>>>(ch);
     }
     if (nc > 0) kb_control<<<nc, 256, 0, s>>>(C, E->d_stat);
     QCM_LAUNCH_CHECK();
@@ -816,22 +480,24 @@ static int run_round(qcm_engine *E) {
     const qcm_engine_opts &o = E->o;
     const TabLayout tl = tab_layout(o.max_jobs);
     BGroup *G = (BGroup *)(E->h_tab + tl.groups);
-    BAcc *A = (BAcc *)(E->h_tab + tl.accs);
+    BGroup *A = (BGroup *)(E->h_tab + tl.accs);
     int64_t *hvb = (int64_t *)(E->h_tab + tl.hvb);
     int64_t *chb = (int64_t *)(E->h_tab + tl.chb);
     int64_t *cnb = (int64_t *)(E->h_tab + tl.cnb);
     int64_t *acb = (int64_t *)(E->h_tab + tl.acb);
     BCtl *C = (BCtl *)(E->h_tab + tl.ctl);
-    const size_t s = o.prec == QCM_FP64 ? 8 : 4;
     const int lim = gs_limit(o);
     int ng = 0, na = 0, nc = 0;
     size_t lds = 0;
     hvb[0] = chb[0] = cnb[0] = acb[0] = 0;
-    auto add_group = [&](const Job &j, const Part &p) {
-        fill_group(G[ng], j, p, j.n);
-        const size_t lut = j.md.u_uniform >= 0.0 ? 0 : sizeof(double) * 256 * j.md.nbytes;
-        lds = std::max(lds, lut + s * (size_t)p.rows * (size_t)p.up.d);
-        hvb[ng + 1] = hvb[ng] + (int64_t)p.e.nvec * p.nblk;
+    auto add_group = [&](const Job &j, const Part &p, bool replay) {
+        G[ng] = engine_group(p.e, j.n);
+        if (replay) {
+            G[ng].psi = j.psi;
+            G[ng].svec = j.svec;
+        }
+        lds = std::max(lds, fused_lds(p.up.d, p.e.rows, o.prec, j.md.nbytes, j.md.u_uniform));
+        hvb[ng + 1] = hvb[ng] + (int64_t)p.e.nvec * p.e.nblk;
         chb[ng + 1] = chb[ng] + (int64_t)p.e.nvec * p.e.nchunks;
         cnb[ng + 1] = cnb[ng] + p.e.nvec;
         ++ng;
@@ -843,7 +509,7 @@ static int run_round(qcm_engine *E) {
         c.status = j.status;
         c.tol = o.tol;
         if (j.phase == PH_GS1) {
-            add_group(j, j.gs);
+            add_group(j, j.gs, false);
             c.test = (o.gs_fixed_steps <= 0) ? 1 : 0;
             c.m = j.n + 1;
             c.alpha = j.gs.e.cs.alpha;
@@ -854,19 +520,19 @@ static int run_round(qcm_engine *E) {
             c.n0 = 1;
             c.len0 = j.gs.e.cs.len;
         } else if (j.phase == PH_GS2) {
-            BAcc &a = A[na];
-            a.v = j.gs.e.vbuf[j.gs.e.iv];
-            a.psi = j.psi;
-            a.svec = j.svec;
-            a.dim = j.gs.e.dim;
-            a.nchunks = j.gs.e.nchunks;
-            a.n = j.n;
-            acb[na + 1] = acb[na] + j.gs.e.nchunks;
-            ++na;
-            if (j.n + 1 < j.M) add_group(j, j.gs);
+            // replay: psi += s_n v_n, fused into the step while one follows
+            if (j.n + 1 < j.M) {
+                add_group(j, j.gs, true);
+            } else {
+                A[na] = engine_group(j.gs.e, j.n);
+                A[na].psi = j.psi;
+                A[na].svec = j.svec;
+                acb[na + 1] = acb[na] + j.gs.e.nchunks;
+                ++na;
+            }
         } else {
             for (int p = 0; p < 2; ++p)
-                if (j.gf[p].valid) add_group(j, j.gf[p]);
+                if (j.gf[p].valid) add_group(j, j.gf[p], false);
             if (j.gf[0].valid) {
                 c.done0 = j.gf[0].e.cs.done;
                 c.n0 = j.npairs;

@@ -188,7 +188,7 @@ static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_gre
         if (nup2 < 0 || nup2 > L) continue;
         int64_t du2 = binom(L, nup2);
         size_t b = spin_tables_bytes(L, nup2) + hop_tables_bytes(m, du2) +
-                   engine_bytes(o->prec, npairs, du2 * gs->d_dn, o->max_steps);
+                   engine_bytes(o->prec, npairs, du2, gs->d_dn, o->max_steps);
         if (split_applies(m, nup2, du2, gs->d_dn)) b += split_bytes(m, nup2, du2, gs->d_dn);
         if (b > part_max) part_max = b;
     }

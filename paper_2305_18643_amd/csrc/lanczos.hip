@@ -5,14 +5,16 @@
 //   beta_n = |w|;  v_{n+1} = w / beta_n          (beta_n^2 = paper's b_{n+1}^2)
 //
 // The engine runs nvec independent chains in one sector at once (vectors laid
-// out consecutively), which is how the Green-function chains are batched.
-// Every dot product is a deterministic two-level sum: fixed chunks of
-// kChunk elements summed in a fixed order by one workgroup each, then the
-// chunk sums summed in a fixed order.  Results therefore depend only on the
-// inputs, never on launch shapes or on other work sharing the GPU.
+// out consecutively), which is how the Green-function chains are batched.  A
+// step is the three passes of lanczos_step.h.  Every dot product is a
+// deterministic two-level sum (fixed blocks or chunks, then a fixed-order sum
+// per chain), so results depend only on the inputs and the sector shape,
+// never on launch timing or on other work sharing the GPU.
 #include <math.h>
 
-#include "lanczos_device.h"
+#include <string.h>
+
+#include "lanczos_step.h"
 
 namespace qcm {
 
@@ -37,12 +39,8 @@ __global__ void __launch_bounds__(256) k_dot_partial(const TX *__restrict__ x,
     if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
 }
 
-// Sum of the chunk partials of each chain, then the recurrence bookkeeping.
-// mode 0: alpha[c][n] = s, amax update.
-// mode 1: beta[c][n] = sqrt(s), breakdown test, inv[c] = 1/beta or 0.
+// Sum of the chunk partials of each chain.
 // mode 2: out[c] = s (plain).
-// mode 3: alpha[c][n] += s, corr[c] = s (reorthogonalisation against v_n)
-// mode 4: corr2[c] = s (reorthogonalisation against v_{n-1})
 // mode 5: b0sq[c] = s, inv[c] = s > 0 ? 1/sqrt(s) : 0 (start-vector norm)
 __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ partial, int nchunks,
                                                 int mode, ChainState cs, int n,
@@ -53,122 +51,20 @@ __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ parti
     for (int k = threadIdx.x; k < nchunks; k += 256) acc += partial[(int64_t)c * nchunks + k];
     double s = block_sum(acc, sh);
     if (threadIdx.x != 0) return;
-    switch (mode) {
-        case 0: {
-            cs.alpha[(int64_t)c * cs.maxs + n] = s;
-            double a = fabs(s);
-            if (a > cs.amax[c]) cs.amax[c] = a;
-            break;
+    (void)n;
+    if (mode == 2) {
+        out[c] = s;
+    } else {
+        cs.b0sq[c] = s;
+        cs.inv[c] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        if (!(s > 0.0)) {
+            cs.done[c] = 1;
+            cs.len[c] = 0;
         }
-        case 1: {
-            double b = sqrt(s);
-            cs.beta[(int64_t)c * cs.maxs + n] = b;
-            if (!cs.done[c]) {
-                double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
-                if (!(b >= cs.btol * am)) {
-                    cs.done[c] = 1;
-                    cs.len[c] = n + 1;
-                } else {
-                    cs.len[c] = n + 1;
-                }
-            }
-            cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
-            break;
-        }
-        case 2:
-            out[c] = s;
-            break;
-        case 3:
-            cs.alpha[(int64_t)c * cs.maxs + n] += s;
-            cs.corr[c] = s;
-            break;
-        case 4:
-            cs.corr2[c] = s;
-            break;
-        case 5:
-            cs.b0sq[c] = s;
-            cs.inv[c] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-            if (!(s > 0.0)) {
-                cs.done[c] = 1;
-                cs.len[c] = 0;
-            }
-            break;
     }
 }
 
 // ---------------------------------------------------------------- vector updates
-
-// w -= beta[c][n-1] * vp  (n > 0), and partial <v, w>
-template <typename T>
-__global__ void __launch_bounds__(256) k_sub_prev_dot(T *__restrict__ w, const T *__restrict__ vp,
-                                                      const T *__restrict__ v, int64_t n_el,
-                                                      int nchunks, ChainState cs, int n,
-                                                      double *__restrict__ partial) {
-    __shared__ double sh[256];
-    const int c = blockIdx.y;
-    const double b = n > 0 ? cs.beta[(int64_t)c * cs.maxs + n - 1] : 0.0;
-    const int64_t off = (int64_t)c * n_el;
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        int64_t i = base + k;
-        if (i < n_el) {
-            double x = ldd(w + off + i);
-            if (n > 0) {
-                x = fma(-b, ldd(vp + off + i), x);
-                st(w + off + i, x);
-                x = ldd(w + off + i);  // the stored value, in storage precision
-            }
-            acc = fma(ldd(v + off + i), x, acc);
-        }
-    }
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
-}
-
-// w -= alpha[c][n] * v, and partial <w, w>
-template <typename T>
-__global__ void __launch_bounds__(256) k_sub_cur_norm(T *__restrict__ w, const T *__restrict__ v,
-                                                      int64_t n_el, int nchunks, ChainState cs,
-                                                      int n, double *__restrict__ partial) {
-    __shared__ double sh[256];
-    const int c = blockIdx.y;
-    const double a = cs.alpha[(int64_t)c * cs.maxs + n];
-    const int64_t off = (int64_t)c * n_el;
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        int64_t i = base + k;
-        if (i < n_el) {
-            double x = fma(-a, ldd(v + off + i), ldd(w + off + i));
-            st(w + off + i, x);
-            x = ldd(w + off + i);
-            acc = fma(x, x, acc);
-        }
-    }
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)c * nchunks + blockIdx.x] = s;
-}
-
-// w -= corr[c] * v + corr2[c] * vp (local reorthogonalisation)
-template <typename T>
-__global__ void __launch_bounds__(256) k_reorth(T *__restrict__ w, const T *__restrict__ v,
-                                                const T *__restrict__ vp, int64_t n_el,
-                                                ChainState cs) {
-    const int c = blockIdx.y;
-    const double c1 = cs.corr[c], c2 = cs.corr2[c];
-    const int64_t off = (int64_t)c * n_el;
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
-    for (int k = threadIdx.x; k < kChunk; k += 256) {
-        int64_t i = base + k;
-        if (i < n_el) {
-            double x = ldd(w + off + i);
-            x = fma(-c1, ldd(v + off + i), x);
-            x = fma(-c2, ldd(vp + off + i), x);
-            st(w + off + i, x);
-        }
-    }
-}
 
 // x *= inv[c]
 template <typename T>
@@ -250,14 +146,20 @@ __global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict
 
 // ---------------------------------------------------------------- engine
 
-size_t engine_bytes(int prec, int nvec, int64_t dim, int maxs) {
+size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs) {
     Carver cv(nullptr);
-    size_t s = prec == QCM_FP64 ? 8 : 4;
+    const size_t s = prec == QCM_FP64 ? 8 : 4;
+    const int64_t dim = d_up * d_dn;
     cv.take<char>(3 * s * (size_t)nvec * dim + 64);
-    int nch = (int)ceil_div(dim, kChunk);
-    cv.take<double>((size_t)nvec * (nch > 0 ? nch : 1));
+    int64_t nch = (int64_t)ceil_div(dim, kChunk);
+    if (nch < 1) nch = 1;
+    int32_t rows, nblk;
+    row_shape(d_up, d_dn, &rows, &nblk);
+    cv.take<double>((size_t)nvec * nch);
+    cv.take<double>((size_t)nvec * (nblk > nch ? nblk : nch));
+    cv.take<double>((size_t)nvec * 3 * nch);
     cv.take<double>((size_t)nvec * maxs * 2);
-    cv.take<double>((size_t)nvec * 6);
+    cv.take<double>((size_t)nvec * 7);
     cv.take<int32_t>((size_t)nvec * 2);
     return cv.off + 256;
 }
@@ -278,18 +180,25 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.vbuf[2] = vecs + 2 * vb;
     e.nchunks = (int)ceil_div(e.dim, kChunk);
     if (e.nchunks < 1) e.nchunks = 1;
+    row_shape(op.up.d, op.dn.d, &e.rows, &e.nblk);
+    e.fused = !op.split &&
+              fused_lds(op.up.d, e.rows, prec, op.md.nbytes, op.md.u_uniform) <= kFusedLds;
+    e.na = e.fused ? e.nblk : e.nchunks;
     e.partial = cv.take<double>((size_t)nvec * e.nchunks);
+    e.pa = cv.take<double>((size_t)nvec * (e.nblk > e.nchunks ? e.nblk : e.nchunks));
+    e.pn = cv.take<double>((size_t)nvec * 3 * e.nchunks);
     e.cs.maxs = maxs;
     e.cs.btol = btol;
     e.cs.alpha = cv.take<double>((size_t)nvec * maxs);
     e.cs.beta = cv.take<double>((size_t)nvec * maxs);
-    double *sc = cv.take<double>((size_t)nvec * 6);
+    double *sc = cv.take<double>((size_t)nvec * 7);
     e.cs.amax = sc;
     e.cs.inv = sc + nvec;
     e.cs.corr = sc + 2 * nvec;
     e.cs.corr2 = sc + 3 * nvec;
     e.cs.b0sq = sc + 4 * nvec;
     e.scratch = sc + 5 * nvec;
+    e.cs.apre = sc + 6 * nvec;
     int32_t *ic = cv.take<int32_t>((size_t)nvec * 2);
     e.cs.len = ic;
     e.cs.done = ic + nvec;
@@ -302,7 +211,7 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
 int engine_reset(Engine &e, hipStream_t s) {
     QCM_HIP(hipMemsetAsync(e.cs.alpha, 0, sizeof(double) * e.nvec * e.maxs, s));
     QCM_HIP(hipMemsetAsync(e.cs.beta, 0, sizeof(double) * e.nvec * e.maxs, s));
-    QCM_HIP(hipMemsetAsync(e.cs.amax, 0, sizeof(double) * e.nvec * 6, s));
+    QCM_HIP(hipMemsetAsync(e.cs.amax, 0, sizeof(double) * e.nvec * 7, s));
     QCM_HIP(hipMemsetAsync(e.cs.len, 0, sizeof(int32_t) * e.nvec * 2, s));
     size_t sz = (e.prec == QCM_FP64 ? 8 : 4) * (size_t)e.nvec * e.dim;
     e.ivp = 0;
@@ -312,28 +221,62 @@ int engine_reset(Engine &e, hipStream_t s) {
     return QCM_OK;
 }
 
+BGroup engine_group(const Engine &e, int n) {
+    BGroup g;
+    memset(&g, 0, sizeof g);
+    const HvOp &op = e.op;
+    g.d_up = op.up.d;
+    g.d_dn = op.dn.d;
+    g.dim = e.dim;
+    g.su = op.up.states;
+    g.sd = op.dn.states;
+    g.eu = op.hu.ediag;
+    g.ed = op.hd.ediag;
+    g.nhu = op.hu.nh;
+    g.nhd = op.hd.nh;
+    g.colu = op.hu.col;
+    g.cold = op.hd.col;
+    g.cfu = op.hu.coef;
+    g.cfd = op.hd.coef;
+    g.ulut = op.md.ulut;
+    g.u_uniform = op.md.u_uniform;
+    g.nbytes = op.md.nbytes;
+    g.rows = e.rows;
+    g.nblk = e.nblk;
+    g.nvec = e.nvec;
+    g.nchunks = e.nchunks;
+    g.na = e.na;
+    g.n = n;
+    g.reorth = e.reorth;
+    g.vp = e.vbuf[e.ivp];
+    g.v = e.vbuf[e.iv];
+    g.w = e.vbuf[e.iw];
+    g.pa = e.pa;
+    g.pn = e.pn;
+    g.psi = nullptr;
+    g.svec = nullptr;
+    g.cs = e.cs;
+    return g;
+}
+
 template <typename T>
 static int step_t(Engine &e, int n, hipStream_t s) {
-    T *vp = (T *)e.vbuf[e.ivp], *v = (T *)e.vbuf[e.iv], *w = (T *)e.vbuf[e.iw];
-    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
-    QCM_TRY(hv_launch(e.op, e.prec, v, w, e.nvec, s));
-    k_sub_prev_dot<T><<<g, 256, 0, s>>>(w, vp, v, e.dim, e.nchunks, e.cs, n, e.partial);
-    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 0, e.cs, n, nullptr);
-    k_sub_cur_norm<T><<<g, 256, 0, s>>>(w, v, e.dim, e.nchunks, e.cs, n, e.partial);
-    if (e.reorth) {
-        // local reorthogonalisation against v_n and v_{n-1}, FP64 dot products
-        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 2, e.cs, n, e.scratch);
-        k_dot_partial<T, T><<<g, 256, 0, s>>>(v, w, e.dim, e.nchunks, e.partial);
-        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 3, e.cs, n, nullptr);
-        k_dot_partial<T, T><<<g, 256, 0, s>>>(vp, w, e.dim, e.nchunks, e.partial);
-        k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 4, e.cs, n, nullptr);
-        k_reorth<T><<<g, 256, 0, s>>>(w, v, vp, e.dim, e.cs);
-        k_dot_partial<T, T><<<g, 256, 0, s>>>(w, w, e.dim, e.nchunks, e.partial);
+    const OneSrc src{engine_group(e, n)};
+    const unsigned nk = (unsigned)e.nvec * e.nchunks;
+    if (e.fused) {
+        const size_t lds = fused_lds(e.op.up.d, e.rows, e.prec, e.op.md.nbytes,
+                                     e.op.md.u_uniform);
+        ks_hv<T, OneSrc><<<(unsigned)e.nvec * e.nblk, 256, lds, s>>>(src);
+    } else {
+        QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
+        ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);
     }
-    k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 1, e.cs, n, nullptr);
-    k_scale<T><<<g, 256, 0, s>>>(w, e.dim, e.cs);
+    ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
+    ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src);
+    ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 1);
+    ks_update<T, OneSrc><<<nk, 256, 0, s>>>(src);
     QCM_LAUNCH_CHECK();
-    // rotate: v_{n-1} <- v_n, v_n <- w, w <- old v_{n-1}
+    // rotate: v_{n-1} <- v_n, v_n <- the new vector, next w <- old v_{n-1}
     int t = e.ivp;
     e.ivp = e.iv;
     e.iv = e.iw;
@@ -450,7 +393,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     if (b->dim < 1) return fail(QCM_EARG, "qcm_lanczos_gs: empty sector");
     const int limit = o->fixed_steps > 0 ? o->fixed_steps : o->max_iter;
     const int every = o->check_every > 0 ? o->check_every : 1;
-    size_t need = hv_setup_bytes(m, b) + engine_bytes(o->prec, 1, b->dim, limit) +
+    size_t need = hv_setup_bytes(m, b) + engine_bytes(o->prec, 1, b->d_up, b->d_dn, limit) +
                   sizeof(double) * (size_t)limit * 6 + 4096 + sizeof(double) * 64;
     *ws_needed = need;
     if (!d_ws) return QCM_OK;

@@ -16,7 +16,8 @@ struct ChainState {
     double *alpha, *beta;
     double *amax;   // running max |alpha| per chain
     double *inv;    // 1/beta (or 0 once the chain has stopped), then 1/|phi|
-    double *corr, *corr2;
+    double *corr, *corr2;   // reorthogonalisation coefficients of the last step
+    double *apre;   // alpha of the last step before its reorthogonalisation term
     double *b0sq;   // <phi|phi> of the start vector
     int32_t *len;   // number of steps recorded
     int32_t *done;  // chain stopped (breakdown or empty start)
@@ -33,12 +34,16 @@ struct Engine {
     int64_t dim;
     void *vbuf[3];
     int ivp, iv, iw;
-    double *partial;
+    double *partial;   // [nvec][nchunks]: start-vector and psi norms
+    double *pa;        // [nvec][na]: alpha partials of a step
+    double *pn;        // [nvec][3][nchunks]: norm partials of a step
+    int32_t na, rows, nblk;
+    int32_t fused;     // product fused with the first pass (rows fit LDS)
     double *scratch;
     ChainState cs;
 };
 
-size_t engine_bytes(int prec, int nvec, int64_t dim, int maxs);
+size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs);
 int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double btol, int reorth,
                 Carver &cv);
 int engine_reset(Engine &e, hipStream_t s);

@@ -1,0 +1,357 @@
+// One Lanczos step of a group of chains, as three passes over the vectors
+// (internal; used by the single-solve engine and by the batched engine).
+//
+// A group is nvec chains in one sector (vectors [nvec][dim], consecutive).
+// With v = v_n, vp = v_{n-1}, beta' = beta_{n-1}:
+//   pass 1  w = H v - beta' vp, stored; partial sums of <v, w>
+//           (fused into the product when rows of V fit in LDS; otherwise the
+//           product runs first and a chunked pass subtracts and sums);
+//   finish  alpha_n = <v, w>;
+//   pass 2  x = w - alpha_n v (not stored): partial sums of |x|^2 and, with
+//           local reorthogonalisation, of <v, x> and <vp, x>;
+//   finish  c1 = <v, x>, c2 = <vp, x>; alpha_n += c1;
+//           beta_n^2 = |x|^2 - c1^2 - c2^2 (the norm of x - c1 v - c2 vp for
+//           unit v, vp orthogonal to each other, up to terms of order c^2 eps);
+//   pass 3  v_{n+1} = (x - c1 v - c2 vp) / beta_n, rounded once to the storage
+//           type (optionally also psi += s_n v_n for the ground-state replay).
+// Every sum is a fixed-order two-level reduction (per block or per chunk of
+// kChunk elements, then per chain), so results depend only on the inputs and
+// the sector shape, not on the launch or on other groups sharing it.
+#pragma once
+
+#include "lanczos_device.h"
+
+namespace qcm {
+
+// Elements of V staged per product block when rows are short.
+constexpr int64_t kBlockElems = 2048;
+// LDS a fused product block may use (row tile + U lookup table).
+constexpr size_t kFusedLds = 144 * 1024;
+
+// Everything a step kernel needs about one group.
+struct BGroup {
+    // sector and Hamiltonian (fused product)
+    int64_t d_up, d_dn, dim;
+    const uint32_t *su, *sd;
+    const double *eu, *ed;
+    const int32_t *nhu, *nhd, *colu, *cold;
+    const double *cfu, *cfd;
+    const double *ulut;
+    double u_uniform;
+    int32_t nbytes;
+    int32_t rows;      // rows of V per product block
+    int32_t nblk;      // product blocks per vector
+    int32_t nvec, nchunks;
+    int32_t na;        // alpha partials per vector (nblk when fused, else nchunks)
+    int32_t n;         // step index
+    int32_t reorth;
+    const void *vp, *v;
+    void *w;
+    double *pa;        // [nvec][na]
+    double *pn;        // [nvec][3][nchunks]
+    double *psi;       // ground-state replay: psi += svec[n] v_n in pass 3 (or NULL)
+    const double *svec;
+    ChainState cs;
+};
+
+__device__ __forceinline__ int find_group(const int64_t *__restrict__ begin, int ng, int64_t x) {
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Work sources: many groups through a table and prefix sums of their work
+// items, or one group passed by value.
+struct TabSrc {
+    const BGroup *G;
+    const int64_t *begin;
+    int ng;
+    __device__ __forceinline__ const BGroup &at(int64_t x, int64_t *local) const {
+        const int g = find_group(begin, ng, x);
+        *local = x - begin[g];
+        return G[g];
+    }
+};
+struct OneSrc {
+    BGroup g;
+    __device__ __forceinline__ const BGroup &at(int64_t x, int64_t *local) const {
+        *local = x;
+        return g;
+    }
+};
+
+inline void row_shape(int64_t d_up, int64_t d_dn, int32_t *rows, int32_t *nblk) {
+    int64_t r = kBlockElems / (d_up > 0 ? d_up : 1);
+    if (r < 1) r = 1;
+    if (r > d_dn) r = d_dn;
+    if (r < 1) r = 1;
+    *rows = (int32_t)r;
+    *nblk = (int32_t)((d_dn + r - 1) / r);
+}
+
+inline size_t fused_lds(int64_t d_up, int32_t rows, int prec, int nbytes, double u_uniform) {
+    const size_t lut = u_uniform >= 0.0 ? 0 : sizeof(double) * 256 * (size_t)nbytes;
+    return lut + (prec == QCM_FP64 ? 8 : 4) * (size_t)rows * (size_t)d_up;
+}
+
+// The group of chains of an engine at step n (vectors from its rotation).
+BGroup engine_group(const Engine &e, int n);
+
+// pass 1, fused: w = H v - beta' vp for `rows` rows of V held in LDS; the
+// in-row term gathers there, the row-mixing term streams neighbour rows from
+// global memory, the diagonal comes from the two strings.  Sum order per
+// element: diagonal, up hops in list order, down hops in list order, then
+// -beta' vp; all FP64, rounded once.  pa != NULL: partial <v, w> per block.
+template <typename T, class Src>
+__global__ void __launch_bounds__(256) ks_hv(Src src) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double sh[256];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const int64_t vec = local / q.nblk;
+    const int64_t rb = local - vec * q.nblk;
+    const int64_t d_up = q.d_up;
+    const int64_t row0 = rb * q.rows;
+    const int64_t nr = min((int64_t)q.rows, q.d_dn - row0);
+    const int nlut = q.u_uniform >= 0.0 ? 0 : q.nbytes * 256;
+    double *lut = reinterpret_cast<double *>(smem_raw);
+    T *row = reinterpret_cast<T *>(smem_raw + sizeof(double) * nlut);
+    const T *v = (const T *)q.v + vec * q.dim;
+    const T *vp = (const T *)q.vp + vec * q.dim;
+    T *w = (T *)q.w + vec * q.dim;
+    const int n = q.n;
+    const double b = (n > 0 && q.pa) ? q.cs.beta[vec * q.cs.maxs + n - 1] : 0.0;
+    for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = q.ulut[k];
+    const int64_t nel = nr * d_up;
+    const T *vblk = v + row0 * d_up;
+    for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
+    __syncthreads();
+    const uint32_t du = (uint32_t)d_up;
+    double pa = 0.0;
+    for (int64_t e = threadIdx.x; e < nel; e += 256) {
+        const uint32_t r = (uint32_t)e / du;
+        const uint32_t iu = (uint32_t)e - r * du;
+        const int64_t idn = row0 + r;
+        const uint32_t dbl = q.su[iu] & q.sd[idn];
+        double diag = q.eu[iu] + q.ed[idn];
+        if (q.u_uniform >= 0.0) {
+            diag += q.u_uniform * (double)__popc(dbl);
+        } else {
+            for (int byte = 0; byte < q.nbytes; ++byte)
+                diag += lut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
+        }
+        const T *rrow = row + (int64_t)r * d_up;
+        const double vi = (double)rrow[iu];
+        double acc = diag * vi;
+        const int nhu = q.nhu[iu];
+        for (int s = 0; s < nhu; ++s) {
+            const int64_t ee = (int64_t)s * d_up + iu;
+            acc = fma(q.cfu[ee], (double)rrow[q.colu[ee]], acc);
+        }
+        const int nhd = q.nhd[idn];
+        for (int s = 0; s < nhd; ++s) {
+            const int64_t ee = (int64_t)s * q.d_dn + idn;
+            acc = fma(q.cfd[ee], (double)v[(int64_t)q.cold[ee] * d_up + iu], acc);
+        }
+        const int64_t i = idn * d_up + iu;
+        if (n > 0 && q.pa) acc = fma(-b, ldd(vp + i), acc);
+        const T wt = (T)acc;
+        w[i] = wt;
+        pa = fma(vi, (double)wt, pa);
+    }
+    if (q.pa) {
+        const double s = block_sum(pa, sh);
+        if (threadIdx.x == 0) q.pa[vec * q.na + rb] = s;
+    }
+}
+
+// chunk of a chunked pass
+struct ChunkAt {
+    int64_t vec, c, base;
+};
+__device__ __forceinline__ ChunkAt chunk_of(const BGroup &q, int64_t local) {
+    ChunkAt r;
+    r.vec = local / q.nchunks;
+    r.c = local - r.vec * q.nchunks;
+    r.base = r.c * kChunk;
+    return r;
+}
+
+// pass 1, after a separate product: w -= beta' vp (n > 0); partial <v, w>
+template <typename T, class Src>
+__global__ void __launch_bounds__(256) ks_sub_prev(Src src) {
+    __shared__ double sh[256];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const ChunkAt at = chunk_of(q, local);
+    const int n = q.n;
+    const double b = n > 0 ? q.cs.beta[at.vec * q.cs.maxs + n - 1] : 0.0;
+    const int64_t off = at.vec * q.dim;
+    T *w = (T *)q.w + off;
+    const T *vp = (const T *)q.vp + off;
+    const T *v = (const T *)q.v + off;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) {
+            double x = ldd(w + i);
+            if (n > 0) {
+                const T xt = (T)fma(-b, ldd(vp + i), x);
+                w[i] = xt;
+                x = (double)xt;
+            }
+            acc = fma(ldd(v + i), x, acc);
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) q.pa[at.vec * q.na + at.c] = s;
+}
+
+// pass 2: partial |x|^2 (and <v, x>, <vp, x>) with x = w - alpha_n v
+template <typename T, class Src>
+__global__ void __launch_bounds__(256) ks_norm(Src src) {
+    __shared__ double sh[256];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const ChunkAt at = chunk_of(q, local);
+    const double a = q.cs.alpha[at.vec * q.cs.maxs + q.n];
+    const int64_t off = at.vec * q.dim;
+    const T *w = (const T *)q.w + off;
+    const T *v = (const T *)q.v + off;
+    const T *vp = (const T *)q.vp + off;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (q.reorth) {
+        for (int k = threadIdx.x; k < kChunk; k += 256) {
+            const int64_t i = at.base + k;
+            if (i < q.dim) {
+                const double vi = ldd(v + i);
+                const double x = fma(-a, vi, ldd(w + i));
+                s0 = fma(x, x, s0);
+                s1 = fma(vi, x, s1);
+                s2 = fma(ldd(vp + i), x, s2);
+            }
+        }
+    } else {
+        for (int k = threadIdx.x; k < kChunk; k += 256) {
+            const int64_t i = at.base + k;
+            if (i < q.dim) {
+                const double x = fma(-a, ldd(v + i), ldd(w + i));
+                s0 = fma(x, x, s0);
+            }
+        }
+    }
+    double *pn = q.pn + at.vec * 3 * q.nchunks + at.c;
+    const double t0 = block_sum(s0, sh);
+    if (threadIdx.x == 0) pn[0] = t0;
+    if (q.reorth) {
+        const double t1 = block_sum(s1, sh);
+        const double t2 = block_sum(s2, sh);
+        if (threadIdx.x == 0) {
+            pn[q.nchunks] = t1;
+            pn[2 * q.nchunks] = t2;
+        }
+    }
+}
+
+// per-chain sums of the partials and the recurrence bookkeeping
+// mode 0: alpha_n; mode 1: reorthogonalisation terms, beta_n, breakdown.
+template <class Src>
+__global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
+    __shared__ double sh[256];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const int c = (int)local;
+    const ChainState &cs = q.cs;
+    const int n = q.n;
+    if (mode == 0) {
+        const double *p = q.pa + (int64_t)c * q.na;
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < q.na; k += 256) acc += p[k];
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) {
+            cs.alpha[(int64_t)c * cs.maxs + n] = s;
+            cs.apre[c] = s;
+            const double a = fabs(s);
+            if (a > cs.amax[c]) cs.amax[c] = a;
+        }
+        return;
+    }
+    const double *p = q.pn + (int64_t)c * 3 * q.nchunks;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = threadIdx.x; k < q.nchunks; k += 256) a0 += p[k];
+    const double s0 = block_sum(a0, sh);
+    double s1 = 0.0, s2 = 0.0;
+    if (q.reorth) {
+        for (int k = threadIdx.x; k < q.nchunks; k += 256) {
+            a1 += p[q.nchunks + k];
+            a2 += p[2 * q.nchunks + k];
+        }
+        s1 = block_sum(a1, sh);
+        s2 = block_sum(a2, sh);
+    }
+    if (threadIdx.x != 0) return;
+    if (q.reorth) cs.alpha[(int64_t)c * cs.maxs + n] += s1;
+    cs.corr[c] = s1;
+    cs.corr2[c] = s2;
+    const double bb = s0 - s1 * s1 - s2 * s2;
+    const double b = sqrt(bb > 0.0 ? bb : 0.0);
+    cs.beta[(int64_t)c * cs.maxs + n] = b;
+    if (!cs.done[c]) {
+        const double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
+        if (!(b >= cs.btol * am)) cs.done[c] = 1;
+        cs.len[c] = n + 1;
+    }
+    cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
+}
+
+// pass 3: w = (w - alpha v - c1 v - c2 vp) / beta_n; psi += svec[n] v (replay)
+template <typename T, class Src>
+__global__ void __launch_bounds__(256) ks_update(Src src) {
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const ChunkAt at = chunk_of(q, local);
+    const ChainState &cs = q.cs;
+    const double a = cs.apre[at.vec], c1 = cs.corr[at.vec], c2 = cs.corr2[at.vec];
+    const double s = cs.inv[at.vec];
+    const int64_t off = at.vec * q.dim;
+    T *w = (T *)q.w + off;
+    const T *v = (const T *)q.v + off;
+    const T *vp = (const T *)q.vp + off;
+    double *psi = q.psi;
+    const double sv = psi ? q.svec[q.n] : 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) {
+            const double vi = ldd(v + i);
+            double x = fma(-a, vi, ldd(w + i));
+            if (q.reorth) {
+                x = fma(-c1, vi, x);
+                x = fma(-c2, ldd(vp + i), x);
+            }
+            w[i] = (T)(x * s);
+            if (psi) psi[i] = fma(sv, vi, psi[i]);
+        }
+    }
+}
+
+// psi += svec[n] v_n alone (the last replay step)
+template <typename T, class Src>
+__global__ void __launch_bounds__(256) ks_accum(Src src) {
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const ChunkAt at = chunk_of(q, local);
+    const T *v = (const T *)q.v;
+    const double sv = q.svec[q.n];
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = at.base + k;
+        if (i < q.dim) q.psi[i] = fma(sv, ldd(v + i), q.psi[i]);
+    }
+}
+
+}  // namespace qcm
