@@ -496,7 +496,8 @@ static int run_round(qcm_engine *E) {
             G[ng].psi = j.psi;
             G[ng].svec = j.svec;
         }
-        lds = std::max(lds, fused_lds(p.up.d, p.e.rows, o.prec, j.md.nbytes, j.md.u_uniform));
+        lds = std::max(lds, fused_lds(p.up.d, p.e.rows, o.prec, j.md.nbytes, j.md.u_uniform,
+                                      2 * j.md.nbond));
         hvb[ng + 1] = hvb[ng] + (int64_t)p.e.nvec * p.e.nblk;
         chb[ng + 1] = chb[ng] + (int64_t)p.e.nvec * p.e.nchunks;
         cnb[ng + 1] = cnb[ng] + p.e.nvec;

@@ -177,30 +177,66 @@ int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, 
 
 using namespace qcm;
 
+// Workspace layout of qcm_green_cf: a common block, then one part at a time
+// (electron, hole) from the same offset.  Run without a base to size it.
+struct GreenCommon {
+    ModelDev md;
+    HopTables hd;
+    double *coef, *z_d, *F;
+    int32_t *lenv, *ops_d, *pidx_d;
+};
+
+static int green_common(const qcm_model *m, const qcm_basis *gs, int n, int stride, int n_z,
+                        Carver &cv, hipStream_t s, GreenCommon *c) {
+    const int npairs = n * (n + 1) / 2;
+    QCM_TRY(upload_model(m, cv, &c->md, s));
+    SpinTables dn = spin_from_basis(gs, 1);
+    QCM_TRY(build_hop_tables(c->md, dn, cv, &c->hd, s, count_bonds(m)));
+    c->coef = cv.take<double>((size_t)npairs * 2 * stride);
+    c->lenv = cv.take<int32_t>((size_t)npairs * 2);
+    c->ops_d = cv.take<int32_t>((size_t)npairs * 2);
+    c->pidx_d = cv.take<int32_t>((size_t)n * n);
+    c->z_d = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1));
+    c->F = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1) * npairs);
+    return QCM_OK;
+}
+
+static int green_part(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o, int nup2,
+                      const GreenCommon &c, Carver &cv, hipStream_t s, SpinTables *up2,
+                      HvOp *op, Engine *e) {
+    const int npairs = o->n_orb * (o->n_orb + 1) / 2;
+    QCM_TRY(build_spin_tables(m->L, nup2, cv, up2, s));
+    op->md = c.md;
+    op->up = *up2;
+    op->dn = spin_from_basis(gs, 1);
+    op->hd = c.hd;
+    op->dim = up2->d * op->dn.d;
+    QCM_TRY(build_hop_tables(c.md, *up2, cv, &op->hu, s, count_bonds(m)));
+    op->split = 0;
+    if (split_applies(m, nup2, up2->d, op->dn.d)) QCM_TRY(split_prepare(m, *op, cv, s));
+    QCM_TRY(engine_init(*e, *op, o->prec, npairs, o->max_steps, o->btol, o->reorth, cv));
+    return QCM_OK;
+}
+
 static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o,
                           int n_z) {
-    const int L = m->L;
-    const int npairs = o->n_orb * (o->n_orb + 1) / 2;
-    size_t need = model_dev_bytes(L) + hop_tables_bytes(m, gs->d_dn) + 4096;
-    size_t part_max = 0;
+    Carver dry(nullptr);
+    GreenCommon c;
+    if (green_common(m, gs, o->n_orb, 1 + 2 * o->max_steps, n_z, dry, nullptr, &c) != QCM_OK)
+        return 0;
+    size_t end = dry.off;
     for (int part = 0; part < 2; ++part) {
-        int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
-        if (nup2 < 0 || nup2 > L) continue;
-        int64_t du2 = binom(L, nup2);
-        size_t b = spin_tables_bytes(L, nup2) + hop_tables_bytes(m, du2) +
-                   engine_bytes(o->prec, npairs, du2, gs->d_dn, o->max_steps);
-        if (split_applies(m, nup2, du2, gs->d_dn)) b += split_bytes(m, nup2, du2, gs->d_dn);
-        if (b > part_max) part_max = b;
+        const int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
+        if (nup2 < 0 || nup2 > m->L) continue;
+        Carver p(nullptr);
+        p.off = dry.off;
+        SpinTables up2;
+        HvOp op;
+        Engine e;
+        if (green_part(m, gs, o, nup2, c, p, nullptr, &up2, &op, &e) != QCM_OK) return 0;
+        if (p.off > end) end = p.off;
     }
-    need += part_max;
-    const int stride = 1 + 2 * o->max_steps;
-    need += sizeof(double) * (size_t)npairs * 2 * stride + 256;
-    need += sizeof(int32_t) * (size_t)npairs * 2 + 256;
-    need += sizeof(int32_t) * (size_t)npairs * 2 + 256;
-    need += sizeof(int32_t) * (size_t)o->n_orb * o->n_orb + 256;
-    need += sizeof(double) * 2 * (size_t)n_z + 256;
-    need += sizeof(double) * 2 * (size_t)n_z * npairs + 256;
-    return need;
+    return end + 256;
 }
 
 extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const double *d_gs,
@@ -251,19 +287,11 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
             }
     }
     Carver cv(d_ws);
-    ModelDev md;
-    QCM_TRY(upload_model(m, cv, &md, s));
-    const int nb = count_bonds(m);
-    SpinTables dn = spin_from_basis(gs, 1);
+    GreenCommon c;
+    QCM_TRY(green_common(m, gs, n, stride, n_z, cv, s, &c));
     SpinTables upg = spin_from_basis(gs, 0);
-    HopTables hd;
-    QCM_TRY(build_hop_tables(md, dn, cv, &hd, s, nb));
-    double *coef = cv.take<double>((size_t)npairs * 2 * stride);
-    int32_t *lenv = cv.take<int32_t>((size_t)npairs * 2);
-    int32_t *ops_d = cv.take<int32_t>((size_t)npairs * 2);
-    int32_t *pidx_d = cv.take<int32_t>((size_t)n * n);
-    double *z_d = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1));
-    double *F = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1) * npairs);
+    double *coef = c.coef, *z_d = c.z_d, *F = c.F;
+    int32_t *lenv = c.lenv, *ops_d = c.ops_d, *pidx_d = c.pidx_d;
     QCM_HIP(hipMemcpyAsync(ops_d, ops.data(), sizeof(int32_t) * ops.size(), hipMemcpyHostToDevice, s));
     QCM_HIP(hipMemcpyAsync(pidx_d, pidx.data(), sizeof(int32_t) * pidx.size(),
                            hipMemcpyHostToDevice, s));
@@ -279,18 +307,9 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         }
         cv.off = part_base;
         SpinTables up2;
-        QCM_TRY(build_spin_tables(L, nup2, cv, &up2, s));
         HvOp op;
-        op.md = md;
-        op.up = up2;
-        op.dn = dn;
-        op.hd = hd;
-        op.dim = up2.d * dn.d;
-        QCM_TRY(build_hop_tables(md, up2, cv, &op.hu, s, nb));
-        op.split = 0;
-        if (split_applies(m, nup2, up2.d, dn.d)) QCM_TRY(split_prepare(m, op, cv, s));
         Engine e;
-        QCM_TRY(engine_init(e, op, o->prec, npairs, maxs, o->btol, o->reorth, cv));
+        QCM_TRY(green_part(m, gs, o, nup2, c, cv, s, &up2, &op, &e));
         QCM_TRY(engine_reset(e, s));
         QCM_TRY(apply_ops_launch(e, d_gs, gs->d_up, upg, up2, part, ops_d, s));
         QCM_TRY(engine_normalize_from_partials(e, s));

@@ -43,6 +43,7 @@ size_t model_dev_bytes(int L) {
     cv.take<double>(L * L);
     cv.take<double>(nbytes * 256);
     cv.take<double>(nbytes * 256);
+    cv.take<double>(2 * L * L);
     return cv.off + 256;
 }
 
@@ -60,13 +61,14 @@ int upload_model(const qcm_model *m, Carver &cv, ModelDev *md, hipStream_t s) {
     md->bond_t = cv.take<double>(L * L);
     md->ulut = cv.take<double>(md->nbytes * 256);
     md->tlut = cv.take<double>(md->nbytes * 256);
+    md->ctab = cv.take<double>(2 * L * L);
     double u0 = m->U[0];
     md->u_uniform = u0;
     for (int k = 0; k < L; ++k)
         if (m->U[k] != u0 || u0 < 0) md->u_uniform = -1.0;
     if (!cv.base) return QCM_OK;
     // pack everything into one host staging block laid out like the device block
-    size_t total = (char *)(md->tlut + md->nbytes * 256) - (char *)md->t;
+    size_t total = (char *)(md->ctab + 2 * L * L) - (char *)md->t;
     std::vector<char> host(total, 0);
     auto at = [&](void *dev) { return host.data() + ((char *)dev - (char *)md->t); };
     memcpy(at(md->t), m->t, sizeof(double) * L * L);
@@ -81,6 +83,11 @@ int upload_model(const qcm_model *m, Carver &cv, ModelDev *md, hipStream_t s) {
                 bt[nb] = m->t[a * L + b];
                 ++nb;
             }
+    double *ct = (double *)at(md->ctab);
+    for (int k = 0; k < nb; ++k) {
+        ct[2 * k] = bt[k];
+        ct[2 * k + 1] = -bt[k];
+    }
     double *ul = (double *)at(md->ulut), *tl = (double *)at(md->tlut);
     for (int byte = 0; byte < md->nbytes; ++byte)
         for (int x = 0; x < 256; ++x) {
@@ -107,6 +114,7 @@ size_t hop_tables_bytes(const qcm_model *m, int64_t d) {
     cv.take<int32_t>((size_t)W * d);
     cv.take<double>((size_t)W * d);
     cv.take<double>(d);
+    if (d < 65536) cv.take<uint32_t>((size_t)W * d);
     return cv.off + 256;
 }
 
@@ -121,7 +129,8 @@ __global__ void k_build_hops(int64_t d, int rowmajor, int W, int L, int l_lo, in
                              const int32_t *__restrict__ bb, const double *__restrict__ bt,
                              const double *__restrict__ tlut, int nbytes,
                              int32_t *__restrict__ nh, int32_t *__restrict__ col,
-                             double *__restrict__ coef, double *__restrict__ ediag) {
+                             double *__restrict__ coef, double *__restrict__ ediag,
+                             uint32_t *__restrict__ pk) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d) return;
     uint32_t x = states[i];
@@ -135,8 +144,10 @@ __global__ void k_build_hops(int64_t d, int rowmajor, int W, int L, int l_lo, in
         uint32_t between = ((mb - 1u) & ~(ma | (ma - 1u)));  // a < b: bits a+1..b-1
         int m = __popc(x & between);
         const int64_t at = rowmajor ? i * W + n : (int64_t)n * d + i;
-        col[at] = spin_rank(rlo, rhi, l_lo, l_hi, y);
+        const int32_t c = spin_rank(rlo, rhi, l_lo, l_hi, y);
+        col[at] = c;
         coef[at] = (m & 1) ? -bt[k] : bt[k];
+        if (pk) pk[at] = (uint32_t)c | ((uint32_t)(2 * k + (m & 1)) << 16);
         ++n;
     }
     nh[i] = n;
@@ -155,12 +166,16 @@ int build_hop_tables(const ModelDev &md, const SpinTables &st, Carver &cv, HopTa
     ht->col = cv.take<int32_t>((size_t)W * st.d);
     ht->coef = cv.take<double>((size_t)W * st.d);
     ht->ediag = cv.take<double>(st.d);
+    // packed entries (column | index of +-t_ab in the model's ctab << 16) when
+    // labels fit 16 bits; slot-major layout only
+    ht->pk = (!rowmajor && st.d < 65536) ? cv.take<uint32_t>((size_t)W * st.d) : nullptr;
     if (!cv.base) return QCM_OK;
     const int B = 256;
     k_build_hops<<<ceil_div(st.d, B), B, 0, s>>>(st.d, ht->rowmajor, W, st.L, st.l_lo, st.l_hi, st.states,
                                                   st.rank_lo, st.rank_hi, nbond_host, md.bond_a,
                                                   md.bond_b, md.bond_t, md.tlut, md.nbytes,
-                                                  ht->nh, ht->col, ht->coef, ht->ediag);
+                                                  ht->nh, ht->col, ht->coef, ht->ediag,
+                                                  rowmajor ? nullptr : ht->pk);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }
@@ -294,10 +309,12 @@ int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStr
 }
 
 // Sizes and set-up shared by every entry point that applies H.
+// The bytes hv_setup carves: the same carving run without a base (no launch).
 size_t hv_setup_bytes(const qcm_model *m, const qcm_basis *b) {
-    size_t n = model_dev_bytes(m->L) + hop_tables_bytes(m, b->d_up) + hop_tables_bytes(m, b->d_dn);
-    if (split_applies(m, b->n_up, b->d_up, b->d_dn)) n += split_bytes(m, b->n_up, b->d_up, b->d_dn);
-    return n;
+    Carver dry(nullptr);
+    HvOp op;
+    if (hv_setup(m, b, dry, &op, nullptr) != QCM_OK) return 0;
+    return dry.off + 256;
 }
 
 int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipStream_t s) {

@@ -154,7 +154,7 @@ size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs) {
     int64_t nch = (int64_t)ceil_div(dim, kChunk);
     if (nch < 1) nch = 1;
     int32_t rows, nblk;
-    row_shape(d_up, d_dn, &rows, &nblk);
+    row_shape(d_up, d_dn, prec, &rows, &nblk);
     cv.take<double>((size_t)nvec * nch);
     cv.take<double>((size_t)nvec * (nblk > nch ? nblk : nch));
     cv.take<double>((size_t)nvec * 3 * nch);
@@ -180,9 +180,10 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.vbuf[2] = vecs + 2 * vb;
     e.nchunks = (int)ceil_div(e.dim, kChunk);
     if (e.nchunks < 1) e.nchunks = 1;
-    row_shape(op.up.d, op.dn.d, &e.rows, &e.nblk);
-    e.fused = !op.split &&
-              fused_lds(op.up.d, e.rows, prec, op.md.nbytes, op.md.u_uniform) <= kFusedLds;
+    row_shape(op.up.d, op.dn.d, prec, &e.rows, &e.nblk);
+    e.fused = !op.split && op.up.d < 65536 &&
+              fused_lds(op.up.d, e.rows, prec, op.md.nbytes, op.md.u_uniform,
+                        2 * op.md.nbond) <= kFusedLds;
     e.na = e.fused ? e.nblk : e.nchunks;
     e.partial = cv.take<double>((size_t)nvec * e.nchunks);
     e.pa = cv.take<double>((size_t)nvec * (e.nblk > e.nchunks ? e.nblk : e.nchunks));
@@ -239,6 +240,9 @@ BGroup engine_group(const Engine &e, int n) {
     g.cfu = op.hu.coef;
     g.cfd = op.hd.coef;
     g.ulut = op.md.ulut;
+    g.pku = op.hu.pk;
+    g.ctab = op.md.ctab;
+    g.nctab = 2 * op.md.nbond;
     g.u_uniform = op.md.u_uniform;
     g.nbytes = op.md.nbytes;
     g.rows = e.rows;
@@ -265,7 +269,7 @@ static int step_t(Engine &e, int n, hipStream_t s) {
     const unsigned nk = (unsigned)e.nvec * e.nchunks;
     if (e.fused) {
         const size_t lds = fused_lds(e.op.up.d, e.rows, e.prec, e.op.md.nbytes,
-                                     e.op.md.u_uniform);
+                                     e.op.md.u_uniform, 2 * e.op.md.nbond);
         ks_hv<T, OneSrc><<<(unsigned)e.nvec * e.nblk, 256, lds, s>>>(src);
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
@@ -393,8 +397,24 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     if (b->dim < 1) return fail(QCM_EARG, "qcm_lanczos_gs: empty sector");
     const int limit = o->fixed_steps > 0 ? o->fixed_steps : o->max_iter;
     const int every = o->check_every > 0 ? o->check_every : 1;
-    size_t need = hv_setup_bytes(m, b) + engine_bytes(o->prec, 1, b->d_up, b->d_dn, limit) +
-                  sizeof(double) * (size_t)limit * 6 + 4096 + sizeof(double) * 64;
+    // the workspace is laid out by one function, run first without a base to
+    // size it (no launch) and then on the workspace
+    HvOp op;
+    Engine e;
+    double *svec = nullptr, *work = nullptr, *dscal = nullptr;
+    GsStatus *status = nullptr;
+    auto layout = [&](Carver &cv, hipStream_t st) -> int {
+        QCM_TRY(hv_setup(m, b, cv, &op, st));
+        QCM_TRY(engine_init(e, op, o->prec, 1, limit, o->btol, o->reorth, cv));
+        svec = cv.take<double>(limit);
+        work = cv.take<double>((size_t)limit * 5);
+        status = cv.take<GsStatus>(1);
+        dscal = cv.take<double>(64);
+        return QCM_OK;
+    };
+    Carver dry(nullptr);
+    QCM_TRY(layout(dry, nullptr));
+    const size_t need = dry.off + 256;
     *ws_needed = need;
     if (!d_ws) return QCM_OK;
     if (!h_out) return fail(QCM_EARG, "qcm_lanczos_gs: h_out is NULL");
@@ -402,14 +422,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
         return fail(QCM_EWORKSPACE, "qcm_lanczos_gs: workspace %zu < %zu", ws_bytes, need);
     hipStream_t s = as_stream(stream);
     Carver cv(d_ws);
-    HvOp op;
-    QCM_TRY(hv_setup(m, b, cv, &op, s));
-    Engine e;
-    QCM_TRY(engine_init(e, op, o->prec, 1, limit, o->btol, o->reorth, cv));
-    double *svec = cv.take<double>(limit);
-    double *work = cv.take<double>((size_t)limit * 5);
-    GsStatus *status = cv.take<GsStatus>(1);
-    double *dscal = cv.take<double>(64);
+    QCM_TRY(layout(cv, s));
 
     // first pass: coefficients
     QCM_TRY(engine_reset(e, s));

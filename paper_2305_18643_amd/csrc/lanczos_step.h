@@ -23,9 +23,9 @@
 
 namespace qcm {
 
-// Elements of V staged per product block when rows are short.
-constexpr int64_t kBlockElems = 2048;
-// LDS a fused product block may use (row tile + U lookup table).
+// Elements of V a product block stages in LDS (at least one whole row).
+constexpr int64_t kTileElems = 2048;
+// LDS a fused product block may use (row tile + lookup tables).
 constexpr size_t kFusedLds = 144 * 1024;
 
 // Everything a step kernel needs about one group.
@@ -37,8 +37,11 @@ struct BGroup {
     const int32_t *nhu, *nhd, *colu, *cold;
     const double *cfu, *cfd;
     const double *ulut;
+    const uint32_t *pku;   // packed up hops: column | (ctab index << 16), slot-major
+    const double *ctab;    // hop coefficients by index (+-t_ab)
     double u_uniform;
     int32_t nbytes;
+    int32_t nctab;
     int32_t rows;      // rows of V per product block
     int32_t nblk;      // product blocks per vector
     int32_t nvec, nchunks;
@@ -86,8 +89,9 @@ struct OneSrc {
     }
 };
 
-inline void row_shape(int64_t d_up, int64_t d_dn, int32_t *rows, int32_t *nblk) {
-    int64_t r = kBlockElems / (d_up > 0 ? d_up : 1);
+inline void row_shape(int64_t d_up, int64_t d_dn, int prec, int32_t *rows, int32_t *nblk) {
+    (void)prec;
+    int64_t r = kTileElems / (d_up > 0 ? d_up : 1);
     if (r < 1) r = 1;
     if (r > d_dn) r = d_dn;
     if (r < 1) r = 1;
@@ -95,19 +99,24 @@ inline void row_shape(int64_t d_up, int64_t d_dn, int32_t *rows, int32_t *nblk) 
     *nblk = (int32_t)((d_dn + r - 1) / r);
 }
 
-inline size_t fused_lds(int64_t d_up, int32_t rows, int prec, int nbytes, double u_uniform) {
+inline size_t fused_lds(int64_t d_up, int32_t rows, int prec, int nbytes, double u_uniform,
+                        int nctab) {
     const size_t lut = u_uniform >= 0.0 ? 0 : sizeof(double) * 256 * (size_t)nbytes;
-    return lut + (prec == QCM_FP64 ? 8 : 4) * (size_t)rows * (size_t)d_up;
+    return lut + sizeof(double) * (size_t)nctab +
+           (prec == QCM_FP64 ? 8 : 4) * (size_t)rows * (size_t)d_up;
 }
 
 // The group of chains of an engine at step n (vectors from its rotation).
 BGroup engine_group(const Engine &e, int n);
 
-// pass 1, fused: w = H v - beta' vp for `rows` rows of V held in LDS; the
-// in-row term gathers there, the row-mixing term streams neighbour rows from
-// global memory, the diagonal comes from the two strings.  Sum order per
-// element: diagonal, up hops in list order, down hops in list order, then
-// -beta' vp; all FP64, rounded once.  pa != NULL: partial <v, w> per block.
+// pass 1, fused: w = H v - beta' vp for `rows` rows of V held in LDS; one
+// thread per element.  The in-row term gathers inside the LDS rows through
+// the packed up-hop entries (coefficients from a small LDS table); the
+// row-mixing term streams neighbour rows from global memory; the diagonal
+// comes from the two strings.  Hop loads are issued four at a time so that
+// several are in flight per thread.  Sum order per element: diagonal, up hops
+// in list order, down hops in list order, then -beta' vp; all FP64, rounded
+// once.  pa != NULL: partial <v, w> per block.
 template <typename T, class Src>
 __global__ void __launch_bounds__(256) ks_hv(Src src) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -116,18 +125,20 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     const BGroup &q = src.at(blockIdx.x, &local);
     const int64_t vec = local / q.nblk;
     const int64_t rb = local - vec * q.nblk;
-    const int64_t d_up = q.d_up;
+    const int64_t d_up = q.d_up, d_dn = q.d_dn;
     const int64_t row0 = rb * q.rows;
-    const int64_t nr = min((int64_t)q.rows, q.d_dn - row0);
+    const int64_t nr = min((int64_t)q.rows, d_dn - row0);
     const int nlut = q.u_uniform >= 0.0 ? 0 : q.nbytes * 256;
     double *lut = reinterpret_cast<double *>(smem_raw);
-    T *row = reinterpret_cast<T *>(smem_raw + sizeof(double) * nlut);
+    double *ct = lut + nlut;
+    T *row = reinterpret_cast<T *>(ct + q.nctab);
     const T *v = (const T *)q.v + vec * q.dim;
     const T *vp = (const T *)q.vp + vec * q.dim;
     T *w = (T *)q.w + vec * q.dim;
-    const int n = q.n;
-    const double b = (n > 0 && q.pa) ? q.cs.beta[vec * q.cs.maxs + n - 1] : 0.0;
+    const bool sub = q.n > 0 && q.pa;
+    const double b = sub ? q.cs.beta[vec * q.cs.maxs + q.n - 1] : 0.0;
     for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = q.ulut[k];
+    for (int k = threadIdx.x; k < q.nctab; k += 256) ct[k] = q.ctab[k];
     const int64_t nel = nr * d_up;
     const T *vblk = v + row0 * d_up;
     for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
@@ -146,28 +157,56 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             for (int byte = 0; byte < q.nbytes; ++byte)
                 diag += lut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
         }
-        const T *rrow = row + (int64_t)r * d_up;
-        const double vi = (double)rrow[iu];
+        const T *rr = row + (int64_t)r * d_up;
+        const double vi = (double)rr[iu];
         double acc = diag * vi;
+        // in-row term
         const int nhu = q.nhu[iu];
-        for (int s = 0; s < nhu; ++s) {
-            const int64_t ee = (int64_t)s * d_up + iu;
-            acc = fma(q.cfu[ee], (double)rrow[q.colu[ee]], acc);
+        const uint32_t *pp = q.pku + iu;
+        int s = 0;
+        for (; s + 4 <= nhu; s += 4) {
+            const uint32_t p0 = pp[(int64_t)s * d_up], p1 = pp[(int64_t)(s + 1) * d_up];
+            const uint32_t p2 = pp[(int64_t)(s + 2) * d_up], p3 = pp[(int64_t)(s + 3) * d_up];
+            const double x0 = (double)rr[p0 & 0xffffu], x1 = (double)rr[p1 & 0xffffu];
+            const double x2 = (double)rr[p2 & 0xffffu], x3 = (double)rr[p3 & 0xffffu];
+            acc = fma(ct[p0 >> 16], x0, acc);
+            acc = fma(ct[p1 >> 16], x1, acc);
+            acc = fma(ct[p2 >> 16], x2, acc);
+            acc = fma(ct[p3 >> 16], x3, acc);
         }
+        for (; s < nhu; ++s) {
+            const uint32_t p0 = pp[(int64_t)s * d_up];
+            acc = fma(ct[p0 >> 16], (double)rr[p0 & 0xffffu], acc);
+        }
+        // row-mixing term
         const int nhd = q.nhd[idn];
-        for (int s = 0; s < nhd; ++s) {
-            const int64_t ee = (int64_t)s * q.d_dn + idn;
-            acc = fma(q.cfd[ee], (double)v[(int64_t)q.cold[ee] * d_up + iu], acc);
+        const T *vc = v + iu;
+        s = 0;
+        for (; s + 4 <= nhd; s += 4) {
+            const int64_t e0 = (int64_t)s * d_dn + idn, e1 = e0 + d_dn;
+            const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
+            const double x0 = (double)vc[(int64_t)q.cold[e0] * d_up];
+            const double x1 = (double)vc[(int64_t)q.cold[e1] * d_up];
+            const double x2 = (double)vc[(int64_t)q.cold[e2] * d_up];
+            const double x3 = (double)vc[(int64_t)q.cold[e3] * d_up];
+            acc = fma(q.cfd[e0], x0, acc);
+            acc = fma(q.cfd[e1], x1, acc);
+            acc = fma(q.cfd[e2], x2, acc);
+            acc = fma(q.cfd[e3], x3, acc);
+        }
+        for (; s < nhd; ++s) {
+            const int64_t e0 = (int64_t)s * d_dn + idn;
+            acc = fma(q.cfd[e0], (double)vc[(int64_t)q.cold[e0] * d_up], acc);
         }
         const int64_t i = idn * d_up + iu;
-        if (n > 0 && q.pa) acc = fma(-b, ldd(vp + i), acc);
+        if (sub) acc = fma(-b, ldd(vp + i), acc);
         const T wt = (T)acc;
         w[i] = wt;
         pa = fma(vi, (double)wt, pa);
     }
     if (q.pa) {
-        const double s = block_sum(pa, sh);
-        if (threadIdx.x == 0) q.pa[vec * q.na + rb] = s;
+        const double t = block_sum(pa, sh);
+        if (threadIdx.x == 0) q.pa[vec * q.na + rb] = t;
     }
 }
 

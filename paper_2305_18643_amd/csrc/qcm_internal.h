@@ -100,6 +100,7 @@ struct ModelDev {
     double *bond_t;       // [nbond]
     double *ulut;         // [nbytes][256]: sum of U_k over set bits of one byte
     double *tlut;         // [nbytes][256]: sum of t_kk over set bits of one byte
+    double *ctab;         // [2*nbond]: t_b, -t_b of bond b (hop coefficients by index)
     int32_t nbytes;       // ceil(L/8)
     double u_uniform;     // >= 0 if all U_k equal (then U * popcount), else -1
 };
@@ -112,6 +113,7 @@ struct HopTables {
     int32_t *col;         // [width * d]
     double *coef;         // [width * d]  sign * t_ab
     double *ediag;        // [d]  sum_k t_kk n_k
+    uint32_t *pk = nullptr;  // [width * d] col | (ctab index << 16), slot-major; d < 65536
     int64_t *off = nullptr;  // row-major layout only: col * (length of the other spin)
 };
 
