@@ -381,7 +381,11 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_team(
 
 // pass B of the team layout: W += K_dn V on column slabs, hopping lists
 // row-contiguous and wave-uniform (scalar loads), 8 neighbour segments in
-// flight per wave.
+// flight per wave.  Within a slab the rows are taken in row_order: grouped by
+// the popcount of the high half of the down string.  Hops inside either half
+// keep that popcount, so the rows an XCD has in flight find most of their
+// neighbour segments among rows of the same group, a working set that fits
+// its L2 (4,900 rows x 512 B for the 4x4 FP64 slab of the largest group).
 // Row-major list of the down hops of every row, as element offsets of the
 // neighbour row (j_dn * d_up) and coefficients, padded to the width W.
 __global__ void k_row_offsets(int64_t d_dn, int W, int64_t d_up, const int32_t *__restrict__ col,
@@ -394,7 +398,8 @@ template <typename T, int RI>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
     const int64_t *__restrict__ offs, const double *__restrict__ cfd, const T *__restrict__ v,
-    T *__restrict__ w, const int R, const int64_t nrb, const int64_t total, const int64_t per) {
+    T *__restrict__ w, const int R, const int64_t nrb, const int64_t total, const int64_t per,
+    const int32_t *__restrict__ order) {
     const int64_t p = blockIdx.x;
     const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
     if (lg >= total) return;
@@ -417,7 +422,7 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
         for (int q = 0; q < RI; ++q) {
             const int64_t r = rb * R + k + q;
             const bool ok = r < d_dn;
-            rr[q] = ok ? r : rb * R + k;
+            rr[q] = ok ? order[r] : 0;
             nh[q] = ok ? nhd[rr[q]] : 0;
             nmax = nh[q] > nmax ? nh[q] : nmax;
             acc[q] = (ok && cok) ? (double)ww[rr[q] * d_up + c0] : 0.0;
@@ -534,7 +539,8 @@ static int hv3_launch_t(const HvOp &op, const SplitTables &st, const HopTables &
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
     k_hv_down_acc<T, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
-                                           hd_rm.coef, (const T *)v, (T *)w, R, nrb, total, per);
+                                           hd_rm.coef, (const T *)v, (T *)w, R, nrb, total, per,
+                                           op.row_order);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }
@@ -582,6 +588,7 @@ size_t split_bytes(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn) {
     cv.take<double>(W * d_dn);
     cv.take<double>(d_dn);
     cv.take<int64_t>(W * d_dn);
+    cv.take<int32_t>(d_dn);
     return cv.off + 1024;
 }
 
@@ -590,6 +597,25 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
     QCM_TRY(build_split_tables(m, op.up.N, cv, &st, s));
     QCM_TRY(build_hop_tables(op.md, op.dn, cv, &op.hd_rm, s, count_bonds(m), 1));
     QCM_TRY(build_row_offsets(op.hd_rm, op.up.d, cv, s));
+    // rows grouped by the popcount of the high half of the down string, so
+    // that the rows in flight and their in-class neighbours share L2
+    op.row_order = cv.take<int32_t>(op.dn.d);
+    if (cv.base) {
+        const int L = op.dn.L, N = op.dn.N, llo = (L + 1) / 2;
+        std::vector<int32_t> ord;
+        ord.reserve(op.dn.d);
+        for (int k = 0; k <= L - llo; ++k) {
+            int32_t idx = 0;
+            for (uint64_t x = 0; x < (uint64_t(1) << L); ++x) {
+                if (__builtin_popcountll(x) != N) continue;
+                if (__builtin_popcountll(x >> llo) == k) ord.push_back(idx);
+                ++idx;
+            }
+        }
+        if ((int64_t)ord.size() != op.dn.d) return fail(QCM_EARG, "row order size");
+        QCM_HIP(hipMemcpyAsync(op.row_order, ord.data(), sizeof(int32_t) * ord.size(),
+                               hipMemcpyHostToDevice, s));
+    }
     op.split = 1;
     op.split_blob = st.blob;
     op.split_lo = st.l_lo;

@@ -135,6 +135,7 @@ struct HvOp {
     int split = 0;
     void *split_blob = nullptr;   // SplitTables of the up spin (packed, device)
     HopTables hd_rm;              // down hops, row-major, with neighbour offsets
+    int32_t *row_order = nullptr; // rows of V in the order the row-mixing pass takes them
     int32_t split_lo = 0;
     unsigned char split_lay[128]; // SplitLayout of the blob
 };
