@@ -206,3 +206,27 @@ def test_engine_oracle_parity(q):
                 line += f", max |dG| {err:.1e}"
                 assert err <= (1e-4 if prec == "fp64" else 5e-3)
             print(line, flush=True)
+
+
+def test_serving_loop_parity(q):
+    """Requests arriving as a Poisson stream through the serving loop: each
+    result equals the same request solved alone (bitwise) and the oracle's E0
+    (FP64 engine: relative 1e-10)."""
+    from paper_2305_18643_amd import serving
+    reqs = [m for m in synth.serving_requests(2305, 60) if m.L <= 10][:16]
+    arr = serving.poisson_arrivals(40.0, len(reqs), seed=11)
+    kw = dict(prec="fp64", gf_steps=60, z=Z, max_jobs=8)
+    eng = q.Engine(1 << 30, **kw)
+    rep = serving.serve(eng, [_spec(q, m, i) for i, m in enumerate(reqs)], arr)
+    eng.close()
+    print(f"served {len(rep.results)} requests, max in flight {rep.max_in_flight}, "
+          f"p50 {rep.percentile(50):.3f} s, p99 {rep.percentile(99):.3f} s", flush=True)
+    assert sorted(rep.results) == list(range(len(reqs)))
+    assert rep.max_in_flight > 1
+    for i, m in enumerate(reqs):
+        alone_eng = q.Engine(1 << 30, **dict(kw, max_jobs=1))
+        alone = _run_all(alone_eng, [_spec(q, m, i)])[i]
+        alone_eng.close()
+        _same(alone, rep.results[i])
+        ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn)
+        assert abs(alone["e0"] - ro["e0"]) <= 1e-10 * abs(ro["e0"])
