@@ -130,6 +130,23 @@ int qcm_sector_basis(int32_t L, int32_t n_up, int32_t n_dn, void *d_ws, size_t w
 int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, const void *d_v, void *d_w,
            void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream);
 
+/*
+ * Plans: the tables of qcm_hv built once and applied many times.
+ * qcm_hv_plan_create builds the model- and sector-dependent tables into d_ws
+ * (size query with d_ws == NULL, as everywhere) and returns a host handle;
+ * the caller keeps d_ws and the basis alive and unmodified while the plan is
+ * used.  qcm_hv_plan_apply computes w = H v for nvec consecutive vectors of
+ * length dim (d_v, d_w device, in the plan's precision, not overlapping), the
+ * same product and arithmetic as qcm_hv, with no table work.  Asynchronous.
+ * qcm_hv_plan_destroy frees the handle (not d_ws).
+ */
+typedef struct qcm_hv_plan qcm_hv_plan;   /* opaque */
+int qcm_hv_plan_create(const qcm_model *m, const qcm_basis *b, int32_t prec, void *d_ws,
+                       size_t ws_bytes, size_t *ws_needed, void *stream, qcm_hv_plan **out);
+int qcm_hv_plan_apply(const qcm_hv_plan *p, const void *d_v, void *d_w, int32_t nvec,
+                      void *stream);
+int qcm_hv_plan_destroy(qcm_hv_plan *p);
+
 /* Options of the Lanczos ground-state solver. */
 typedef struct qcm_lanczos_opts {
     int32_t max_iter;     /* cap on Lanczos steps (the paper's default is 600) */

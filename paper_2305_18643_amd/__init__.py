@@ -2,10 +2,10 @@
 (arXiv 2305.18643): sector basis, H.v, Lanczos ground state, continued-
 fraction Green function and CPT, as hand-written HIP kernels for gfx950
 behind a C ABI (include/qcm.h).  This package is the thin Python binding."""
-from ._binding import (EXPORTS, PREC, QCM_FP32V, QCM_FP64, Engine, HostModel, JobSpec, QcmError,
-                       SectorBasis, as_model, batch_bytes, batch_solve, cpt_gk, green_cf, hv,
+from ._binding import (EXPORTS, PREC, QCM_FP32V, QCM_FP64, Engine, HostModel, HvPlan, JobSpec,
+                       QcmError, SectorBasis, as_model, batch_bytes, batch_solve, cpt_gk, green_cf, hv,
                        lanczos_gs, load_library, sector_basis)
 
-__all__ = ["EXPORTS", "PREC", "QCM_FP32V", "QCM_FP64", "Engine", "HostModel", "JobSpec",
+__all__ = ["EXPORTS", "PREC", "QCM_FP32V", "QCM_FP64", "Engine", "HostModel", "HvPlan", "JobSpec",
            "QcmError", "SectorBasis", "as_model", "batch_bytes", "batch_solve", "cpt_gk",
            "green_cf", "hv", "lanczos_gs", "load_library", "sector_basis"]

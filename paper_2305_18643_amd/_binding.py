@@ -104,7 +104,8 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_lanczos_default_opts", "qcm_lanczos_gs", "qcm_green_cf", "qcm_cpt_gk",
            "qcm_engine_default_opts", "qcm_engine_create", "qcm_engine_destroy",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
-           "qcm_engine_info", "qcm_batch_solve"]
+           "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
+           "qcm_hv_plan_destroy"]
 
 _lib = None
 
@@ -142,6 +143,12 @@ def load_library(path: str = LIB_PATH):
                                ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, _c_d, vp,
                                vp, sz, _c_sz, vp]
     P = ctypes.POINTER
+    lib.qcm_hv_plan_create.restype = ctypes.c_int
+    lib.qcm_hv_plan_create.argtypes = [P(Model), P(Basis), ctypes.c_int32, vp, sz, _c_sz, vp, P(vp)]
+    lib.qcm_hv_plan_apply.restype = ctypes.c_int
+    lib.qcm_hv_plan_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.qcm_hv_plan_destroy.restype = ctypes.c_int
+    lib.qcm_hv_plan_destroy.argtypes = [vp]
     lib.qcm_engine_default_opts.restype = ctypes.c_int
     lib.qcm_engine_default_opts.argtypes = [P(EngineOpts)]
     lib.qcm_engine_create.restype = ctypes.c_int
@@ -281,6 +288,46 @@ def hv(model, basis: SectorBasis, v, w=None, stream=None, ws=None):
     _check(lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(basis.c), prec, _ptr(v), _ptr(w), _ptr(ws),
                       ws.numel(), ctypes.byref(need), _stream(torch, stream)))
     return w
+
+
+class HvPlan:
+    """Tables of H.v built once (qcm_hv_plan_*); call it as plan(v, w)."""
+
+    def __init__(self, model, basis: SectorBasis, prec="fp64", stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.m = as_model(model)
+        self.basis = basis
+        self.prec = PREC[prec]
+        need = ctypes.c_size_t(0)
+        _check(self.lib.qcm_hv_plan_create(ctypes.byref(self.m.c), ctypes.byref(basis.c),
+                                           self.prec, None, 0, ctypes.byref(need), None, None))
+        self.ws = _workspace(torch, need.value, basis.device)
+        self.h = ctypes.c_void_p()
+        _check(self.lib.qcm_hv_plan_create(ctypes.byref(self.m.c), ctypes.byref(basis.c),
+                                           self.prec, _ptr(self.ws), self.ws.numel(),
+                                           ctypes.byref(need), _stream(torch, stream),
+                                           ctypes.byref(self.h)))
+
+    def __call__(self, v, w, nvec=1, stream=None):
+        torch = _torch()
+        want = torch.float64 if self.prec == QCM_FP64 else torch.float32
+        if v.dtype != want or w.dtype != want or v.numel() != nvec * self.basis.dim or \
+                w.numel() != v.numel():
+            raise ValueError("v, w must be nvec * dim elements of the plan's precision")
+        _check(self.lib.qcm_hv_plan_apply(self.h, _ptr(v), _ptr(w), nvec, _stream(torch, stream)))
+        return w
+
+    def close(self):
+        if self.h:
+            _check(self.lib.qcm_hv_plan_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lanczos_gs(model, basis: SectorBasis, *, max_iter=600, fixed_steps=0, want_vector=True,

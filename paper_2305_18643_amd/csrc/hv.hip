@@ -366,3 +366,54 @@ extern "C" int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, cons
     QCM_TRY(hv_setup(m, b, cv, &op, s));
     return hv_launch(op, prec, d_v, d_w, 1, s);
 }
+
+// ---------------------------------------------------------------- plans
+
+struct qcm_hv_plan {
+    qcm::HvOp op;
+    int32_t prec;
+    int64_t dim;
+};
+
+extern "C" int qcm_hv_plan_create(const qcm_model *m, const qcm_basis *b, int32_t prec,
+                                  void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream,
+                                  qcm_hv_plan **out) {
+    if (!ws_needed) return fail(QCM_EARG, "qcm_hv_plan_create: ws_needed is NULL");
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(b, m->L));
+    if (prec != QCM_FP64 && prec != QCM_FP32V)
+        return fail(QCM_EARG, "qcm_hv_plan_create: bad prec %d", prec);
+    const size_t need = hv_setup_bytes(m, b);
+    *ws_needed = need;
+    if (!d_ws) return QCM_OK;
+    if (!out) return fail(QCM_EARG, "qcm_hv_plan_create: out is NULL");
+    *out = nullptr;
+    if (ws_bytes < need)
+        return fail(QCM_EWORKSPACE, "qcm_hv_plan_create: workspace %zu < %zu", ws_bytes, need);
+    qcm_hv_plan *p = new qcm_hv_plan();
+    Carver cv(d_ws);
+    const int rc = hv_setup(m, b, cv, &p->op, as_stream(stream));
+    if (rc != QCM_OK) {
+        delete p;
+        return rc;
+    }
+    p->prec = prec;
+    p->dim = b->dim;
+    *out = p;
+    return QCM_OK;
+}
+
+extern "C" int qcm_hv_plan_apply(const qcm_hv_plan *p, const void *d_v, void *d_w, int32_t nvec,
+                                 void *stream) {
+    if (!p) return fail(QCM_EARG, "qcm_hv_plan_apply: plan is NULL");
+    if (nvec < 1 || !d_v || !d_w) return fail(QCM_EARG, "qcm_hv_plan_apply: bad vectors");
+    const size_t vb = (p->prec == QCM_FP64 ? 8 : 4) * (size_t)p->dim * (size_t)nvec;
+    const char *pv = (const char *)d_v, *pw = (const char *)d_w;
+    if (pv < pw + vb && pw < pv + vb) return fail(QCM_EARG, "qcm_hv_plan_apply: v and w overlap");
+    return hv_launch(p->op, p->prec, d_v, d_w, nvec, as_stream(stream));
+}
+
+extern "C" int qcm_hv_plan_destroy(qcm_hv_plan *p) {
+    delete p;
+    return QCM_OK;
+}

@@ -381,7 +381,8 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_team(
 
 // pass B of the team layout: W += K_dn V on column slabs, hopping lists
 // row-contiguous and wave-uniform (scalar loads), 8 neighbour segments in
-// flight per wave.  Within a slab the rows are taken in row_order: grouped by
+// flight per wave.  When d_up is even a lane takes two adjacent columns
+// (one 2-element load per neighbour), which halves the load instructions.  Within a slab the rows are taken in row_order: grouped by
 // the popcount of the high half of the down string.  Hops inside either half
 // keep that popcount, so the rows an XCD has in flight find most of their
 // neighbour segments among rows of the same group, a working set that fits
@@ -394,29 +395,39 @@ __global__ void k_row_offsets(int64_t d_dn, int W, int64_t d_up, const int32_t *
     if (e < d_dn * W) off[e] = (int64_t)col[e] * d_up;
 }
 
-template <typename T, int RI>
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    typedef double2 type;
+};
+template <>
+struct Pair<float> {
+    typedef float2 type;
+};
+
+template <typename T, int RI, int CW>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
     const int64_t *__restrict__ offs, const double *__restrict__ cfd, const T *__restrict__ v,
     T *__restrict__ w, const int R, const int64_t nrb, const int64_t total, const int64_t per,
     const int32_t *__restrict__ order) {
+    typedef typename Pair<T>::type T2;
     const int64_t p = blockIdx.x;
     const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
     if (lg >= total) return;
     const int64_t slab = lg / nrb, rb = lg - slab * nrb;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t c0 = slab * 64 + lane;
+    const int64_t c0 = slab * (64 * CW) + lane * CW;
     const bool cok = c0 < d_up;
     const int64_t vb = (int64_t)blockIdx.y * d_up * d_dn;
     const T *vv = v + vb;
     T *ww = w + vb;
-    // RI rows of the wave are worked on together: their hopping lists are
-    // wave-uniform (scalar loads), 8 neighbour segments of each in flight
     for (int k = wave * RI; k < R; k += 4 * RI) {
         int64_t rr[RI];
         int nh[RI];
-        double acc[RI];
+        double acc[RI][CW];
         int nmax = 0;
 #pragma unroll
         for (int q = 0; q < RI; ++q) {
@@ -425,11 +436,17 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
             rr[q] = ok ? order[r] : 0;
             nh[q] = ok ? nhd[rr[q]] : 0;
             nmax = nh[q] > nmax ? nh[q] : nmax;
-            acc[q] = (ok && cok) ? (double)ww[rr[q] * d_up + c0] : 0.0;
+            if (CW == 2) {
+                T2 a2 = (ok && cok) ? *reinterpret_cast<const T2 *>(ww + rr[q] * d_up + c0) : T2{};
+                acc[q][0] = (double)a2.x;
+                acc[q][CW - 1] = (double)a2.y;
+            } else {
+                acc[q][0] = (ok && cok) ? (double)ww[rr[q] * d_up + c0] : 0.0;
+            }
         }
         if (rb * R + k >= d_dn) break;
         for (int s0 = 0; s0 < nmax; s0 += 8) {
-            T x[RI][8];
+            T x[RI][8][CW];
             double cf[RI][8];
 #pragma unroll
             for (int q = 0; q < RI; ++q) {
@@ -440,18 +457,36 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
                     const bool ok = s0 + u < nh[q];
                     const int64_t jo = ok ? ol[s0 + u] : 0;
                     cf[q][u] = ok ? cl[s0 + u] : 0.0;
-                    x[q][u] = (ok && cok) ? vv[jo + c0] : T(0);
+                    if (CW == 2) {
+                        T2 t2 = (ok && cok) ? *reinterpret_cast<const T2 *>(vv + jo + c0) : T2{};
+                        x[q][u][0] = t2.x;
+                        x[q][u][CW - 1] = t2.y;
+                    } else {
+                        x[q][u][0] = (ok && cok) ? vv[jo + c0] : T(0);
+                    }
                 }
             }
 #pragma unroll
             for (int q = 0; q < RI; ++q)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc[q] = fma(cf[q][u], (double)x[q][u], acc[q]);
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+                        acc[q][c] = fma(cf[q][u], (double)x[q][u][c], acc[q][c]);
         }
         if (cok) {
 #pragma unroll
             for (int q = 0; q < RI; ++q)
-                if (rb * R + k + q < d_dn) ww[rr[q] * d_up + c0] = (T)acc[q];
+                if (rb * R + k + q < d_dn) {
+                    if (CW == 2) {
+                        T2 o2;
+                        o2.x = (T)acc[q][0];
+                        o2.y = (T)acc[q][CW - 1];
+                        *reinterpret_cast<T2 *>(ww + rr[q] * d_up + c0) = o2;
+                    } else {
+                        ww[rr[q] * d_up + c0] = (T)acc[q][0];
+                    }
+                }
         }
     }
 }
@@ -533,14 +568,20 @@ static int hv3_launch_t(const HvOp &op, const SplitTables &st, const HopTables &
     QCM_LAUNCH_CHECK();
     // pass B: row mixing, accumulates into W
     const int R = 16;
-    const int64_t nslab = (d_up + 63) / 64;
+    const int cw = (d_up % 2 == 0) ? 2 : 1;
+    const int64_t nslab = (d_up + 64 * cw - 1) / (64 * cw);
     const int64_t nrb = (d_dn + R - 1) / R;
     const int64_t total = nslab * nrb;
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
-    k_hv_down_acc<T, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
-                                           hd_rm.coef, (const T *)v, (T *)w, R, nrb, total, per,
-                                           op.row_order);
+    if (cw == 2)
+        k_hv_down_acc<T, 2, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
+                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
+                                                  per, op.row_order);
+    else
+        k_hv_down_acc<T, 2, 1><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
+                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
+                                                  per, op.row_order);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }

@@ -233,3 +233,20 @@ def test_cpt_2x2(q):
     gp = q.cpt_gk(torch.from_numpy(Go).to("cuda"), R, E, bonds, ks).cpu().numpy()
     gpo = cf.cpt_periodized(Go, R, E, bonds, ks)
     assert np.abs(gp - gpo).max() <= 1e-10
+
+
+def test_hv_plan_matches_hv(q):
+    torch = _torch()
+    for m in (synth.cluster_3x4(), synth.random_model(102, 11, 3, 6)):
+        b = q.sector_basis(m.L, m.nup, m.ndn)
+        for dt, prec in ((torch.float64, "fp64"), (torch.float32, "fp32v")):
+            v = (torch.rand(2 * b.dim, dtype=torch.float64, device="cuda") * 2 - 1).to(dt)
+            plan = q.HvPlan(m, b, prec)
+            w2 = torch.empty_like(v)
+            plan(v, w2, nvec=2)
+            for k in range(2):
+                w1 = q.hv(m, b, v[k * b.dim:(k + 1) * b.dim].contiguous())
+                assert torch.equal(w1, w2[k * b.dim:(k + 1) * b.dim])
+            with pytest.raises(q.QcmError):
+                plan(v, v, nvec=2)
+            plan.close()
