@@ -378,7 +378,9 @@ int qcm_engine_submit(qcm_engine *e, const qcm_job *j);
  * qcm_engine_step — run up to `rounds` rounds (stops early when no job is in
  * flight).  Completed jobs have their outputs written and their results
  * queued for qcm_engine_poll.  *n_active (may be NULL) receives the number of
- * jobs still in flight.  Synchronises the stream after every round.
+ * jobs still in flight.  Synchronises the stream after every round.  After a
+ * QCM_EHIP from a round the engine is unusable (submit and step return
+ * QCM_EHIP); destroy it.
  */
 int qcm_engine_step(qcm_engine *e, int32_t rounds, int32_t *n_active);
 

@@ -138,6 +138,7 @@ struct qcm_engine {
     BStat *h_stat = nullptr, *d_stat = nullptr;
     double *d_z = nullptr;
     int max_groups = 0;
+    int failed = 0;   // a round failed (HIP error): the engine only accepts destroy
 };
 
 namespace qcm {
@@ -717,6 +718,7 @@ extern "C" int qcm_engine_job_bytes(const qcm_engine_opts *o, const qcm_job *j, 
 
 extern "C" int qcm_engine_submit(qcm_engine *E, const qcm_job *j) {
     if (!E) return fail(QCM_EARG, "qcm_engine_submit: engine is NULL");
+    if (E->failed) return fail(QCM_EHIP, "qcm_engine_submit: engine failed earlier; destroy it");
     QCM_TRY(check_job(E->o, j));
     if ((int)E->active.size() >= E->o.max_jobs)
         return fail(QCM_EWORKSPACE, "qcm_engine_submit: all %d slots busy", E->o.max_jobs);
@@ -750,7 +752,16 @@ extern "C" int qcm_engine_submit(qcm_engine *E, const qcm_job *j) {
 extern "C" int qcm_engine_step(qcm_engine *E, int32_t rounds, int32_t *n_active) {
     if (!E) return fail(QCM_EARG, "qcm_engine_step: engine is NULL");
     if (rounds < 0) return fail(QCM_EARG, "qcm_engine_step: rounds < 0");
-    for (int r = 0; r < rounds && !E->active.empty(); ++r) QCM_TRY(run_round(E));
+    if (E->failed) return fail(QCM_EHIP, "qcm_engine_step: engine failed earlier; destroy it");
+    for (int r = 0; r < rounds && !E->active.empty(); ++r) {
+        const int rc = run_round(E);
+        if (rc != QCM_OK) {
+            // jobs stay in `active` (destroy frees them); their device state is
+            // undefined after a failed launch or copy
+            E->failed = 1;
+            return rc;
+        }
+    }
     if (n_active) *n_active = (int32_t)E->active.size();
     return QCM_OK;
 }
