@@ -240,6 +240,47 @@ int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const double *d_gs, do
                  const double *h_z, double *d_G, void *d_ws, size_t ws_bytes, size_t *ws_needed,
                  void *stream);
 
+/* Options of the band Lanczos Green function. */
+typedef struct qcm_band_opts {
+    int32_t n_orb;        /* p: number of orbitals (start states), 1..32 */
+    int32_t pad0;
+    const int32_t *orbs;  /* host [n_orb], distinct orbitals in [0, L) */
+    int32_t max_basis;    /* basis vectors per part, 1..1024 */
+    int32_t prec;         /* QCM_FP64 or QCM_FP32V vector storage */
+    double dtol;          /* deflation: candidate norm <= dtol * max(1, max |T_kk|) */
+    int32_t max_sweeps;   /* Jacobi sweeps for the eigenproblem of T (40) */
+    int32_t pad1;
+} qcm_band_opts;
+
+/* Fill `o` with defaults: max_basis 400, FP64, dtol 1e-10, 40 sweeps (no orbitals). */
+void qcm_band_default_opts(qcm_band_opts *o);
+
+/*
+ * qcm_green_band — up-spin G_ij(z) for i, j in `orbs` by the band Lanczos
+ * method (subsection "The band Lanczos algorithm for the Green function"):
+ * for the electron part the start states c+_i |Omega> in (n_up + 1, n_dn),
+ * for the hole part c_i |Omega> in (n_up - 1, n_dn); the Krylov space of
+ * all start states is built one basis vector at a time, each new vector
+ * orthogonalised against the band of previous vectors, redundant candidates
+ * deflated, and stopped at max_basis vectors or when no candidate is left.
+ * The projected Hamiltonian T of each part is diagonalised on the device
+ * (parallel Jacobi), giving the Lehmann representation
+ *   G_ij(z) = sum_r Qe_ir Qe_jr / (z + E0 - Le_r) + sum_r Qh_ir Qh_jr / (z - E0 + Lh_r),
+ * with [Qe Qh][Qe Qh]^T = 1 (the anticommutator).
+ *   gs, d_gs, e0: as in qcm_green_cf.
+ *   h_R     : host int32 [2] or NULL, basis size of each part (0 if the sector
+ *             does not exist or every start state vanishes).
+ *   h_lambda: host [2][max_basis] or NULL, Lambda of each part (first R used).
+ *   h_Q     : host [2][n_orb][max_basis] or NULL, Q of each part.
+ *   n_z, h_z, d_G: as in qcm_green_cf (device complex128 [n_z][n_orb][n_orb]).
+ * Workspace: 3 n_orb + 3 vectors per part plus two max_basis^2 FP64 matrices.
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs, double e0,
+                   const qcm_band_opts *o, int32_t *h_R, double *h_lambda, double *h_Q,
+                   int32_t n_z, const double *h_z, double *d_G, void *d_ws, size_t ws_bytes,
+                   size_t *ws_needed, void *stream);
+
 /* An inter-cluster hopping term for CPT: amplitude t between site i of the
  * cluster at the origin and site j of the cluster at shift[0] E1 +
  * shift[1] E2 + shift[2] E3.  Its Hermitian partner is implied. */

@@ -3,9 +3,9 @@
 fraction Green function and CPT, as hand-written HIP kernels for gfx950
 behind a C ABI (include/qcm.h).  This package is the thin Python binding."""
 from ._binding import (EXPORTS, PREC, QCM_FP32V, QCM_FP64, Engine, HostModel, HvPlan, JobSpec,
-                       QcmError, SectorBasis, as_model, batch_bytes, batch_solve, cpt_gk, green_cf, hv,
-                       lanczos_gs, load_library, sector_basis)
+                       QcmError, SectorBasis, as_model, batch_bytes, batch_solve, cpt_gk,
+                       green_band, green_cf, hv, lanczos_gs, load_library, sector_basis)
 
 __all__ = ["EXPORTS", "PREC", "QCM_FP32V", "QCM_FP64", "Engine", "HostModel", "HvPlan", "JobSpec",
            "QcmError", "SectorBasis", "as_model", "batch_bytes", "batch_solve", "cpt_gk",
-           "green_cf", "hv", "lanczos_gs", "load_library", "sector_basis"]
+           "green_band", "green_cf", "hv", "lanczos_gs", "load_library", "sector_basis"]

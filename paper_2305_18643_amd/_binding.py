@@ -64,6 +64,12 @@ class GreenOpts(ctypes.Structure):
                 ("btol", ctypes.c_double)]
 
 
+class BandOpts(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("pad0", ctypes.c_int32), ("orbs", _c_i32),
+                ("max_basis", ctypes.c_int32), ("prec", ctypes.c_int32), ("dtol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+
+
 class Bond(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("shift", ctypes.c_int32 * 3),
                 ("pad", ctypes.c_int32), ("t", ctypes.c_double)]
@@ -105,7 +111,7 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_default_opts", "qcm_engine_create", "qcm_engine_destroy",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
-           "qcm_hv_plan_destroy"]
+           "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band"]
 
 _lib = None
 
@@ -143,6 +149,11 @@ def load_library(path: str = LIB_PATH):
                                ctypes.c_int32, ctypes.POINTER(Bond), ctypes.c_int32, _c_d, vp,
                                vp, sz, _c_sz, vp]
     P = ctypes.POINTER
+    lib.qcm_band_default_opts.restype = None
+    lib.qcm_band_default_opts.argtypes = [P(BandOpts)]
+    lib.qcm_green_band.restype = ctypes.c_int
+    lib.qcm_green_band.argtypes = [P(Model), P(Basis), vp, ctypes.c_double, P(BandOpts), _c_i32,
+                                   _c_d, _c_d, ctypes.c_int32, _c_d, vp, vp, sz, _c_sz, vp]
     lib.qcm_hv_plan_create.restype = ctypes.c_int
     lib.qcm_hv_plan_create.argtypes = [P(Model), P(Basis), ctypes.c_int32, vp, sz, _c_sz, vp, P(vp)]
     lib.qcm_hv_plan_apply.restype = ctypes.c_int
@@ -398,6 +409,44 @@ def green_cf(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_steps=20
                             ctypes.c_void_p(G.data_ptr()), _ptr(ws), ws.numel(),
                             ctypes.byref(need), _stream(torch, stream)))
     return dict(G=G[:nz], coef=coef, len=lens)
+
+
+def green_band(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_basis=400,
+               prec="fp64", dtol=1e-10, max_sweeps=40, stream=None, ws=None) -> dict:
+    """Band Lanczos up-spin G_ij(z) for i, j in orbs; returns G (device
+    complex128 [n_z, n, n]), R (numpy [2]), lam (list of two numpy arrays) and
+    Q (list of two numpy [n, R] arrays), electron part first."""
+    torch = _torch()
+    lib = load_library()
+    m = as_model(model)
+    orbs_a = np.ascontiguousarray(orbs, dtype=np.int32)
+    n = orbs_a.shape[0]
+    o = BandOpts()
+    lib.qcm_band_default_opts(ctypes.byref(o))
+    o.n_orb, o.orbs, o.max_basis, o.prec = n, orbs_a.ctypes.data_as(_c_i32), max_basis, PREC[prec]
+    o.dtol, o.max_sweeps = dtol, max_sweeps
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1).ravel())
+    nz = z.shape[0]
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_green_band(ctypes.byref(m.c), ctypes.byref(basis.c), None, e0, ctypes.byref(o),
+                              None, None, None, nz, zz.ctypes.data_as(_c_d), None, None, 0,
+                              ctypes.byref(need), None))
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(torch, need.value, basis.device)
+    G = torch.zeros((max(nz, 1), n, n), dtype=torch.complex128, device=basis.device)
+    R = np.zeros(2, dtype=np.int32)
+    lam = np.zeros((2, max_basis))
+    Q = np.zeros((2, n, max_basis))
+    if psi.dtype != torch.float64 or psi.numel() != basis.dim:
+        raise ValueError("psi must be a float64 device vector of the basis dimension")
+    _check(lib.qcm_green_band(ctypes.byref(m.c), ctypes.byref(basis.c), _ptr(psi), float(e0),
+                              ctypes.byref(o), R.ctypes.data_as(_c_i32), lam.ctypes.data_as(_c_d),
+                              Q.ctypes.data_as(_c_d), nz, zz.ctypes.data_as(_c_d),
+                              ctypes.c_void_p(G.data_ptr()), _ptr(ws), ws.numel(),
+                              ctypes.byref(need), _stream(torch, stream)))
+    return dict(G=G[:nz], R=R, lam=[lam[k, :R[k]].copy() for k in range(2)],
+                Q=[Q[k, :, :R[k]].copy() for k in range(2)])
 
 
 def cpt_gk(Gc, R, E, bonds, ks, z=None, stream=None):

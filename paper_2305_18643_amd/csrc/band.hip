@@ -1,0 +1,596 @@
+// Band Lanczos Green function (paper: section "Exact diagonalizations",
+// subsection "The band Lanczos algorithm for the Green function"; Lehmann
+// form of eq. (spectral1)).
+//
+// For the p start states |phi_mu> = c+_mu |Omega> (electron part, sector
+// N_up + 1) and c_mu |Omega> (hole part, N_up - 1), the Krylov space is built
+// one basis vector v_j at a time: the next candidate is normalised (or
+// deflated when its norm is negligible), the other candidates are
+// orthogonalised against v_j, the new candidate H v_j is orthogonalised
+// against the band of previous basis vectors (coefficients known by symmetry)
+// and against v_j and the deflated look-back set (coefficients computed).
+// The coefficients form the projected Hamiltonian T (a band of 2p diagonals
+// plus the entries deflation adds) and the projections rho of the start
+// states.  T = U diag(Lambda) U^T by a parallel Jacobi method in one
+// workgroup; Q = rho^T U; G(z) = sum_r Q_mu,r Q_nu,r / (z -+ ...).
+//
+// The host runs the recurrence's bookkeeping (which vectors are candidates,
+// basis vectors or deflated) and reads back one norm per step for the
+// deflation test; vectors, coefficients and every sum stay on the device.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <vector>
+
+#include "lanczos_device.h"
+
+namespace qcm {
+
+constexpr int kBandMaxP = 32;     // start states per part
+constexpr int kBandMaxR = 1024;   // basis vectors per part
+
+// element offsets of up to kBandMaxP + 1 vectors of the slot pool
+struct VecList {
+    int64_t off[kBandMaxP + 1];
+    int32_t n;
+};
+
+// where the sums of one launch go: T (symmetric), rho, or nowhere
+struct Put {
+    int32_t n;
+    int32_t mode[kBandMaxP + 1];   // 0: T[i][k] = T[k][i]; 1: rho[i][k]; 2: none; 3: T[i][i], scale
+    int32_t i[kBandMaxP + 1], k[kBandMaxP + 1];
+};
+
+// partial[q][chunk] = <x, y_q> over one chunk of kChunk elements
+template <typename T>
+__global__ void __launch_bounds__(256) kbl_dots(const T *__restrict__ base, int64_t xo,
+                                                VecList ys, int64_t dim, int nchunks,
+                                                double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int q = blockIdx.y;
+    const T *x = base + xo;
+    const T *y = base + ys.off[q];
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t e = b0 + k;
+        if (e < dim) acc = fma(ldd(x + e), ldd(y + e), acc);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)q * nchunks + blockIdx.x] = s;
+}
+
+// res[q] = sum of the partials of sum q (fixed order), stored as `put` says
+__global__ void __launch_bounds__(256) kbl_finish(const double *__restrict__ partial, int nchunks,
+                                                  Put put, double *__restrict__ res,
+                                                  double *__restrict__ Tm, int ldt,
+                                                  double *__restrict__ rho, int p,
+                                                  double *__restrict__ scal) {
+    __shared__ double sh[256];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nchunks; k += 256) acc += partial[(int64_t)q * nchunks + k];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    res[q] = s;
+    const int i = put.i[q], k = put.k[q];
+    switch (put.mode[q]) {
+        case 0:
+            Tm[(int64_t)i * ldt + k] = s;
+            Tm[(int64_t)k * ldt + i] = s;
+            break;
+        case 1:
+            rho[(int64_t)i * p + k] = s;
+            break;
+        case 3:
+            Tm[(int64_t)i * ldt + i] = s;
+            if (fabs(s) > scal[1]) scal[1] = fabs(s);
+            break;
+        default:
+            break;
+    }
+}
+
+// y_q -= res[q] * x for every y of the list
+template <typename T>
+__global__ void __launch_bounds__(256) kbl_axpys(T *__restrict__ base, int64_t xo, VecList ys,
+                                                 int64_t dim, const double *__restrict__ res) {
+    const int q = blockIdx.y;
+    const double c = res[q];
+    const T *x = base + xo;
+    T *y = base + ys.off[q];
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t e = b0 + k;
+        if (e < dim) y[e] = (T)fma(-c, ldd(x + e), ldd(y + e));
+    }
+}
+
+// w -= sum_q T[iq][jq] v_q, the terms in list order (coefficients from T)
+template <typename T>
+__global__ void __launch_bounds__(256) kbl_sub_band(T *__restrict__ base, int64_t wo, VecList vs,
+                                                    Put idx, int64_t dim,
+                                                    const double *__restrict__ Tm, int ldt) {
+    T *w = base + wo;
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t e = b0 + k;
+        if (e >= dim) continue;
+        double x = ldd(w + e);
+        for (int q = 0; q < vs.n; ++q) {
+            const double c = Tm[(int64_t)idx.i[q] * ldt + idx.k[q]];
+            x = fma(-c, ldd(base + vs.off[q] + e), x);
+        }
+        w[e] = (T)x;
+    }
+}
+
+// x *= 1/nrm, and the normalisation coefficient into T or rho
+template <typename T>
+__global__ void __launch_bounds__(256) kbl_normalise(T *__restrict__ base, int64_t xo, int64_t dim,
+                                                     double nrm, int mode, int i, int k,
+                                                     double *__restrict__ Tm, int ldt,
+                                                     double *__restrict__ rho, int p) {
+    T *x = base + xo;
+    const double s = 1.0 / nrm;
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+        const int64_t e = b0 + q;
+        if (e < dim) x[e] = (T)(ldd(x + e) * s);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (mode == 0) {
+            Tm[(int64_t)i * ldt + k] = nrm;
+            Tm[(int64_t)k * ldt + i] = nrm;
+        } else {
+            rho[(int64_t)i * p + k] = nrm;
+        }
+    }
+}
+
+// Eigen-decomposition of the symmetric R x R matrix A (leading block, row
+// stride lda) by the cyclic parallel Jacobi method: each round applies the
+// rotations of R/2 disjoint index pairs (round-robin tournament ordering),
+// rows first, then columns and U.  One workgroup.  On return the diagonal of
+// A holds Lambda and U (R x R, row stride R) the eigenvectors (columns).
+__global__ void __launch_bounds__(256) kbl_jacobi(double *__restrict__ A, int lda, int R,
+                                                  double *__restrict__ Uo, int max_sweeps,
+                                                  double *__restrict__ info) {
+    __shared__ double cs[kBandMaxR / 2 + 1], sn[kBandMaxR / 2 + 1];
+    __shared__ int pa[kBandMaxR / 2 + 1], pb[kBandMaxR / 2 + 1];
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    for (int64_t e = tid; e < (int64_t)R * R; e += 256) Uo[e] = (e / R == e % R) ? 1.0 : 0.0;
+    const int m = (R % 2 == 0) ? R : R + 1;   // with a dummy index R when R is odd
+    const int np = m / 2;
+    __syncthreads();
+    int sweep = 0;
+    double off = 0.0, tot = 0.0;
+    for (; sweep < max_sweeps; ++sweep) {
+        // convergence: off-diagonal mass against the whole
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
+            const int r = (int)(e / R), c = (int)(e % R);
+            const double v = A[(int64_t)r * lda + c];
+            if (r != c) a0 += v * v;
+            a1 += v * v;
+        }
+        off = block_sum(a0, sh);
+        tot = block_sum(a1, sh);
+        if (!(off > 1e-30 * tot)) break;
+        for (int rd = 0; rd < m - 1; ++rd) {
+            for (int k = tid; k < np; k += 256) {
+                int a, b;
+                if (k == 0) {
+                    a = m - 1;
+                    b = rd;
+                } else {
+                    a = (rd + k) % (m - 1);
+                    b = (rd - k + (m - 1)) % (m - 1);
+                }
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                if (q < R) {
+                    const double app = A[(int64_t)p * lda + p], aqq = A[(int64_t)q * lda + q];
+                    const double apq = A[(int64_t)p * lda + q];
+                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * (fabs(app) + fabs(aqq))) {
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                    }
+                }
+                pa[k] = p;
+                pb[k] = q;
+                cs[k] = c;
+                sn[k] = s;
+            }
+            __syncthreads();
+            // rows p, q of A
+            for (int64_t e = tid; e < (int64_t)np * R; e += 256) {
+                const int k = (int)(e / R), col = (int)(e % R);
+                const int p = pa[k], q = pb[k];
+                if (q >= R || sn[k] == 0.0) continue;
+                const double c = cs[k], s = sn[k];
+                const double xp = A[(int64_t)p * lda + col], xq = A[(int64_t)q * lda + col];
+                A[(int64_t)p * lda + col] = c * xp - s * xq;
+                A[(int64_t)q * lda + col] = s * xp + c * xq;
+            }
+            __syncthreads();
+            // columns p, q of A and of U
+            for (int64_t e = tid; e < (int64_t)np * R; e += 256) {
+                const int k = (int)(e / R), row = (int)(e % R);
+                const int p = pa[k], q = pb[k];
+                if (q >= R || sn[k] == 0.0) continue;
+                const double c = cs[k], s = sn[k];
+                const double xp = A[(int64_t)row * lda + p], xq = A[(int64_t)row * lda + q];
+                A[(int64_t)row * lda + p] = c * xp - s * xq;
+                A[(int64_t)row * lda + q] = s * xp + c * xq;
+                const double up = Uo[(int64_t)row * R + p], uq = Uo[(int64_t)row * R + q];
+                Uo[(int64_t)row * R + p] = c * up - s * uq;
+                Uo[(int64_t)row * R + q] = s * up + c * uq;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        info[0] = sweep;
+        info[1] = tot > 0.0 ? off / tot : 0.0;
+    }
+}
+
+// lam[r] = A[r][r]; Q[mu][r] = sum_k rho[k][mu] U[k][r]
+__global__ void kbl_lehmann(const double *__restrict__ A, int lda, const double *__restrict__ Uo,
+                            int R, const double *__restrict__ rho, int p,
+                            double *__restrict__ lam, double *__restrict__ Q) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < R) lam[e] = A[e * lda + e];
+    if (e >= (int64_t)p * R) return;
+    const int mu = (int)(e / R), r = (int)(e % R);
+    double s = 0.0;
+    for (int k = 0; k < R; ++k) s = fma(rho[(int64_t)k * p + mu], Uo[(int64_t)k * R + r], s);
+    Q[(int64_t)mu * R + r] = s;
+}
+
+// G[z][mu][nu] = sum_r Qe_mu,r Qe_nu,r / (z + E0 - le_r) + Qh_mu,r Qh_nu,r / (z - E0 + lh_r)
+__global__ void kbl_green(const double *__restrict__ Qe, const double *__restrict__ le, int Re,
+                          const double *__restrict__ Qh, const double *__restrict__ lh, int Rh,
+                          int p, int nz, const double *__restrict__ zs, double e0,
+                          double *__restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nz * p * p) return;
+    const int iz = (int)(e / (p * p)), mn = (int)(e % (p * p));
+    const int mu = mn / p, nu = mn % p;
+    const double zr = zs[2 * iz], zi = zs[2 * iz + 1];
+    double gr = 0.0, gi = 0.0;
+    for (int r = 0; r < Re; ++r) {
+        const double w = Qe[(int64_t)mu * Re + r] * Qe[(int64_t)nu * Re + r];
+        const double dr = zr + e0 - le[r], den = dr * dr + zi * zi;
+        gr += w * dr / den;
+        gi -= w * zi / den;
+    }
+    for (int r = 0; r < Rh; ++r) {
+        const double w = Qh[(int64_t)mu * Rh + r] * Qh[(int64_t)nu * Rh + r];
+        const double dr = zr - e0 + lh[r], den = dr * dr + zi * zi;
+        gr += w * dr / den;
+        gi -= w * zi / den;
+    }
+    G[2 * e] = gr;
+    G[2 * e + 1] = gi;
+}
+
+// ---------------------------------------------------------------- host side
+
+struct BandPart {
+    int valid = 0;
+    SpinTables up{};
+    HvOp op;
+    int64_t dim = 0;
+    int nchunks = 1;
+    char *pool = nullptr;        // slots of dim elements
+    int nslot = 0;
+    double *Tm = nullptr, *rho = nullptr, *Uo = nullptr, *lam = nullptr, *Q = nullptr;
+    double *partial = nullptr, *res = nullptr, *scal = nullptr, *info = nullptr;
+    int R = 0;
+};
+
+struct BandLayout {
+    ModelDev md;
+    HopTables hd;
+    int32_t *ops = nullptr;
+    double *zd = nullptr, *G = nullptr;
+    BandPart part[2];
+};
+
+static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_opts *o, int n_z,
+                       Carver &cv, hipStream_t s, BandLayout *B) {
+    const int L = m->L, p = o->n_orb, Rm = o->max_basis;
+    const size_t vs = o->prec == QCM_FP64 ? 8 : 4;
+    QCM_TRY(upload_model(m, cv, &B->md, s));
+    SpinTables dn = spin_from_basis(gs, 1);
+    QCM_TRY(build_hop_tables(B->md, dn, cv, &B->hd, s, count_bonds(m)));
+    B->ops = cv.take<int32_t>(2 * (size_t)p);
+    B->zd = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1));
+    for (int part = 0; part < 2; ++part) {
+        BandPart &P = B->part[part];
+        const int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
+        P.valid = nup2 >= 0 && nup2 <= L;
+        if (!P.valid) continue;
+        QCM_TRY(build_spin_tables(L, nup2, cv, &P.up, s));
+        P.op.md = B->md;
+        P.op.up = P.up;
+        P.op.dn = dn;
+        P.op.hd = B->hd;
+        P.op.dim = P.up.d * dn.d;
+        QCM_TRY(build_hop_tables(B->md, P.up, cv, &P.op.hu, s, count_bonds(m)));
+        P.op.split = 0;
+        if (split_applies(m, nup2, P.up.d, dn.d)) QCM_TRY(split_prepare(m, P.op, cv, s));
+        P.dim = P.op.dim;
+        P.nchunks = (int)std::max<int64_t>(1, (int64_t)ceil_div(P.dim, kChunk));
+        P.nslot = 3 * p + 3;
+        P.pool = cv.take<char>(vs * (size_t)P.dim * P.nslot);
+        P.Tm = cv.take<double>((size_t)Rm * Rm);
+        P.rho = cv.take<double>((size_t)Rm * p);
+        P.Uo = cv.take<double>((size_t)Rm * Rm);
+        P.lam = cv.take<double>(Rm);
+        P.Q = cv.take<double>((size_t)p * Rm);
+        P.partial = cv.take<double>((size_t)(kBandMaxP + 1) * P.nchunks);
+        P.res = cv.take<double>(kBandMaxP + 1);
+        P.scal = cv.take<double>(8);
+        P.info = cv.take<double>(8);
+    }
+    B->G = cv.take<double>(2 * (size_t)(n_z > 0 ? n_z : 1) * p * p);
+    return QCM_OK;
+}
+
+template <typename T>
+static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int64_t d_src_up,
+                    const SpinTables &src_up, int kind, const int32_t *ops, hipStream_t s) {
+    const int p = o->n_orb, Rm = o->max_basis, ldt = Rm;
+    const int64_t dim = P.dim;
+    const int nch = P.nchunks;
+    T *base = (T *)P.pool;
+    auto off = [&](int slot) { return (int64_t)slot * dim; };
+    const dim3 g1((unsigned)nch, 1);
+    QCM_HIP(hipMemsetAsync(P.Tm, 0, sizeof(double) * (size_t)Rm * Rm, s));
+    QCM_HIP(hipMemsetAsync(P.rho, 0, sizeof(double) * (size_t)Rm * p, s));
+    QCM_HIP(hipMemsetAsync(P.scal, 0, sizeof(double) * 8, s));
+    // start vectors into slots 0..p-1
+    QCM_TRY(apply_ops_raw(sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V, d_gs, d_src_up, src_up, P.up, dim,
+                          kind, ops, p, base, nch, P.partial, s));
+    std::vector<int> freeslots;
+    for (int q = P.nslot - 1; q >= p; --q) freeslots.push_back(q);
+    std::map<int, int> cand;   // candidate index -> slot
+    std::map<int, int> vslot;  // basis index -> slot
+    for (int q = 0; q < p; ++q) cand[q + 1] = q;
+    std::set<int> I;
+    int pc = p;
+    double scale = 1.0;
+    int j = 0;
+    Put none{};
+    none.n = 1;
+    none.mode[0] = 2;
+    double host[2];
+    while (j < Rm) {
+        ++j;
+        double nrm = 0.0;
+        for (;;) {
+            // (1) norm of the next candidate, read back for the deflation test
+            VecList one{};
+            one.n = 1;
+            one.off[0] = off(cand[j]);
+            kbl_dots<T><<<dim3(nch, 1), 256, 0, s>>>(base, off(cand[j]), one, dim, nch, P.partial);
+            kbl_finish<<<1, 256, 0, s>>>(P.partial, nch, none, P.res, P.Tm, ldt, P.rho, p, P.scal);
+            QCM_LAUNCH_CHECK();
+            QCM_HIP(hipMemcpyAsync(host, P.res, sizeof(double), hipMemcpyDeviceToHost, s));
+            QCM_HIP(hipMemcpyAsync(host + 1, P.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            QCM_HIP(hipStreamSynchronize(s));
+            scale = std::max(1.0, host[1]);
+            nrm = sqrt(host[0] > 0.0 ? host[0] : 0.0);
+            if (nrm > o->dtol * scale) break;
+            if (j - pc > 0) I.insert(j - pc);
+            freeslots.push_back(cand[j]);
+            --pc;
+            if (pc == 0) {
+                P.R = j - 1;
+                return QCM_OK;
+            }
+            for (int k = j; k < j + pc; ++k) cand[k] = cand[k + 1];
+            cand.erase(j + pc);
+        }
+        // (2) normalise: v_j
+        const int sj = cand[j];
+        cand.erase(j);
+        vslot[j] = sj;
+        if (j - pc > 0)
+            kbl_normalise<T><<<g1, 256, 0, s>>>(base, off(sj), dim, nrm, 0, j - 1, j - pc - 1,
+                                                P.Tm, ldt, P.rho, p);
+        else
+            kbl_normalise<T><<<g1, 256, 0, s>>>(base, off(sj), dim, nrm, 1, j - 1, j - pc + p - 1,
+                                                P.Tm, ldt, P.rho, p);
+        // (3) the other candidates against v_j
+        if (pc > 1) {
+            VecList ys{};
+            Put put{};
+            ys.n = put.n = pc - 1;
+            for (int q = 0; q < pc - 1; ++q) {
+                const int k = j + 1 + q;
+                ys.off[q] = off(cand[k]);
+                if (k - pc > 0) {
+                    put.mode[q] = 0;
+                    put.i[q] = j - 1;
+                    put.k[q] = k - pc - 1;
+                } else {
+                    put.mode[q] = 1;
+                    put.i[q] = j - 1;
+                    put.k[q] = k - pc + p - 1;
+                }
+            }
+            kbl_dots<T><<<dim3(nch, pc - 1), 256, 0, s>>>(base, off(sj), ys, dim, nch, P.partial);
+            kbl_finish<<<pc - 1, 256, 0, s>>>(P.partial, nch, put, P.res, P.Tm, ldt, P.rho, p,
+                                              P.scal);
+            kbl_axpys<T><<<dim3(nch, pc - 1), 256, 0, s>>>(base, off(sj), ys, dim, P.res);
+            QCM_LAUNCH_CHECK();
+        }
+        // (4) the new candidate w = H v_j
+        if (freeslots.empty()) return fail(QCM_EHIP, "band Lanczos: out of vector slots");
+        const int sw = freeslots.back();
+        freeslots.pop_back();
+        QCM_TRY(hv_launch(P.op, sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V, base + off(sj),
+                          base + off(sw), 1, s));
+        // (5) the band of previous basis vectors, coefficients T[k][j] = T[j][k]
+        {
+            VecList vs{};
+            Put idx{};
+            for (int k = std::max(1, j - pc); k < j; ++k) {
+                vs.off[vs.n] = off(vslot[k]);
+                idx.i[vs.n] = k - 1;
+                idx.k[vs.n] = j - 1;
+                ++vs.n;
+            }
+            idx.n = vs.n;
+            if (vs.n > 0) {
+                kbl_sub_band<T><<<g1, 256, 0, s>>>(base, off(sw), vs, idx, dim, P.Tm, ldt);
+                QCM_LAUNCH_CHECK();
+            }
+        }
+        // (6) v_j and the look-back set, coefficients computed (in index order)
+        std::set<int> K = I;
+        K.insert(j);
+        for (int k : K) {
+            VecList one{};
+            one.n = 1;
+            one.off[0] = off(sw);
+            Put put{};
+            put.n = 1;
+            put.mode[0] = k == j ? 3 : 0;
+            put.i[0] = k - 1;
+            put.k[0] = j - 1;
+            kbl_dots<T><<<dim3(nch, 1), 256, 0, s>>>(base, off(vslot[k]), one, dim, nch, P.partial);
+            kbl_finish<<<1, 256, 0, s>>>(P.partial, nch, put, P.res, P.Tm, ldt, P.rho, p, P.scal);
+            kbl_axpys<T><<<dim3(nch, 1), 256, 0, s>>>(base, off(vslot[k]), one, dim, P.res);
+            QCM_LAUNCH_CHECK();
+        }
+        cand[j + pc] = sw;
+        // basis vectors older than the band and outside the look-back set are done
+        for (auto it = vslot.begin(); it != vslot.end();) {
+            if (it->first < j - p && !I.count(it->first)) {
+                freeslots.push_back(it->second);
+                it = vslot.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    P.R = j;
+    return QCM_OK;
+}
+
+}  // namespace qcm
+
+using namespace qcm;
+
+extern "C" void qcm_band_default_opts(qcm_band_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->max_basis = 400;
+    o->prec = QCM_FP64;
+    o->dtol = 1e-10;
+    o->max_sweeps = 40;
+}
+
+extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs,
+                              double e0, const qcm_band_opts *o, int32_t *h_R,
+                              double *h_lambda, double *h_Q, int32_t n_z, const double *h_z,
+                              double *d_G, void *d_ws, size_t ws_bytes, size_t *ws_needed,
+                              void *stream) {
+    if (!ws_needed || !o) return fail(QCM_EARG, "qcm_green_band: NULL ws_needed or opts");
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(gs, m->L));
+    const int L = m->L, p = o->n_orb;
+    if (p < 1 || p > L || p > kBandMaxP || !o->orbs)
+        return fail(QCM_EARG, "qcm_green_band: bad orbital list (1..%d orbitals)", kBandMaxP);
+    for (int i = 0; i < p; ++i) {
+        if (o->orbs[i] < 0 || o->orbs[i] >= L)
+            return fail(QCM_EARG, "qcm_green_band: orbital %d out of range", o->orbs[i]);
+        for (int k = 0; k < i; ++k)
+            if (o->orbs[k] == o->orbs[i]) return fail(QCM_EARG, "qcm_green_band: repeated orbital");
+    }
+    if (o->max_basis < 1 || o->max_basis > kBandMaxR)
+        return fail(QCM_EARG, "qcm_green_band: max_basis outside 1..%d", kBandMaxR);
+    if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
+        return fail(QCM_EARG, "qcm_green_band: bad prec");
+    if (!(o->dtol > 0.0) || o->max_sweeps < 1)
+        return fail(QCM_EARG, "qcm_green_band: dtol must be > 0 and max_sweeps >= 1");
+    if (n_z < 0 || (n_z > 0 && (!h_z || (!d_G && d_ws))))
+        return fail(QCM_EARG, "qcm_green_band: bad frequency arguments");
+    Carver dry(nullptr);
+    BandLayout DB;
+    QCM_TRY(band_layout(m, gs, o, n_z, dry, nullptr, &DB));
+    const size_t need = dry.off + 256;
+    *ws_needed = need;
+    if (!d_ws) return QCM_OK;
+    if (!d_gs) return fail(QCM_EARG, "qcm_green_band: d_gs is NULL");
+    if (ws_bytes < need)
+        return fail(QCM_EWORKSPACE, "qcm_green_band: workspace %zu < %zu", ws_bytes, need);
+    hipStream_t s = as_stream(stream);
+    Carver cv(d_ws);
+    BandLayout B;
+    QCM_TRY(band_layout(m, gs, o, n_z, cv, s, &B));
+    std::vector<int32_t> ops(2 * (size_t)p);
+    for (int i = 0; i < p; ++i) {
+        ops[2 * i] = o->orbs[i];
+        ops[2 * i + 1] = -1;
+    }
+    QCM_HIP(hipMemcpyAsync(B.ops, ops.data(), sizeof(int32_t) * ops.size(), hipMemcpyHostToDevice, s));
+    if (n_z > 0)
+        QCM_HIP(hipMemcpyAsync(B.zd, h_z, sizeof(double) * 2 * n_z, hipMemcpyHostToDevice, s));
+    const SpinTables upg = spin_from_basis(gs, 0);
+    int Rs[2] = {0, 0};
+    for (int part = 0; part < 2; ++part) {
+        BandPart &P = B.part[part];
+        if (!P.valid) continue;
+        if (o->prec == QCM_FP64)
+            QCM_TRY(band_run<double>(o, P, d_gs, gs->d_up, upg, part, B.ops, s));
+        else
+            QCM_TRY(band_run<float>(o, P, d_gs, gs->d_up, upg, part, B.ops, s));
+        Rs[part] = P.R;
+        if (P.R > 0) {
+            kbl_jacobi<<<1, 256, 0, s>>>(P.Tm, o->max_basis, P.R, P.Uo, o->max_sweeps, P.info);
+            const int64_t nth = std::max<int64_t>(P.R, (int64_t)p * P.R);
+            kbl_lehmann<<<ceil_div(nth, 256), 256, 0, s>>>(P.Tm, o->max_basis, P.Uo, P.R, P.rho, p,
+                                                          P.lam, P.Q);
+            QCM_LAUNCH_CHECK();
+        }
+    }
+    if (n_z > 0) {
+        const BandPart &Pe = B.part[0], &Ph = B.part[1];
+        const int64_t tot = (int64_t)n_z * p * p;
+        kbl_green<<<ceil_div(tot, 256), 256, 0, s>>>(Pe.Q, Pe.lam, Rs[0], Ph.Q, Ph.lam, Rs[1], p,
+                                                    n_z, B.zd, e0, d_G);
+        QCM_LAUNCH_CHECK();
+    }
+    if (h_R) {
+        h_R[0] = Rs[0];
+        h_R[1] = Rs[1];
+    }
+    for (int part = 0; part < 2; ++part) {
+        const BandPart &P = B.part[part];
+        const int R = Rs[part];
+        if (R <= 0) continue;
+        if (h_lambda)
+            QCM_HIP(hipMemcpyAsync(h_lambda + (size_t)part * o->max_basis, P.lam,
+                                   sizeof(double) * R, hipMemcpyDeviceToHost, s));
+        if (h_Q)
+            for (int mu = 0; mu < p; ++mu)
+                QCM_HIP(hipMemcpyAsync(h_Q + ((size_t)part * p + mu) * o->max_basis,
+                                       P.Q + (size_t)mu * R, sizeof(double) * R,
+                                       hipMemcpyDeviceToHost, s));
+    }
+    QCM_HIP(hipStreamSynchronize(s));
+    return QCM_OK;
+}

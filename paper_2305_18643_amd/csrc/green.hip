@@ -131,21 +131,28 @@ __global__ void k_cf_combine(const double *__restrict__ F, const int32_t *__rest
 
 // Start vectors of the chains of one part into the current vectors of e,
 // with their norm partials in e.partial (kind 0: creation, 1: annihilation).
-int apply_ops_launch(Engine &e, const double *psi, int64_t d_src_up, const SpinTables &src_up,
-                     const SpinTables &tgt_up, int kind, const int32_t *ops, hipStream_t s) {
-    const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
-    if (e.prec == QCM_FP64)
+// nvec start vectors (consecutive, length dim each) into out, with their
+// norm partials [nvec][nchunks] in partial.
+int apply_ops_raw(int prec, const double *psi, int64_t d_src_up, const SpinTables &src_up,
+                  const SpinTables &tgt_up, int64_t dim, int kind, const int32_t *ops, int nvec,
+                  void *out, int nchunks, double *partial, hipStream_t s) {
+    const dim3 g((unsigned)nchunks, (unsigned)nvec);
+    if (prec == QCM_FP64)
         k_apply_ops<double><<<g, 256, 0, s>>>(psi, d_src_up, src_up.rank_lo, src_up.rank_hi,
                                               src_up.l_lo, src_up.l_hi, tgt_up.states, tgt_up.d,
-                                              e.dim, kind, ops, (double *)e.vbuf[e.iv], e.nchunks,
-                                              e.partial);
+                                              dim, kind, ops, (double *)out, nchunks, partial);
     else
         k_apply_ops<float><<<g, 256, 0, s>>>(psi, d_src_up, src_up.rank_lo, src_up.rank_hi,
                                              src_up.l_lo, src_up.l_hi, tgt_up.states, tgt_up.d,
-                                             e.dim, kind, ops, (float *)e.vbuf[e.iv], e.nchunks,
-                                             e.partial);
+                                             dim, kind, ops, (float *)out, nchunks, partial);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
+}
+
+int apply_ops_launch(Engine &e, const double *psi, int64_t d_src_up, const SpinTables &src_up,
+                     const SpinTables &tgt_up, int kind, const int32_t *ops, hipStream_t s) {
+    return apply_ops_raw(e.prec, psi, d_src_up, src_up, tgt_up, e.dim, kind, ops, e.nvec,
+                         e.vbuf[e.iv], e.nchunks, e.partial, s);
 }
 
 // Coefficients of part `part` of every pair into coef/len; e == NULL (the

@@ -57,6 +57,9 @@ int psi_finalize(Engine &e, double *psi, hipStream_t s);
 int residual_norm(const HvOp &op, const double *psi, double theta, double *w64, double *partial,
                   double *out, hipStream_t s);
 // Green-function pieces (green.hip)
+int apply_ops_raw(int prec, const double *psi, int64_t d_src_up, const SpinTables &src_up,
+                  const SpinTables &tgt_up, int64_t dim, int kind, const int32_t *ops, int nvec,
+                  void *out, int nchunks, double *partial, hipStream_t s);
 int apply_ops_launch(Engine &e, const double *psi, int64_t d_src_up, const SpinTables &src_up,
                      const SpinTables &tgt_up, int kind, const int32_t *ops, hipStream_t s);
 int green_store(const Engine *e, int npairs, int part, double *coef, int32_t *len, int stride,

@@ -117,3 +117,24 @@ def test_band_paper_stopping_rule():
     assert 3 < R < 225
     assert abs(parts[0][0][0] - ev[0]) <= 1e-9 * max(1.0, abs(ev[0]))
     assert _qqt(parts, [0, 2, 5]) <= 1e-12
+
+
+@pytest.mark.parametrize("full_reorth", [False, True], ids=["paper", "reorth"])
+def test_band_truncated_moments_equal_dense(full_reorth):
+    # A truncated run of m complete blocks reproduces B^T H^k B for k < 2m:
+    # checked against H built densely (oracle/dense.py), with R = 4 blocks.
+    m = synth.chain(8, U=4.0, mu=2.0, nup=4, ndn=4)
+    e0, psi = _gs(m)
+    orbs = [0, 1, 2, 3]
+    _, parts = band.green_band(m.t, m.U, 4, 4, psi, orbs, e0, Z, max_basis=16,
+                               full_reorth=full_reorth)
+    for part, (nup2, sgn) in enumerate(((5, 0), (3, 1))):
+        B = np.stack([oracle.apply_op(m.L, 4, 4, psi, sgn, mu) for mu in orbs], axis=1)
+        H = dense.dense_h(m.t, m.U, nup2, 4)
+        lam, Q = parts[part]
+        HkB = B.copy()
+        for k in range(8):
+            ref = B.T @ HkB
+            got = (Q * lam ** k) @ Q.T
+            assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+            HkB = H @ HkB
