@@ -250,9 +250,14 @@ typedef struct qcm_band_opts {
     double dtol;          /* deflation: candidate norm <= dtol * max(1, max |T_kk|) */
     int32_t max_sweeps;   /* Jacobi sweeps for the eigenproblem of T (40) */
     int32_t pad1;
+    double etol;          /* > 0: stop once the lowest eigenvalue of T has moved by at
+                             most etol * max(1, |theta|) over one block of n_orb basis
+                             vectors (checked when the basis size is a multiple of
+                             n_orb); 0: run to max_basis or exhaustion */
 } qcm_band_opts;
 
-/* Fill `o` with defaults: max_basis 400, FP64, dtol 1e-10, 40 sweeps (no orbitals). */
+/* Fill `o` with defaults: max_basis 400, FP64, dtol 1e-10, 40 sweeps, etol 0
+ * (no orbitals). */
 void qcm_band_default_opts(qcm_band_opts *o);
 
 /*
@@ -262,7 +267,9 @@ void qcm_band_default_opts(qcm_band_opts *o);
  * for the hole part c_i |Omega> in (n_up - 1, n_dn); the Krylov space of
  * all start states is built one basis vector at a time, each new vector
  * orthogonalised against the band of previous vectors, redundant candidates
- * deflated, and stopped at max_basis vectors or when no candidate is left.
+ * deflated, and stopped at max_basis vectors, when no candidate is left, or
+ * (etol > 0) when the lowest eigenvalue of T has converged, the paper's rule
+ * against orthogonality leaks.
  * The projected Hamiltonian T of each part is diagonalised on the device
  * (parallel Jacobi), giving the Lehmann representation
  *   G_ij(z) = sum_r Qe_ir Qe_jr / (z + E0 - Le_r) + sum_r Qh_ir Qh_jr / (z - E0 + Lh_r),
@@ -273,7 +280,8 @@ void qcm_band_default_opts(qcm_band_opts *o);
  *   h_lambda: host [2][max_basis] or NULL, Lambda of each part (first R used).
  *   h_Q     : host [2][n_orb][max_basis] or NULL, Q of each part.
  *   n_z, h_z, d_G: as in qcm_green_cf (device complex128 [n_z][n_orb][n_orb]).
- * Workspace: 3 n_orb + 3 vectors per part plus two max_basis^2 FP64 matrices.
+ * Workspace: 3 n_orb + 3 vectors per part plus two max_basis^2 FP64 matrices
+ * (three with etol > 0).
  * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
  */
 int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs, double e0,

@@ -36,7 +36,8 @@ def band_lanczos(matvec, B: np.ndarray, max_basis: int, dtol_rel: float = 1e-10,
     far) is removed.  The run stops when no candidate is left (the Krylov
     space is exhausted), when R reaches max_basis, or (etol > 0) when the
     lowest eigenvalue of T has moved by at most etol * max(1, |theta|) over
-    the last p basis vectors, the paper's rule against orthogonality leaks.
+    one block of p basis vectors (tested when R is a multiple of p), the
+    paper's rule against orthogonality leaks.
     full_reorth (a test device, not the paper's recurrence) also removes
     from each new candidate its components along every earlier basis vector
     without recording them in T, so that an exhausted space deflates
@@ -106,11 +107,12 @@ def band_lanczos(matvec, B: np.ndarray, max_basis: int, dtol_rel: float = 1e-10,
             for k in list(V):
                 if k < j - p and k not in I:
                     del V[k]
-        # the paper's stopping rule: convergence of the lowest eigenvalue of T
-        if etol > 0.0 and j >= p:
+        # the paper's stopping rule: convergence of the lowest eigenvalue of T,
+        # tested once per block of p basis vectors against the previous block
+        if etol > 0.0 and j % p == 0:
             T, _, _ = _finish(t, rho, j, p)
             th = float(np.linalg.eigvalsh(0.5 * (T + T.T))[0])
-            if len(theta_hist) >= p and abs(th - theta_hist[-p]) <= etol * max(1.0, abs(th)):
+            if theta_hist and abs(th - theta_hist[-1]) <= etol * max(1.0, abs(th)):
                 return _finish(t, rho, j, p)
             theta_hist.append(th)
     return _finish(t, rho, j, p)

@@ -67,7 +67,7 @@ class GreenOpts(ctypes.Structure):
 class BandOpts(ctypes.Structure):
     _fields_ = [("n_orb", ctypes.c_int32), ("pad0", ctypes.c_int32), ("orbs", _c_i32),
                 ("max_basis", ctypes.c_int32), ("prec", ctypes.c_int32), ("dtol", ctypes.c_double),
-                ("max_sweeps", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+                ("max_sweeps", ctypes.c_int32), ("pad1", ctypes.c_int32), ("etol", ctypes.c_double)]
 
 
 class Bond(ctypes.Structure):
@@ -412,10 +412,11 @@ def green_cf(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_steps=20
 
 
 def green_band(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_basis=400,
-               prec="fp64", dtol=1e-10, max_sweeps=40, stream=None, ws=None) -> dict:
+               prec="fp64", dtol=1e-10, max_sweeps=40, etol=0.0, stream=None, ws=None) -> dict:
     """Band Lanczos up-spin G_ij(z) for i, j in orbs; returns G (device
     complex128 [n_z, n, n]), R (numpy [2]), lam (list of two numpy arrays) and
-    Q (list of two numpy [n, R] arrays), electron part first."""
+    Q (list of two numpy [n, R] arrays), electron part first.  etol > 0 stops
+    each part once its lowest Ritz value has converged (the paper's rule)."""
     torch = _torch()
     lib = load_library()
     m = as_model(model)
@@ -424,7 +425,7 @@ def green_band(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_basis=
     o = BandOpts()
     lib.qcm_band_default_opts(ctypes.byref(o))
     o.n_orb, o.orbs, o.max_basis, o.prec = n, orbs_a.ctypes.data_as(_c_i32), max_basis, PREC[prec]
-    o.dtol, o.max_sweeps = dtol, max_sweeps
+    o.dtol, o.max_sweeps, o.etol = dtol, max_sweeps, etol
     z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
     zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1).ravel())
     nz = z.shape[0]

@@ -152,38 +152,77 @@ __global__ void __launch_bounds__(256) kbl_normalise(T *__restrict__ base, int64
     }
 }
 
+constexpr int kJacT = 1024;   // threads of the Jacobi workgroup
+constexpr int kJacU = 4;      // rotation items per thread in flight
+
+// sum over the kJacT threads of one workgroup, fixed tree
+__device__ __forceinline__ double jac_sum(double x, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int s = kJacT / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
 // Eigen-decomposition of the symmetric R x R matrix A (leading block, row
 // stride lda) by the cyclic parallel Jacobi method: each round applies the
 // rotations of R/2 disjoint index pairs (round-robin tournament ordering),
-// rows first, then columns and U.  One workgroup.  On return the diagonal of
-// A holds Lambda and U (R x R, row stride R) the eigenvectors (columns).
-__global__ void __launch_bounds__(256) kbl_jacobi(double *__restrict__ A, int lda, int R,
-                                                  double *__restrict__ Uo, int max_sweeps,
-                                                  double *__restrict__ info) {
+// rows first, then columns (and U).  One workgroup of kJacT threads.  With
+// IN_LDS the matrix is staged in LDS (R <= kJacLdsR); otherwise it stays in
+// global memory and each thread loads NU items before it writes any, so that
+// many L2 accesses are in flight.  The column pass walks the pairs along one
+// row at a time, so the lanes of a wave stay within one row.  On return the
+// diagonal of A holds Lambda and, with WANT_U, U (R x R, row stride R) the
+// eigenvectors (columns); info = {sweeps, off-diagonal fraction, lowest
+// eigenvalue}.
+constexpr int kJacLdsR = 128;
+
+template <bool IN_LDS, bool WANT_U, int NU>
+__global__ void __launch_bounds__(kJacT) kbl_jacobi(double *__restrict__ A, int lda, int R,
+                                                    double *__restrict__ Uo, int max_sweeps,
+                                                    double *__restrict__ info) {
     __shared__ double cs[kBandMaxR / 2 + 1], sn[kBandMaxR / 2 + 1];
     __shared__ int pa[kBandMaxR / 2 + 1], pb[kBandMaxR / 2 + 1];
-    __shared__ double sh[256];
+    __shared__ double sh[kJacT];
+    extern __shared__ double sA[];
     const int tid = threadIdx.x;
-    for (int64_t e = tid; e < (int64_t)R * R; e += 256) Uo[e] = (e / R == e % R) ? 1.0 : 0.0;
+    const int ld = IN_LDS ? R : lda;
+    auto at = [&](int64_t i) -> double & {
+        if constexpr (IN_LDS)
+            return sA[i];
+        else
+            return A[i];
+    };
+    if (IN_LDS)
+        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT)
+            sA[e] = A[(e / R) * lda + e % R];
+    if (WANT_U)
+        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT) Uo[e] = (e / R == e % R) ? 1.0 : 0.0;
     const int m = (R % 2 == 0) ? R : R + 1;   // with a dummy index R when R is odd
     const int np = m / 2;
+    const int64_t nitem = (int64_t)np * R;
     __syncthreads();
     int sweep = 0;
     double off = 0.0, tot = 0.0;
     for (; sweep < max_sweeps; ++sweep) {
         // convergence: off-diagonal mass against the whole
         double a0 = 0.0, a1 = 0.0;
-        for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
+        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT) {
             const int r = (int)(e / R), c = (int)(e % R);
-            const double v = A[(int64_t)r * lda + c];
+            const double v = at((int64_t)r * ld + c);
             if (r != c) a0 += v * v;
             a1 += v * v;
         }
-        off = block_sum(a0, sh);
-        tot = block_sum(a1, sh);
+        off = jac_sum(a0, sh);
+        tot = jac_sum(a1, sh);
         if (!(off > 1e-30 * tot)) break;
         for (int rd = 0; rd < m - 1; ++rd) {
-            for (int k = tid; k < np; k += 256) {
+            for (int k = tid; k < np; k += kJacT) {
                 int a, b;
                 if (k == 0) {
                     a = m - 1;
@@ -195,8 +234,8 @@ __global__ void __launch_bounds__(256) kbl_jacobi(double *__restrict__ A, int ld
                 const int p = a < b ? a : b, q = a < b ? b : a;
                 double c = 1.0, s = 0.0;
                 if (q < R) {
-                    const double app = A[(int64_t)p * lda + p], aqq = A[(int64_t)q * lda + q];
-                    const double apq = A[(int64_t)p * lda + q];
+                    const double app = at((int64_t)p * ld + p), aqq = at((int64_t)q * ld + q);
+                    const double apq = at((int64_t)p * ld + q);
                     if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * (fabs(app) + fabs(aqq))) {
                         const double th = (aqq - app) / (2.0 * apq);
                         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
@@ -210,37 +249,101 @@ __global__ void __launch_bounds__(256) kbl_jacobi(double *__restrict__ A, int ld
                 sn[k] = s;
             }
             __syncthreads();
-            // rows p, q of A
-            for (int64_t e = tid; e < (int64_t)np * R; e += 256) {
-                const int k = (int)(e / R), col = (int)(e % R);
-                const int p = pa[k], q = pb[k];
-                if (q >= R || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double xp = A[(int64_t)p * lda + col], xq = A[(int64_t)q * lda + col];
-                A[(int64_t)p * lda + col] = c * xp - s * xq;
-                A[(int64_t)q * lda + col] = s * xp + c * xq;
+            // rows p, q of A: item e = (pair k, column), consecutive lanes along a row
+            for (int64_t e0 = tid; e0 < nitem; e0 += (int64_t)NU * kJacT) {
+                double xp[NU], xq[NU];
+                int64_t ip[NU], iq[NU];
+                bool ok[NU];
+                int kk[NU];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int64_t e = e0 + (int64_t)u * kJacT;
+                    const bool in = e < nitem;
+                    const int k = in ? (int)(e / R) : 0, col = in ? (int)(e % R) : 0;
+                    ok[u] = in && pb[k] < R && sn[k] != 0.0;
+                    kk[u] = k;
+                    ip[u] = (int64_t)pa[k] * ld + col;
+                    iq[u] = (int64_t)pb[k] * ld + col;
+                    xp[u] = ok[u] ? at(ip[u]) : 0.0;
+                    xq[u] = ok[u] ? at(iq[u]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    if (!ok[u]) continue;
+                    const double c = cs[kk[u]], s = sn[kk[u]];
+                    at(ip[u]) = c * xp[u] - s * xq[u];
+                    at(iq[u]) = s * xp[u] + c * xq[u];
+                }
             }
             __syncthreads();
-            // columns p, q of A and of U
-            for (int64_t e = tid; e < (int64_t)np * R; e += 256) {
-                const int k = (int)(e / R), row = (int)(e % R);
-                const int p = pa[k], q = pb[k];
-                if (q >= R || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double xp = A[(int64_t)row * lda + p], xq = A[(int64_t)row * lda + q];
-                A[(int64_t)row * lda + p] = c * xp - s * xq;
-                A[(int64_t)row * lda + q] = s * xp + c * xq;
-                const double up = Uo[(int64_t)row * R + p], uq = Uo[(int64_t)row * R + q];
-                Uo[(int64_t)row * R + p] = c * up - s * uq;
-                Uo[(int64_t)row * R + q] = s * up + c * uq;
+            // columns p, q of A (and U): item e = (row, pair k), consecutive
+            // lanes take the pairs of one row
+            for (int64_t e0 = tid; e0 < nitem; e0 += (int64_t)NU * kJacT) {
+                double xp[NU], xq[NU], up[NU], uq[NU];
+                int64_t ap[NU], aq[NU], bp[NU], bq[NU];
+                bool ok[NU];
+                int kk[NU];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int64_t e = e0 + (int64_t)u * kJacT;
+                    const bool in = e < nitem;
+                    const int row = in ? (int)(e / np) : 0, k = in ? (int)(e % np) : 0;
+                    ok[u] = in && pb[k] < R && sn[k] != 0.0;
+                    kk[u] = k;
+                    const int p = pa[k], q = pb[k];
+                    ap[u] = (int64_t)row * ld + p;
+                    aq[u] = (int64_t)row * ld + q;
+                    bp[u] = (int64_t)row * R + p;
+                    bq[u] = (int64_t)row * R + q;
+                    xp[u] = ok[u] ? at(ap[u]) : 0.0;
+                    xq[u] = ok[u] ? at(aq[u]) : 0.0;
+                    up[u] = (WANT_U && ok[u]) ? Uo[bp[u]] : 0.0;
+                    uq[u] = (WANT_U && ok[u]) ? Uo[bq[u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    if (!ok[u]) continue;
+                    const double c = cs[kk[u]], s = sn[kk[u]];
+                    at(ap[u]) = c * xp[u] - s * xq[u];
+                    at(aq[u]) = s * xp[u] + c * xq[u];
+                    if (WANT_U) {
+                        Uo[bp[u]] = c * up[u] - s * uq[u];
+                        Uo[bq[u]] = s * up[u] + c * uq[u];
+                    }
+                }
             }
             __syncthreads();
         }
     }
+    if (IN_LDS)
+        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT)
+            A[(e / R) * lda + e % R] = sA[e];
     if (tid == 0) {
+        double lo = R > 0 ? at(0) : 0.0;
+        for (int r = 1; r < R; ++r) lo = fmin(lo, at((int64_t)r * ld + r));
         info[0] = sweep;
         info[1] = tot > 0.0 ? off / tot : 0.0;
+        info[2] = lo;
     }
+}
+
+// Jacobi of the leading R x R block of A; U only when want_u
+static int jacobi_launch(double *A, int lda, int R, double *Uo, int max_sweeps, double *info,
+                         bool want_u, hipStream_t s) {
+    if (R <= kJacLdsR) {
+        const size_t lds = sizeof(double) * (size_t)R * R;
+        if (want_u)
+            kbl_jacobi<true, true, 4><<<1, kJacT, lds, s>>>(A, lda, R, Uo, max_sweeps, info);
+        else
+            kbl_jacobi<true, false, 4><<<1, kJacT, lds, s>>>(A, lda, R, Uo, max_sweeps, info);
+    } else {
+        if (want_u)
+            kbl_jacobi<false, true, 4><<<1, kJacT, 0, s>>>(A, lda, R, Uo, max_sweeps, info);
+        else
+            kbl_jacobi<false, false, 8><<<1, kJacT, 0, s>>>(A, lda, R, Uo, max_sweeps, info);
+    }
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
 }
 
 // lam[r] = A[r][r]; Q[mu][r] = sum_k rho[k][mu] U[k][r]
@@ -294,6 +397,7 @@ struct BandPart {
     char *pool = nullptr;        // slots of dim elements
     int nslot = 0;
     double *Tm = nullptr, *rho = nullptr, *Uo = nullptr, *lam = nullptr, *Q = nullptr;
+    double *Tc = nullptr;        // copy of T for the convergence test (etol > 0)
     double *partial = nullptr, *res = nullptr, *scal = nullptr, *info = nullptr;
     int R = 0;
 };
@@ -336,6 +440,7 @@ static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_o
         P.Tm = cv.take<double>((size_t)Rm * Rm);
         P.rho = cv.take<double>((size_t)Rm * p);
         P.Uo = cv.take<double>((size_t)Rm * Rm);
+        if (o->etol > 0.0) P.Tc = cv.take<double>((size_t)Rm * Rm);
         P.lam = cv.take<double>(Rm);
         P.Q = cv.take<double>((size_t)p * Rm);
         P.partial = cv.take<double>((size_t)(kBandMaxP + 1) * P.nchunks);
@@ -375,6 +480,8 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
     none.n = 1;
     none.mode[0] = 2;
     double host[2];
+    bool have_prev = false;
+    double theta_prev = 0.0;
     while (j < Rm) {
         ++j;
         double nrm = 0.0;
@@ -485,6 +592,19 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
                 ++it;
             }
         }
+        // the paper's stopping rule, once per block: the lowest eigenvalue of
+        // T_j (Jacobi on a copy) against the one a block earlier
+        if (o->etol > 0.0 && j % p == 0) {
+            QCM_HIP(hipMemcpy2DAsync(P.Tc, sizeof(double) * ldt, P.Tm, sizeof(double) * ldt,
+                                     sizeof(double) * j, j, hipMemcpyDeviceToDevice, s));
+            QCM_TRY(jacobi_launch(P.Tc, ldt, j, P.Uo, o->max_sweeps, P.info, false, s));
+            double th = 0.0;
+            QCM_HIP(hipMemcpyAsync(&th, P.info + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+            QCM_HIP(hipStreamSynchronize(s));
+            if (have_prev && fabs(th - theta_prev) <= o->etol * std::max(1.0, fabs(th))) break;
+            have_prev = true;
+            theta_prev = th;
+        }
     }
     P.R = j;
     return QCM_OK;
@@ -501,6 +621,7 @@ extern "C" void qcm_band_default_opts(qcm_band_opts *o) {
     o->prec = QCM_FP64;
     o->dtol = 1e-10;
     o->max_sweeps = 40;
+    o->etol = 0.0;
 }
 
 extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs,
@@ -524,8 +645,8 @@ extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const dou
         return fail(QCM_EARG, "qcm_green_band: max_basis outside 1..%d", kBandMaxR);
     if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
         return fail(QCM_EARG, "qcm_green_band: bad prec");
-    if (!(o->dtol > 0.0) || o->max_sweeps < 1)
-        return fail(QCM_EARG, "qcm_green_band: dtol must be > 0 and max_sweeps >= 1");
+    if (!(o->dtol > 0.0) || o->max_sweeps < 1 || !(o->etol >= 0.0))
+        return fail(QCM_EARG, "qcm_green_band: need dtol > 0, max_sweeps >= 1, etol >= 0");
     if (n_z < 0 || (n_z > 0 && (!h_z || (!d_G && d_ws))))
         return fail(QCM_EARG, "qcm_green_band: bad frequency arguments");
     Carver dry(nullptr);
@@ -560,7 +681,7 @@ extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const dou
             QCM_TRY(band_run<float>(o, P, d_gs, gs->d_up, upg, part, B.ops, s));
         Rs[part] = P.R;
         if (P.R > 0) {
-            kbl_jacobi<<<1, 256, 0, s>>>(P.Tm, o->max_basis, P.R, P.Uo, o->max_sweeps, P.info);
+            QCM_TRY(jacobi_launch(P.Tm, o->max_basis, P.R, P.Uo, o->max_sweeps, P.info, true, s));
             const int64_t nth = std::max<int64_t>(P.R, (int64_t)p * P.R);
             kbl_lehmann<<<ceil_div(nth, 256), 256, 0, s>>>(P.Tm, o->max_basis, P.Uo, P.R, P.rho, p,
                                                           P.lam, P.Q);

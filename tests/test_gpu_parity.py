@@ -319,3 +319,41 @@ def test_band_lanczos_from_gpu_ground_state(q, m, orbs, R):
             worst = max(worst, np.abs(Mg - Mo).max() / max(1.0, np.abs(Mo).max()))
     print(f"  moments 0..3: max relative difference {worst:.2e}")
     assert worst <= 1e-9
+
+
+@pytest.mark.parametrize("m,orbs", [(synth.random_model(501, 6, 3, 2), [0, 2, 5]),
+                                    (synth.chain(8, U=4.0, mu=2.0, nup=4, ndn=4), [0, 1, 2, 3]),
+                                    (synth.impurity_model(np.random.default_rng(18643), 3), [0, 1, 2, 3]),
+                                    (synth.chain(10, U=4.0, mu=2.0, nup=5, ndn=5), list(range(10)))],
+                         ids=["rand6", "chain8", "imp7", "chain10"])
+def test_band_lanczos_stopping_rule(q, m, orbs):
+    """The paper's stopping rule (lowest eigenvalue of T converged to 1e-10,
+    tested once per block) on the GPU and in the oracle, from the same start
+    states: the same basis size R per part, the same lowest Ritz value
+    (relative 1e-10), the moments B^T H^k B for k = 0..3 (relative 1e-9) and
+    Q Q^T = 1 (1e-12).  The converged G is printed, not compared: past the
+    point where orthogonality leaks it depends on rounding."""
+    from oracle import band
+    torch = _torch()
+    print(f"band stop {m.name} p={len(orbs)}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=1000, etol=1e-10)
+    Go, parts = band.green_band(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, ro["e0"], Z64,
+                                max_basis=1000, etol=1e-10)
+    err = np.abs(g["G"].cpu().numpy() - Go).max()
+    print(f"  R {list(g['R'])} (oracle {[x[0].shape[0] for x in parts]}), max |dG| {err:.2e}")
+    worst = 0.0
+    for part in range(2):
+        assert g["R"][part] == parts[part][0].shape[0]
+        lg, lo = g["lam"][part].min(), parts[part][0].min()
+        assert abs(lg - lo) <= 1e-10 * max(1.0, abs(lo))
+        for k in range(4):
+            Mg = _moments(g["lam"][part], g["Q"][part], k)
+            Mo = _moments(parts[part][0], parts[part][1], k)
+            worst = max(worst, np.abs(Mg - Mo).max() / max(1.0, np.abs(Mo).max()))
+    print(f"  moments 0..3: max relative difference {worst:.2e}")
+    assert worst <= 1e-9
+    Q = np.concatenate(g["Q"], axis=1)
+    assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
