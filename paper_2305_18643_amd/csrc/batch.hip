@@ -313,10 +313,11 @@ static Job *make_job(const qcm_job *src) {
     return j;
 }
 
-static size_t job_bytes_of(const qcm_engine_opts &o, Job &j) {
+static int job_bytes_of(const qcm_engine_opts &o, Job &j, size_t *bytes) {
     Carver cv(nullptr);
-    job_layout(o, j, cv, nullptr);
-    return round_up(cv.off, 256) + 256;
+    QCM_TRY(job_layout(o, j, cv, nullptr));
+    *bytes = round_up(cv.off, 256) + 256;
+    return QCM_OK;
 }
 
 // ---------------------------------------------------------------- pool
@@ -711,9 +712,9 @@ extern "C" int qcm_engine_job_bytes(const qcm_engine_opts *o, const qcm_job *j, 
     QCM_TRY(check_engine_opts(o));
     QCM_TRY(check_job(*o, j));
     Job *x = make_job(j);
-    *bytes = job_bytes_of(*o, *x);
+    const int rc = job_bytes_of(*o, *x, bytes);
     delete x;
-    return QCM_OK;
+    return rc;
 }
 
 extern "C" int qcm_engine_submit(qcm_engine *E, const qcm_job *j) {
@@ -723,7 +724,14 @@ extern "C" int qcm_engine_submit(qcm_engine *E, const qcm_job *j) {
     if ((int)E->active.size() >= E->o.max_jobs)
         return fail(QCM_EWORKSPACE, "qcm_engine_submit: all %d slots busy", E->o.max_jobs);
     Job *x = make_job(j);
-    const size_t bytes = job_bytes_of(E->o, *x);
+    size_t bytes = 0;
+    {
+        const int rc = job_bytes_of(E->o, *x, &bytes);
+        if (rc != QCM_OK) {
+            delete x;
+            return rc;
+        }
+    }
     size_t off = 0;
     if (!pool_alloc(E, bytes, &off)) {
         delete x;
@@ -803,8 +811,9 @@ extern "C" int qcm_batch_solve(const qcm_engine_opts *o, int32_t n_jobs, const q
     for (int i = 0; i < n_jobs; ++i) {
         QCM_TRY(check_job(*o, &jobs[i]));
         Job *x = make_job(&jobs[i]);
-        bytes[i] = job_bytes_of(*o, *x);
+        const int rc = job_bytes_of(*o, *x, &bytes[i]);
         delete x;
+        if (rc != QCM_OK) return rc;
         sum += bytes[i];
         big = std::max(big, bytes[i]);
     }

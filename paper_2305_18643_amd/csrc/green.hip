@@ -225,12 +225,11 @@ static int green_part(const qcm_model *m, const qcm_basis *gs, const qcm_green_o
     return QCM_OK;
 }
 
-static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o,
-                          int n_z) {
+static int green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o, int n_z,
+                       size_t *need) {
     Carver dry(nullptr);
     GreenCommon c;
-    if (green_common(m, gs, o->n_orb, 1 + 2 * o->max_steps, n_z, dry, nullptr, &c) != QCM_OK)
-        return 0;
+    QCM_TRY(green_common(m, gs, o->n_orb, 1 + 2 * o->max_steps, n_z, dry, nullptr, &c));
     size_t end = dry.off;
     for (int part = 0; part < 2; ++part) {
         const int nup2 = part == 0 ? gs->n_up + 1 : gs->n_up - 1;
@@ -240,10 +239,11 @@ static size_t green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_gre
         SpinTables up2;
         HvOp op;
         Engine e;
-        if (green_part(m, gs, o, nup2, c, p, nullptr, &up2, &op, &e) != QCM_OK) return 0;
+        QCM_TRY(green_part(m, gs, o, nup2, c, p, nullptr, &up2, &op, &e));
         if (p.off > end) end = p.off;
     }
-    return end + 256;
+    *need = end + 256;
+    return QCM_OK;
 }
 
 extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const double *d_gs,
@@ -267,7 +267,8 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         return fail(QCM_EARG, "qcm_green_cf: bad prec");
     if (n_z < 0 || (n_z > 0 && (!h_z || (!d_G && d_ws))))
         return fail(QCM_EARG, "qcm_green_cf: bad frequency arguments");
-    size_t need = green_bytes(m, gs, o, n_z);
+    size_t need = 0;
+    QCM_TRY(green_bytes(m, gs, o, n_z, &need));
     *ws_needed = need;
     if (!d_ws) return QCM_OK;
     if (!d_gs) return fail(QCM_EARG, "qcm_green_cf: d_gs is NULL");

@@ -66,6 +66,17 @@ int upload_model(const qcm_model *m, Carver &cv, ModelDev *md, hipStream_t s) {
     md->u_uniform = u0;
     for (int k = 0; k < L; ++k)
         if (m->U[k] != u0 || u0 < 0) md->u_uniform = -1.0;
+    md->t_is_uniform = 1;
+    md->t_uniform = 0.0;
+    bool seen = false;
+    for (int a = 0; a < L; ++a)
+        for (int b = a + 1; b < L; ++b) {
+            const double tab = m->t[a * L + b];
+            if (tab == 0.0) continue;
+            if (!seen) md->t_uniform = tab;
+            else if (tab != md->t_uniform) md->t_is_uniform = 0;
+            seen = true;
+        }
     if (!cv.base) return QCM_OK;
     // pack everything into one host staging block laid out like the device block
     size_t total = (char *)(md->ctab + 2 * L * L) - (char *)md->t;
@@ -310,11 +321,12 @@ int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStr
 
 // Sizes and set-up shared by every entry point that applies H.
 // The bytes hv_setup carves: the same carving run without a base (no launch).
-size_t hv_setup_bytes(const qcm_model *m, const qcm_basis *b) {
+int hv_setup_bytes(const qcm_model *m, const qcm_basis *b, size_t *need) {
     Carver dry(nullptr);
     HvOp op;
-    if (hv_setup(m, b, dry, &op, nullptr) != QCM_OK) return 0;
-    return dry.off + 256;
+    QCM_TRY(hv_setup(m, b, dry, &op, nullptr));
+    *need = dry.off + 256;
+    return QCM_OK;
 }
 
 int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipStream_t s) {
@@ -352,7 +364,8 @@ extern "C" int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, cons
     QCM_TRY(validate_model(m));
     QCM_TRY(check_basis(b, m->L));
     if (prec != QCM_FP64 && prec != QCM_FP32V) return fail(QCM_EARG, "qcm_hv: bad prec %d", prec);
-    size_t need = hv_setup_bytes(m, b);
+    size_t need = 0;
+    QCM_TRY(hv_setup_bytes(m, b, &need));
     *ws_needed = need;
     if (!d_ws) return QCM_OK;
     if (ws_bytes < need) return fail(QCM_EWORKSPACE, "qcm_hv: workspace %zu < %zu", ws_bytes, need);
@@ -383,7 +396,8 @@ extern "C" int qcm_hv_plan_create(const qcm_model *m, const qcm_basis *b, int32_
     QCM_TRY(check_basis(b, m->L));
     if (prec != QCM_FP64 && prec != QCM_FP32V)
         return fail(QCM_EARG, "qcm_hv_plan_create: bad prec %d", prec);
-    const size_t need = hv_setup_bytes(m, b);
+    size_t need = 0;
+    QCM_TRY(hv_setup_bytes(m, b, &need));
     *ws_needed = need;
     if (!d_ws) return QCM_OK;
     if (!out) return fail(QCM_EARG, "qcm_hv_plan_create: out is NULL");

@@ -103,6 +103,8 @@ struct ModelDev {
     double *ctab;         // [2*nbond]: t_b, -t_b of bond b (hop coefficients by index)
     int32_t nbytes;       // ceil(L/8)
     double u_uniform;     // >= 0 if all U_k equal (then U * popcount), else -1
+    int32_t t_is_uniform; // every bond has the same t_ab (then a hop coefficient is +-t)
+    double t_uniform;     // that t_ab
 };
 
 struct HopTables {
@@ -125,7 +127,6 @@ int build_hop_tables(const ModelDev &md, const SpinTables &st, Carver &cv, HopTa
                      hipStream_t s, int nbond_host, int rowmajor = 0);
 
 // ---------------------------------------------------------------- H.v
-struct SplitLayout;
 struct HvOp {
     ModelDev md;
     SpinTables up, dn;
@@ -133,20 +134,17 @@ struct HvOp {
     int64_t dim;
     // two-pass path for long rows (see hv_split.hip); used when split != 0
     int split = 0;
-    void *split_blob = nullptr;   // SplitTables of the up spin (packed, device)
+    uint32_t *inrow_pk = nullptr; // up hops packed for the in-row pass (LDS offset | index | sign)
     HopTables hd_rm;              // down hops, row-major, with neighbour offsets
     int32_t *row_order = nullptr; // rows of V in the order the row-mixing pass takes them
-    int32_t split_lo = 0;
-    unsigned char split_lay[128]; // SplitLayout of the blob
 };
 // nvec vectors of length dim, consecutive (stride dim).  prec: QCM_FP64/QCM_FP32V.
 int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s);
 size_t hv_scratch_bytes(const HvOp &op, int prec, int nvec);
-size_t hv_setup_bytes(const qcm_model *m, const qcm_basis *b);
+int hv_setup_bytes(const qcm_model *m, const qcm_basis *b, size_t *need);
 int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipStream_t s);
 // the two-pass path: whether it applies, its workspace, and its set-up
 bool split_applies(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn);
-size_t split_bytes(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn);
 int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s);
 int check_basis(const qcm_basis *b, int L);
 
@@ -158,39 +156,6 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 namespace qcm {
 
-// ---------------------------------------------------------------- split hopping tables
-// Hopping of one spin described through the split b = (h, l) of a string into
-// its high L_hi and low L_lo bits (the same split as the rank tables), so
-// that label(b) = rlo[l] + rhi[popc(l)][h]:
-//  - lo hops move an electron inside l: label changes by a function of l only;
-//  - hi hops move it inside h: label changes by a function of h only;
-//  - cross hops move it between the halves: target = base(h') + rlo[l'].
-// Everything is small (2^(L/2) entries) and is staged into LDS.
-struct SplitLayout {
-    int32_t off_coef, off_elo, off_ehi, off_hient, off_rlo, off_looff, off_hioff, off_loent, bytes;
-    // team layout (one low half per thread, high halves looped)
-    int32_t off_cls, off_llist, off_hlist, off_hbase, off_xbond, off_xtab;
-    int32_t ncls, nxb, max_lo, max_hi, zero_coef;
-};
-// Sections of the packed table blob (byte offsets in SplitLayout):
-//   coef[2*nbond]        t_b and -t_b
-//   e_lo[2^l_lo], e_hi[2^l_hi]   sum of t_kk over the set bits of l, of h
-//   hi_ent               (uint32)(int32 label shift) | (coef index << 32)
-//   rlo[2^l_lo]          label of the low half
-//   lo_off, hi_off       CSR offsets per l, per h
-//   lo_ent               (int16 label shift) | (coef index << 16)
-struct SplitTables {
-    int32_t l_lo, l_hi, nbond;
-    SplitLayout lay;
-    void *blob;         // device copy of the packed tables (lay.bytes)
-};
-
-// host-side construction; returns false if the tables would not fit `cap` bytes
-bool split_tables_size(const qcm_model *m, int N, size_t *bytes);
-int build_split_tables(const qcm_model *m, int N, Carver &cv, SplitTables *st, hipStream_t s);
-size_t hv2_lds_bytes(const SplitTables &st, int prec, int64_t d_up, int nbytes, double u_uniform);
 int build_row_offsets(HopTables &ht, int64_t d_up, Carver &cv, hipStream_t s);
-int hv3_launch(const HvOp &op, const SplitTables &st, const HopTables &hd_rm, int prec,
-               const void *v, void *w, int nvec, hipStream_t s);
 
 }  // namespace qcm

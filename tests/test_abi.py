@@ -123,3 +123,50 @@ def test_product_path_does_not_reference_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def _fake_basis(b, L, nu, nd):
+    """A basis with the right sizes and placeholder device pointers: a size
+    query (d_ws = NULL) reads only the sizes."""
+    from math import comb
+    bas = b.Basis()
+    bas.L, bas.n_up, bas.n_dn = L, nu, nd
+    bas.d_up, bas.d_dn = comb(L, nu), comb(L, nd)
+    bas.dim = bas.d_up * bas.d_dn
+    for f in ("states_up", "states_dn", "rank_lo_up", "rank_hi_up", "rank_lo_dn", "rank_hi_dn"):
+        setattr(bas, f, 4096)
+    return bas
+
+
+def test_size_queries_cover_the_long_row_tables(lib):
+    """The workspace a size query reports must hold every table the call then
+    builds.  For the 16-site half-filled sector (two-pass product) that is at
+    least the hopping lists of both spins (24 slots of 12,870 strings: column,
+    coefficient, packed entry) and the row offsets of the row-mixing pass, so
+    a query that returns less (a dry run that failed and was taken for an
+    empty one) would let the set-up kernels write past the workspace."""
+    import synth
+    from paper_2305_18643_amd import _binding as b
+    m = synth.cluster_4x4(8.0)
+    mc = b.Model()
+    t = np.ascontiguousarray(m.t)
+    U = np.ascontiguousarray(m.U)
+    mc.L, mc.t, mc.U = m.L, t.ctypes.data_as(b._c_d), U.ctypes.data_as(b._c_d)
+    bas = _fake_basis(b, 16, 8, 8)
+    floor = 24 * 12870 * (4 + 8 + 4) * 2 + 24 * 12870 * 8
+    need = ctypes.c_size_t(0)
+    assert lib.qcm_hv(ctypes.byref(mc), ctypes.byref(bas), 0, None, None, None, 0,
+                      ctypes.byref(need), None) == 0
+    assert need.value >= floor
+    plan = ctypes.c_void_p()
+    need2 = ctypes.c_size_t(0)
+    assert lib.qcm_hv_plan_create(ctypes.byref(mc), ctypes.byref(bas), 0, None, 0,
+                                  ctypes.byref(need2), None, ctypes.byref(plan)) == 0
+    assert need2.value == need.value
+    o = b.LanczosOpts()
+    lib.qcm_lanczos_default_opts(ctypes.byref(o))
+    o.want_vector = 0
+    need3 = ctypes.c_size_t(0)
+    assert lib.qcm_lanczos_gs(ctypes.byref(mc), ctypes.byref(bas), ctypes.byref(o), None, None,
+                              None, None, None, 0, ctypes.byref(need3), None) == 0
+    assert need3.value >= floor + 3 * 8 * 165636900
