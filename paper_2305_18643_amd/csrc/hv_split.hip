@@ -367,6 +367,7 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
         if ((int64_t)ord.size() != op.dn.d) return fail(QCM_EARG, "row order size");
         QCM_HIP(hipMemcpyAsync(op.row_order, ord.data(), sizeof(int32_t) * ord.size(),
                                hipMemcpyHostToDevice, s));
+        QCM_HIP(hipStreamSynchronize(s));   // ord is pageable and about to go
     }
     if (cv.base) {
         k_pack_inrow<<<ceil_div((int64_t)n, 256), 256, 0, s>>>((int64_t)n, op.hu.pk, op.inrow_pk);

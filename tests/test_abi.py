@@ -131,6 +131,7 @@ def _fake_basis(b, L, nu, nd):
     from math import comb
     bas = b.Basis()
     bas.L, bas.n_up, bas.n_dn = L, nu, nd
+    bas.l_lo, bas.l_hi = (L + 1) // 2, L - (L + 1) // 2
     bas.d_up, bas.d_dn = comb(L, nu), comb(L, nd)
     bas.dim = bas.d_up * bas.d_dn
     for f in ("states_up", "states_dn", "rank_lo_up", "rank_hi_up", "rank_lo_dn", "rank_hi_dn"):
