@@ -148,7 +148,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.U),
-                     "kernel": "H.v (k_hv_inrow_team + k_hv_down_acc)",
+                     "kernel": "H.v (k_hv_inrow_pk + k_hv_down_acc)",
                      "bytes_per_launch": bytes_alg},
     }
 
