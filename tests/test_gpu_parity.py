@@ -357,3 +357,72 @@ def test_band_lanczos_stopping_rule(q, m, orbs):
     assert worst <= 1e-9
     Q = np.concatenate(g["Q"], axis=1)
     assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
+
+
+def _deep_model():
+    """Orbital 0 far below the others: always occupied, so c+_0 |Omega> = 0
+    and the band recurrence must deflate that start state at once."""
+    m = synth.random_model(502, 6, 3, 3)
+    t = m.t.copy()
+    t[0, 0] = -40.0
+    return synth.Model("deep6", t, m.U, 3, 3)
+
+
+@pytest.mark.parametrize("m,orbs", [(synth.random_model(505, 6, 0, 3), [0, 2, 4]),
+                                    (synth.random_model(506, 6, 6, 2), [1, 3, 5]),
+                                    (_deep_model(), [0, 2, 4])],
+                         ids=["empty_up", "full_up", "vanishing_start"])
+def test_band_lanczos_edge_sectors(q, m, orbs):
+    """Band Lanczos where a part does not exist (N_up = 0: no hole part;
+    N_up = L: no electron part) or a start state vanishes (deflated at once):
+    the same R per part as the oracle, G to 1e-8 from the same start states,
+    and Q Q^T = 1 over what exists (the anticommutator needs both parts only
+    where both exist)."""
+    from oracle import band
+    torch = _torch()
+    print(f"band edge {m.name} ({m.nup},{m.ndn})", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=12)
+    Go, parts = band.green_band(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, ro["e0"], Z64,
+                                max_basis=12)
+    err = np.abs(g["G"].cpu().numpy() - Go).max()
+    print(f"  R {list(g['R'])} (oracle {[x[0].shape[0] for x in parts]}), max |dG| {err:.2e}")
+    for k in range(2):
+        assert g["R"][k] == parts[k][0].shape[0]
+    if m.nup == 0:
+        assert g["R"][1] == 0
+    if m.nup == m.L:
+        assert g["R"][0] == 0
+    assert err <= 1e-8
+    Q = np.concatenate(g["Q"], axis=1)
+    assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
+
+
+def test_band_lanczos_fp32v_errors_reported(q):
+    """FP32 vectors (FP64 sums and coefficients): against the FP64 run from
+    the same start states, the lowest Ritz value of each part and the
+    moments B^T H^k B (k <= 3) to relative 1e-5, G reported."""
+    torch = _torch()
+    m = synth.chain(10, U=4.0, mu=2.0, nup=5, ndn=5)
+    orbs = list(range(10))
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g64 = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=60)
+    g32 = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=60, prec="fp32v")
+    dG = np.abs(g64["G"].cpu().numpy() - g32["G"].cpu().numpy()).max()
+    worst = 0.0
+    for part in range(2):
+        assert g32["R"][part] == g64["R"][part]
+        l64, l32 = g64["lam"][part].min(), g32["lam"][part].min()
+        assert abs(l64 - l32) <= 1e-5 * abs(l64)
+        for k in range(4):
+            M64 = _moments(g64["lam"][part], g64["Q"][part], k)
+            M32 = _moments(g32["lam"][part], g32["Q"][part], k)
+            worst = max(worst, np.abs(M64 - M32).max() / max(1.0, np.abs(M64).max()))
+    print(f"  band FP32V vs FP64: moments {worst:.2e}, max |dG| {dG:.2e}")
+    assert worst <= 1e-5
+    Q = np.concatenate(g32["Q"], axis=1)
+    assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-6
