@@ -250,7 +250,7 @@ static int job_layout(const qcm_engine_opts &o, Job &j, Carver &cv, hipStream_t 
     const int lim = gs_limit(o);
     j.psi = cv.take<double>(dim);
     j.svec = cv.take<double>(lim);
-    j.work = cv.take<double>((size_t)lim * 5);
+    j.work = cv.take<double>((size_t)lim * 6);
     j.status = cv.take<GsStatus>(1);
     j.dscal = cv.take<double>(64);
     const int n = j.d.n_orb;

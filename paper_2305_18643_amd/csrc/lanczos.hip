@@ -407,7 +407,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
         QCM_TRY(hv_setup(m, b, cv, &op, st));
         QCM_TRY(engine_init(e, op, o->prec, 1, limit, o->btol, o->reorth, cv));
         svec = cv.take<double>(limit);
-        work = cv.take<double>((size_t)limit * 5);
+        work = cv.take<double>((size_t)limit * 6);
         status = cv.take<GsStatus>(1);
         dscal = cv.take<double>(64);
         return QCM_OK;

@@ -33,14 +33,14 @@ __device__ __forceinline__ void st(T *p, double x) {
     *p = (T)x;
 }
 
-// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots)
-__device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b,
+// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots);
+// b2[i] = b[i]^2
+__device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b2,
                            double x) {
     int cnt = 0;
     double q = 1.0;
     for (int i = 0; i < M; ++i) {
-        double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
-        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+        q = (a[i] - x) - (i > 0 ? b2[i - 1] / q : 0.0);
         if (q == 0.0) q = -1e-300;
         cnt += q < 0.0;
     }
@@ -48,9 +48,9 @@ __device__ inline int sturm_below(int M, const double *__restrict__ a, const dou
 }
 
 // k-th smallest eigenvalue by 256-way multisection: every thread tests one
-// point of the current bracket; 10 rounds narrow it by 257^10.
-__device__ inline double tridiag_kth(int M, const double *a, const double *b, int k, double *sh_lo,
-                              double *sh_hi) {
+// point of the current bracket; 10 rounds narrow it by 257^10.  b2 = b^2.
+__device__ inline double tridiag_kth(int M, const double *a, const double *b, const double *b2,
+                                     int k, double *sh_lo, double *sh_hi) {
     const int t = threadIdx.x;
     __shared__ int cnts[256];
     if (t == 0) {
@@ -65,19 +65,21 @@ __device__ inline double tridiag_kth(int M, const double *a, const double *b, in
         *sh_hi = hi + pad;
     }
     __syncthreads();
+    __shared__ int first;
     for (int round = 0; round < 10; ++round) {
-        double lo = *sh_lo, hi = *sh_hi;
+        const double lo = *sh_lo, hi = *sh_hi;
+        // stop once the bracket is at the resolution of its end points
+        if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)))) break;
         double x = lo + (hi - lo) * (double)(t + 1) / 257.0;
-        cnts[t] = sturm_below(M, a, b, x);
+        cnts[t] = sturm_below(M, a, b2, x);
+        if (t == 0) first = 256;
+        __syncthreads();
+        // the first point with more than k eigenvalues below it (a minimum,
+        // so the result does not rest on the counts being monotone)
+        if (cnts[t] > k) atomicMin(&first, t);
         __syncthreads();
         if (t == 0) {
-            // first point with more than k eigenvalues below it
-            int j = 256;
-            for (int q = 0; q < 256; ++q)
-                if (cnts[q] > k) {
-                    j = q;
-                    break;
-                }
+            const int j = first;
             double nlo = j == 0 ? lo : lo + (hi - lo) * (double)j / 257.0;
             double nhi = j == 256 ? hi : lo + (hi - lo) * (double)(j + 1) / 257.0;
             *sh_lo = nlo;
@@ -144,25 +146,55 @@ __device__ inline void tridiag_vector(int M, const double *a, const double *b, d
         for (int i = 0; i < M; ++i) x[i] = -x[i];
 }
 
+// Largest T_M whose coefficients and inverse-iteration arrays are staged in
+// LDS by the ground-state test (every Sturm step and every elimination step
+// then reads LDS instead of waiting on a cache round trip).
+constexpr int kTriLds = 640;
+
 // The ground-state test of one workgroup (256 threads) on T_M: theta_0,
 // theta_1, the eigenvector of theta_0 in svec, residual estimate
-// beta[M-1] |s[M-1]| and the convergence flag, written to *status.
+// beta[M-1] |s[M-1]| and the convergence flag, written to *status.  Up to
+// kTriLds steps the work happens in LDS; longer T_M use `work` (5 M doubles)
+// and beta^2 in work + 5 M (M doubles).
 __device__ inline void tridiag_status_block(const double *__restrict__ alpha,
                                             const double *__restrict__ beta, int M, double tol,
                                             double *__restrict__ work, double *__restrict__ svec,
                                             GsStatus *__restrict__ status) {
     __shared__ double lo, hi;
-    double th0 = tridiag_kth(M, alpha, beta, 0, &lo, &hi);
-    double th1 = M > 1 ? tridiag_kth(M, alpha, beta, 1, &lo, &hi) : NAN;
+    __shared__ double la[kTriLds], lb[kTriLds], lb2[kTriLds], lx[kTriLds], lw[5 * kTriLds];
+    const bool in_lds = M <= kTriLds;
+    const double *a = alpha, *b = beta;
+    double *b2 = work + 5 * (size_t)M, *x = svec, *w = work;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < M; i += blockDim.x) {
+            la[i] = alpha[i];
+            lb[i] = beta[i];
+            lb2[i] = beta[i] * beta[i];
+        }
+        a = la;
+        b = lb;
+        b2 = lb2;
+        x = lx;
+        w = lw;
+    } else {
+        for (int i = threadIdx.x; i < M; i += blockDim.x) b2[i] = beta[i] * beta[i];
+    }
+    __syncthreads();
+    double th0 = tridiag_kth(M, a, b, b2, 0, &lo, &hi);
+    double th1 = M > 1 ? tridiag_kth(M, a, b, b2, 1, &lo, &hi) : NAN;
     if (threadIdx.x == 0) {
-        tridiag_vector(M, alpha, beta, th0, svec, work, work + M, work + 2 * M, work + 3 * M,
-                       work + 4 * M);
-        double est = beta[M - 1] * fabs(svec[M - 1]);
+        const int S = in_lds ? kTriLds : M;
+        tridiag_vector(M, a, b, th0, x, w, w + S, w + 2 * S, w + 3 * S, w + 4 * S);
+        double est = beta[M - 1] * fabs(x[M - 1]);
         status->theta0 = th0;
         status->theta1 = th1;
         status->est = est;
         status->converged = est <= tol * fmax(1.0, fabs(th0)) ? 1 : 0;
         status->M = M;
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < M; i += blockDim.x) svec[i] = lx[i];
     }
 }
 
