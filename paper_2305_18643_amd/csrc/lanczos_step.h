@@ -145,12 +145,12 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     __syncthreads();
     const uint32_t du = (uint32_t)d_up;
     double pa = 0.0;
-    for (int64_t e = threadIdx.x; e < nel; e += 256) {
-        const uint32_t r = (uint32_t)e / du;
-        const uint32_t iu = (uint32_t)e - r * du;
-        const int64_t idn = row0 + r;
-        const uint32_t dbl = q.su[iu] & q.sd[idn];
-        double diag = q.eu[iu] + q.ed[idn];
+    // one element: diagonal, in-row hops through the packed entries, row-mixing
+    // hops from global memory, -beta vp, rounded once
+    auto element = [&](uint32_t r, uint32_t iu, int64_t idn, uint32_t sdn, double edn, int nhd,
+                       const int32_t *__restrict__ cold_r, const double *__restrict__ cfd_r) {
+        const uint32_t dbl = q.su[iu] & sdn;
+        double diag = q.eu[iu] + edn;
         if (q.u_uniform >= 0.0) {
             diag += q.u_uniform * (double)__popc(dbl);
         } else {
@@ -178,31 +178,50 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             const uint32_t p0 = pp[(int64_t)s * d_up];
             acc = fma(ct[p0 >> 16], (double)rr[p0 & 0xffffu], acc);
         }
-        // row-mixing term
-        const int nhd = q.nhd[idn];
+        // row-mixing term (hop s of row idn at cold_r[s * d_dn])
         const T *vc = v + iu;
         s = 0;
         for (; s + 4 <= nhd; s += 4) {
-            const int64_t e0 = (int64_t)s * d_dn + idn, e1 = e0 + d_dn;
+            const int64_t e0 = (int64_t)s * d_dn, e1 = e0 + d_dn;
             const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
-            const double x0 = (double)vc[(int64_t)q.cold[e0] * d_up];
-            const double x1 = (double)vc[(int64_t)q.cold[e1] * d_up];
-            const double x2 = (double)vc[(int64_t)q.cold[e2] * d_up];
-            const double x3 = (double)vc[(int64_t)q.cold[e3] * d_up];
-            acc = fma(q.cfd[e0], x0, acc);
-            acc = fma(q.cfd[e1], x1, acc);
-            acc = fma(q.cfd[e2], x2, acc);
-            acc = fma(q.cfd[e3], x3, acc);
+            const double x0 = (double)vc[(int64_t)cold_r[e0] * d_up];
+            const double x1 = (double)vc[(int64_t)cold_r[e1] * d_up];
+            const double x2 = (double)vc[(int64_t)cold_r[e2] * d_up];
+            const double x3 = (double)vc[(int64_t)cold_r[e3] * d_up];
+            acc = fma(cfd_r[e0], x0, acc);
+            acc = fma(cfd_r[e1], x1, acc);
+            acc = fma(cfd_r[e2], x2, acc);
+            acc = fma(cfd_r[e3], x3, acc);
         }
         for (; s < nhd; ++s) {
-            const int64_t e0 = (int64_t)s * d_dn + idn;
-            acc = fma(q.cfd[e0], (double)vc[(int64_t)q.cold[e0] * d_up], acc);
+            const int64_t e0 = (int64_t)s * d_dn;
+            acc = fma(cfd_r[e0], (double)vc[(int64_t)cold_r[e0] * d_up], acc);
         }
         const int64_t i = idn * d_up + iu;
         if (sub) acc = fma(-b, ldd(vp + i), acc);
         const T wt = (T)acc;
         w[i] = wt;
         pa = fma(vi, (double)wt, pa);
+    };
+    if (d_up >= 1024) {
+        // long rows: the rows one after another, so the row index and its
+        // down-hop list are wave-uniform (scalar loads) and no division is
+        // needed; shorter rows keep the packed mapping, which leaves no lane idle
+        for (uint32_t r = 0; r < (uint32_t)nr; ++r) {
+            const int64_t idn = row0 + r;
+            const uint32_t sdn = q.sd[idn];
+            const double edn = q.ed[idn];
+            const int nhd = q.nhd[idn];
+            for (uint32_t iu = threadIdx.x; iu < du; iu += 256)
+                element(r, iu, idn, sdn, edn, nhd, q.cold + idn, q.cfd + idn);
+        }
+    } else {
+        for (int64_t e = threadIdx.x; e < nel; e += 256) {
+            const uint32_t r = (uint32_t)e / du;
+            const uint32_t iu = (uint32_t)e - r * du;
+            const int64_t idn = row0 + r;
+            element(r, iu, idn, q.sd[idn], q.ed[idn], q.nhd[idn], q.cold + idn, q.cfd + idn);
+        }
     }
     if (q.pa) {
         const double t = block_sum(pa, sh);
