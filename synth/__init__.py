@@ -193,3 +193,74 @@ def serving_model(rng: np.random.Generator) -> Model:
 def serving_requests(seed: int = 2305, count: int = 100) -> list[Model]:
     rng = np.random.default_rng(seed)
     return [serving_model(rng) for _ in range(count)]
+
+
+@dataclass
+class CdmftSetup:
+    """A CDMFT problem: a cluster of L sites with n_bath bath orbitals, the
+    lattice it tiles, the bath parameters and the distance-function grid.
+
+    The bath is described by linear maps from the variational parameters p:
+    eps = A_eps @ p (n_bath) and theta = (A_theta @ p).reshape(L, n_bath),
+    theta[mu, alpha] being the cluster-bath hopping (eq. (cdmft1) of the
+    paper)."""
+    name: str
+    tc: np.ndarray          # L x L cluster hopping (without mu)
+    mu: float
+    U: float                # on every cluster site
+    nup: int                # sector of the impurity (cluster + bath)
+    ndn: int
+    A_eps: np.ndarray       # n_bath x n_par
+    A_theta: np.ndarray     # (L * n_bath) x n_par
+    p0: np.ndarray          # initial variational parameters
+    E: np.ndarray           # super-lattice vectors (rows)
+    bonds: list             # inter-cluster bonds (i, j, shift, t)
+    beta: float             # fictitious inverse temperature of the grid
+    wc: float               # frequency cutoff of the distance function
+
+    @property
+    def L(self) -> int:
+        return int(self.tc.shape[0])
+
+    @property
+    def n_bath(self) -> int:
+        return int(self.A_eps.shape[0])
+
+
+def cdmft_chain_4_4b(U: float = 4.0, mu: float = 2.0, t: float = -1.0) -> CdmftSetup:
+    """The one-dimensional Hubbard model on 4-site clusters with 4 bath
+    orbitals (the paper's CDMFT example, its bath figure (a)): cluster sites
+    0..3 (open chain, t on each bond, period 4 along the chain); bath orbitals
+    0 and 1 have energy eb1 and couple to sites 0 and 3 with -tb1, bath
+    orbitals 2 and 3 have energy eb2 and couple to sites 0 and 3 with -tb2.
+    Parameters p = (eb1, eb2, tb1, tb2), starting at (1, -1, 1, 1); sector
+    N = 8, S_z = 0; beta = 50, cutoff 2."""
+    L, nb = 4, 4
+    tc = np.zeros((L, L))
+    for i in range(L - 1):
+        tc[i, i + 1] = tc[i + 1, i] = t
+    A_eps = np.zeros((nb, 4))
+    A_eps[0, 0] = A_eps[1, 0] = 1.0
+    A_eps[2, 1] = A_eps[3, 1] = 1.0
+    A_theta = np.zeros((L * nb, 4))
+    A_theta[0 * nb + 0, 2] = -1.0
+    A_theta[3 * nb + 1, 2] = -1.0
+    A_theta[0 * nb + 2, 3] = -1.0
+    A_theta[3 * nb + 3, 3] = -1.0
+    E = np.array([[4, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.int32)
+    bonds = [(3, 0, (1, 0, 0), t)]
+    return CdmftSetup("chain4_4b", tc, mu, U, 4, 4, A_eps, A_theta,
+                      np.array([1.0, -1.0, 1.0, 1.0]), E, bonds, 50.0, 2.0)
+
+
+def matsubara_grid(beta: float, wc: float) -> np.ndarray:
+    """i omega_n, omega_n = (2n + 1) pi / beta, n = 0, 1, ... up to omega_n <= wc."""
+    n = np.arange(int(np.floor((wc * beta / np.pi - 1.0) / 2.0)) + 1)
+    return 1j * (2 * n + 1) * np.pi / beta
+
+
+def k_grid_1d(nk: int) -> np.ndarray:
+    """nk points of the reduced zone of a 1D super-lattice along x, in units
+    of 2 pi divided by the period: k = (m / nk, 0, 0), m = 0..nk-1, to be
+    used with super-lattice shifts s as the phase exp(2 pi i k . s)."""
+    return np.stack([np.arange(nk) / nk, np.zeros(nk), np.zeros(nk)], axis=1)
