@@ -323,6 +323,72 @@ int qcm_cpt_gk(int32_t L, int32_t n_z, const double *d_Gc, const int32_t *h_R,
                size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------------------------
+ * CDMFT self-consistency (section "Cellular dynamical mean-field theory",
+ * subsection "The CDMFT self-consistent procedure").  The impurity (cluster
+ * of L sites plus n_bath bath orbitals, eq. (cdmft1)) is solved with
+ * qcm_lanczos_gs and qcm_green_cf on the cluster orbitals; these two calls
+ * take the cluster Green function from there to the new bath.
+ *
+ * The bath: theta[mu][alpha] (cluster site mu, bath orbital alpha) and
+ * eps[alpha]; the hybridization function (eq. (hybridization)) is
+ *   Gamma(z) = sum_alpha theta[:, alpha] theta[:, alpha]^T / (z - eps_alpha).
+ * tcp is the cluster hopping with -mu on its diagonal.  Inter-cluster bonds
+ * use qcm_bond with the shift in units of the super-lattice vectors and the
+ * phase exp(2 pi i k.shift) (k in units of 2 pi in the reciprocal basis of
+ * the super-lattice), the Hermitian partner added.
+ * ------------------------------------------------------------------------ */
+
+/* Largest cluster and bath handled by the CDMFT calls. */
+#define QCM_CDMFT_MAX_L 8
+#define QCM_CDMFT_MAX_BATH 16
+#define QCM_CDMFT_MAX_PAR 32
+
+/*
+ * qcm_cdmft_g0inv — from the cluster Green function G_c(z_n) of the impurity:
+ *   Sigma_c(z) = z - tcp - Gamma(z) - G_c(z)^-1,
+ *   Gbar(z)    = (1/n_k) sum_k [z - tcp - V(k) - Sigma_c(z)]^-1 (super-lattice
+ *                average; V(k) from the bonds),
+ *   calG0(z)^-1 = Gbar(z)^-1 + Sigma_c(z).
+ *   L (1..8), n_bath (0..16); h_tcp: host [L][L]; h_theta: host [L][n_bath];
+ *   h_eps: host [n_bath]; n_bonds, h_bonds: host inter-cluster bonds;
+ *   n_k >= 1, h_k: host double [n_k][3]; n_z, h_z: host complex [n_z] (re, im).
+ *   d_Gc: device complex128 [n_z][L][L] (as qcm_green_cf writes it).
+ *   d_sigma, d_gbar, d_g0inv: device complex128 [n_z][L][L] (d_sigma and
+ *   d_gbar may be NULL).  Each output is a fixed-order sum: it depends only
+ *   on the inputs.
+ * Errors: QCM_EARG (also for a singular matrix: the message names it),
+ * QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_cdmft_g0inv(int32_t L, int32_t n_bath, const double *h_tcp, const double *h_theta,
+                    const double *h_eps, int32_t n_bonds, const qcm_bond *h_bonds, int32_t n_k,
+                    const double *h_k, int32_t n_z, const double *h_z, const double *d_Gc,
+                    double *d_sigma, double *d_gbar, double *d_g0inv, void *d_ws,
+                    size_t ws_bytes, size_t *ws_needed, void *stream);
+
+/*
+ * qcm_cdmft_fit — the bath parameters p (n_par, 1..32) that minimise the
+ * distance function (eq. (dist_func))
+ *   d(p) = sum_n w_n || z_n - tcp - Gamma(z_n; p) - calG0^-1(z_n) ||_F^2,
+ * with eps = A_eps p and theta = A_theta p (linear maps from the parameters,
+ * so that symmetry-related bath entries share a parameter).  BFGS from the
+ * given p, with the analytic gradient and a backtracking (Armijo) line
+ * search, on the device in one workgroup, until max_j |dd/dp_j| <= gtol or
+ * max_iter steps.
+ *   h_A_eps: host [n_bath][n_par]; h_A_theta: host [L * n_bath][n_par]
+ *   (row mu * n_bath + alpha); h_tcp, n_z, h_z: as above; h_w: host [n_z]
+ *   weights; d_g0inv: device complex128 [n_z][L][L] (from qcm_cdmft_g0inv).
+ *   h_p: host [n_par], start in, minimiser out; h_dist: host, d at the
+ *   result; h_iters: host, BFGS steps taken (negative if the line search
+ *   failed: h_p then holds the best point found).
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_cdmft_fit(int32_t L, int32_t n_bath, int32_t n_par, const double *h_A_eps,
+                  const double *h_A_theta, const double *h_tcp, int32_t n_z, const double *h_z,
+                  const double *h_w, const double *d_g0inv, double *h_p, double gtol,
+                  int32_t max_iter, double *h_dist, int32_t *h_iters, void *d_ws, size_t ws_bytes,
+                  size_t *ws_needed, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched and continuously served solves.
  *
  * A job is a model, a sector and (optionally) a block of orbitals: the

@@ -111,7 +111,8 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_default_opts", "qcm_engine_create", "qcm_engine_destroy",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
-           "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band"]
+           "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
+           "qcm_cdmft_fit"]
 
 _lib = None
 
@@ -179,6 +180,13 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_batch_solve.restype = ctypes.c_int
     lib.qcm_batch_solve.argtypes = [P(EngineOpts), ctypes.c_int32, P(Job), P(JobResult), vp, sz,
                                     _c_sz, vp]
+    I32, D = ctypes.c_int32, ctypes.c_double
+    lib.qcm_cdmft_g0inv.restype = ctypes.c_int
+    lib.qcm_cdmft_g0inv.argtypes = [I32, I32, _c_d, _c_d, _c_d, I32, P(Bond), I32, _c_d, I32, _c_d,
+                                    vp, vp, vp, vp, vp, sz, _c_sz, vp]
+    lib.qcm_cdmft_fit.restype = ctypes.c_int
+    lib.qcm_cdmft_fit.argtypes = [I32, I32, I32, _c_d, _c_d, _c_d, I32, _c_d, _c_d, vp, _c_d, D,
+                                  I32, _c_d, _c_i32, vp, sz, _c_sz, vp]
     _lib = lib
     return lib
 
@@ -480,6 +488,84 @@ def cpt_gk(Gc, R, E, bonds, ks, z=None, stream=None):
                           ks.ctypes.data_as(_c_d), ctypes.c_void_p(out.data_ptr()), _ptr(ws),
                           ws.numel(), ctypes.byref(need), _stream(torch, stream)))
     return out
+
+
+# ---------------------------------------------------------------- CDMFT
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a if shape is None else a.reshape(shape)
+
+
+def _zz(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1).ravel()), z.shape[0]
+
+
+def cdmft_g0inv(Gc, tcp, theta, eps, bonds, ks, z, *, stream=None):
+    """Sigma_c, Gbar and calG0^{-1} (device complex128 [n_z, L, L] each) from
+    the cluster Green function Gc (device complex128 [n_z, L, L])."""
+    torch = _torch()
+    lib = load_library()
+    if Gc.dtype != torch.complex128 or Gc.dim() != 3 or not Gc.is_contiguous():
+        raise ValueError("Gc must be a contiguous complex128 [n_z, L, L] tensor")
+    nz, L, _ = Gc.shape
+    tcp = _f64(tcp, (L, L))
+    theta = _f64(theta).reshape(L, -1)
+    nb = theta.shape[1]
+    theta = np.ascontiguousarray(theta)
+    eps = _f64(eps, (nb,))
+    ks = _f64(ks).reshape(-1, 3)
+    zz, nz2 = _zz(z)
+    if nz2 != nz:
+        raise ValueError("z and Gc disagree on the number of frequencies")
+    bl = list(bonds)
+    barr = (Bond * max(len(bl), 1))()
+    for q, (i, j, sh, t) in enumerate(bl):
+        barr[q].i, barr[q].j, barr[q].t = int(i), int(j), float(t)
+        for a in range(3):
+            barr[q].shift[a] = int(sh[a])
+    out = [torch.zeros((nz, L, L), dtype=torch.complex128, device=Gc.device) for _ in range(3)]
+    need = ctypes.c_size_t(0)
+    args = (L, nb, tcp.ctypes.data_as(_c_d), theta.ctypes.data_as(_c_d), eps.ctypes.data_as(_c_d),
+            len(bl), barr, ks.shape[0], ks.ctypes.data_as(_c_d), nz, zz.ctypes.data_as(_c_d))
+    _check(lib.qcm_cdmft_g0inv(*args, None, None, None, None, None, 0, ctypes.byref(need), None))
+    ws = _workspace(torch, need.value, Gc.device)
+    _check(lib.qcm_cdmft_g0inv(*args, ctypes.c_void_p(Gc.data_ptr()),
+                               *[ctypes.c_void_p(o.data_ptr()) for o in out], _ptr(ws), ws.numel(),
+                               ctypes.byref(need), _stream(torch, stream)))
+    return dict(sigma=out[0], gbar=out[1], g0inv=out[2])
+
+
+def cdmft_fit(g0inv, tcp, A_eps, A_theta, p0, z, w, *, gtol=1e-10, max_iter=500, stream=None):
+    """Bath parameters minimising the distance function from p0 (BFGS on the
+    device).  Returns (p, distance, BFGS steps; negative if the line search
+    failed)."""
+    torch = _torch()
+    lib = load_library()
+    nz, L, _ = g0inv.shape
+    A_eps = _f64(A_eps)
+    npar = A_eps.shape[1]
+    nb = A_eps.shape[0]
+    A_theta = _f64(A_theta, (L * nb, npar))
+    tcp = _f64(tcp, (L, L))
+    zz, nz2 = _zz(z)
+    w = _f64(w, (nz,))
+    if nz2 != nz:
+        raise ValueError("z and g0inv disagree on the number of frequencies")
+    p = _f64(p0, (npar,)).copy()
+    dist = ctypes.c_double(0.0)
+    iters = ctypes.c_int32(0)
+    need = ctypes.c_size_t(0)
+    args = (L, nb, npar, A_eps.ctypes.data_as(_c_d), A_theta.ctypes.data_as(_c_d),
+            tcp.ctypes.data_as(_c_d), nz, zz.ctypes.data_as(_c_d), w.ctypes.data_as(_c_d))
+    _check(lib.qcm_cdmft_fit(*args, None, p.ctypes.data_as(_c_d), gtol, max_iter, None, None, None,
+                             0, ctypes.byref(need), None))
+    ws = _workspace(torch, need.value, g0inv.device)
+    _check(lib.qcm_cdmft_fit(*args, ctypes.c_void_p(g0inv.data_ptr()), p.ctypes.data_as(_c_d), gtol,
+                             max_iter, ctypes.byref(dist), ctypes.byref(iters), _ptr(ws), ws.numel(),
+                             ctypes.byref(need), _stream(torch, stream)))
+    return p, dist.value, iters.value
 
 
 # ---------------------------------------------------------------- batched / served solves

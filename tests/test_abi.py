@@ -23,7 +23,7 @@ def lib():
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "qcm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(qcm_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(qcm_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -171,3 +171,33 @@ def test_size_queries_cover_the_long_row_tables(lib):
     assert lib.qcm_lanczos_gs(ctypes.byref(mc), ctypes.byref(bas), ctypes.byref(o), None, None,
                               None, None, None, 0, ctypes.byref(need3), None) == 0
     assert need3.value >= floor + 3 * 8 * 165636900
+
+
+def test_cdmft_argument_checks(lib):
+    """The CDMFT calls validate sizes before any launch (no GPU needed)."""
+    from paper_2305_18643_amd import _binding as b
+    need = ctypes.c_size_t(0)
+    tcp = np.zeros(16)
+    z = np.array([0.0, 0.1])
+    k = np.zeros(3)
+    assert lib.qcm_cdmft_g0inv(4, 2, tcp.ctypes.data_as(b._c_d), tcp.ctypes.data_as(b._c_d),
+                               tcp.ctypes.data_as(b._c_d), 0, None, 1, k.ctypes.data_as(b._c_d), 1,
+                               z.ctypes.data_as(b._c_d), None, None, None, None, None, 0,
+                               ctypes.byref(need), None) == 0
+    assert need.value > 0
+    assert lib.qcm_cdmft_g0inv(9, 2, tcp.ctypes.data_as(b._c_d), None, None, 0, None, 1,
+                               k.ctypes.data_as(b._c_d), 1, z.ctypes.data_as(b._c_d), None, None,
+                               None, None, None, 0, ctypes.byref(need), None) == b.QCM_ERANGE
+    assert lib.qcm_cdmft_g0inv(4, 0, tcp.ctypes.data_as(b._c_d), None, None, 0, None, 0, None, 1,
+                               z.ctypes.data_as(b._c_d), None, None, None, None, None, 0,
+                               ctypes.byref(need), None) == b.QCM_EARG
+    A = np.zeros(64)
+    assert lib.qcm_cdmft_fit(4, 2, 33, A.ctypes.data_as(b._c_d), A.ctypes.data_as(b._c_d),
+                             tcp.ctypes.data_as(b._c_d), 1, z.ctypes.data_as(b._c_d),
+                             z.ctypes.data_as(b._c_d), None, A.ctypes.data_as(b._c_d), 1e-10, 10,
+                             None, None, None, 0, ctypes.byref(need), None) == b.QCM_ERANGE
+    assert lib.qcm_cdmft_fit(4, 2, 4, A.ctypes.data_as(b._c_d), A.ctypes.data_as(b._c_d),
+                             tcp.ctypes.data_as(b._c_d), 1, z.ctypes.data_as(b._c_d),
+                             z.ctypes.data_as(b._c_d), None, A.ctypes.data_as(b._c_d), 1e-10, 10,
+                             None, None, None, 0, ctypes.byref(need), None) == 0
+    assert need.value > 0
