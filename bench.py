@@ -42,6 +42,7 @@ def parse():
                    help="rows of the sector the oracle computes for the CPU baseline "
                         "(0: every row, one full product)")
     p.add_argument("--lanczos-steps", type=int, default=300, help="fixed Lanczos steps at 16 sites")
+    p.add_argument("--no-cdmft", action="store_true", help="skip the CDMFT loop figures")
     p.add_argument("--no-context", action="store_true",
                    help="skip the 14-site chain (the paper's timed workload)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-solve figures")
@@ -183,6 +184,8 @@ def main():
 
     if not args.no_context:
         out["context_chain14"] = context_section(args, torch, q, synth, np)
+    if not args.no_cdmft:
+        out["cdmft"] = cdmft_section(args, torch, q, synth, np)
     if not args.no_batch:
         out["batched"] = batched_section(args, torch, q, synth, np)
     if not args.no_serve:
@@ -270,6 +273,46 @@ def context_section(args, torch, q, synth, np):
             "max_abs_G_band_minus_cf": dg,
             "paper": {"hardware": "Apple M2 Max, 8 OpenMP threads", "sector_dim": 5889312,
                       "lanczos_s": 26.8, "gs_plus_gf_s": 86.0, "gf_method": "band Lanczos"}}
+
+
+def cdmft_section(args, torch, q, synth, np):
+    """The CDMFT loop of the paper's 1D example: Hubbard chain U = 4, mu = 2,
+    4-site clusters with 4 bath orbitals (parameters eb1, eb2, tb1, tb2 from
+    (1, -1, 1, 1)), sector (4,4) of the 8-orbital impurity, 64 wave-vectors,
+    Matsubara grid beta = 50 up to omega = 2, uniform weights, stopped when
+    no parameter moves by more than 1e-6.  One iteration of the CPU oracle is
+    timed beside it (context)."""
+    from oracle import cdmft as C
+    s = synth.cdmft_chain_4_4b()
+    z = synth.matsubara_grid(s.beta, s.wc)
+    w = np.full(z.shape[0], 1.0 / z.shape[0])
+    ks = synth.k_grid_1d(64)
+    q.cdmft(s, s.p0, ks, z, w, max_iter=1)          # warm-up (library and kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = q.cdmft(s, s.p0, ks, z, w, max_iter=40, tol=1e-6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": "1D Hubbard U=4 mu=2, 4-site clusters + 4 bath orbitals, impurity sector "
+                       "(4,4) d=4900, 64 k, beta=50, wc=2 (16 frequencies), tol 1e-6",
+           "iterations": r["iterations"], "converged": bool(r["converged"]),
+           "loop_s": round(dt, 4), "s_per_iteration": round(dt / r["iterations"], 5),
+           "bath": [float(x) for x in r["p"]], "distance": r["distance"]}
+    msg = f"cdmft: {r['iterations']} iterations in {dt:.2f} s"
+    if not args.no_cpu:
+        # CPU baseline: one iteration of the oracle (its Lanczos and continued
+        # fractions on one thread, then NumPy / SciPy)
+        t1 = time.perf_counter()
+        Gc, _ = C.cluster_green(s, s.p0, z)
+        sig = C.sigma(s, s.p0, z, Gc)
+        G0i = C.g0inv(C.gbar(s, z, sig, ks), sig)
+        C.fit(s, s.p0, z, w, G0i)
+        t_cpu = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s per iteration", "cores": 1,
+                               "kind": "oracle", "sample": "one CDMFT iteration from p0"}
+        msg += f"; one oracle iteration {t_cpu:.2f} s"
+    print(msg, file=sys.stderr, flush=True)
+    return out
 
 
 def batched_section(args, torch, q, synth, np):

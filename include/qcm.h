@@ -372,8 +372,9 @@ int qcm_cdmft_g0inv(int32_t L, int32_t n_bath, const double *h_tcp, const double
  * with eps = A_eps p and theta = A_theta p (linear maps from the parameters,
  * so that symmetry-related bath entries share a parameter).  BFGS from the
  * given p, with the analytic gradient and a backtracking (Armijo) line
- * search, on the device in one workgroup, until max_j |dd/dp_j| <= gtol or
- * max_iter steps.
+ * search, on the device in one workgroup, until max_j |dd/dp_j| <= gtol, a
+ * step no longer lowers d by more than 1e-15 d, the trial step falls below
+ * 1e-15 max(1, |p|) (the resolution of FP64), or max_iter steps.
  *   h_A_eps: host [n_bath][n_par]; h_A_theta: host [L * n_bath][n_par]
  *   (row mu * n_bath + alpha); h_tcp, n_z, h_z: as above; h_w: host [n_z]
  *   weights; d_g0inv: device complex128 [n_z][L][L] (from qcm_cdmft_g0inv).

@@ -9,9 +9,11 @@
 //    and calG0^-1 = Gbar^-1 + Sigma_c.
 //  * k_cdmft_fit, one workgroup: BFGS on the distance function
 //    d(p) = sum_n w_n || z_n - tcp - Gamma(z_n; p) - calG0^-1(z_n) ||_F^2,
-//    the threads sharing the frequencies for d and its analytic gradient,
-//    thread 0 doing the small dense algebra (direction, line search
-//    bookkeeping, inverse-Hessian update) between barriers.
+//    the threads sharing the entries (frequency, row, column) for d and its
+//    analytic gradient (partial sums in a per-thread row of an LDS table,
+//    summed by column in a fixed order), thread 0 doing the small dense
+//    algebra (direction, line search bookkeeping, inverse-Hessian update)
+//    between barriers.
 #include <math.h>
 #include <string.h>
 
@@ -204,9 +206,15 @@ struct FitArgs {
 };
 
 // d(pp) and its gradient (into grad, LDS) by all threads; theta/eps in LDS.
+// A thread takes the entries (n, m, q) of A(z_n) = z_n - tcp - Gamma - calG0^-1
+// with index = thread + k * 256 and keeps its partial sums in its own row of
+// `part` (np gradient components, then d); the columns are then summed in a
+// fixed order, so the result depends only on the inputs.
+constexpr int kPartW = kCP + 1;
+
 __device__ double fit_eval(const FitArgs &a, const double *pp, double *grad, double *th,
-                           double *ep, double *red) {
-    const int t = threadIdx.x, L = a.L, nb = a.nb, np = a.np;
+                           double *ep, double *part) {
+    const int t = threadIdx.x, L = a.L, nb = a.nb, np = a.np, n2 = L * L;
     for (int e = t; e < nb; e += blockDim.x) {
         double s = 0.0;
         for (int j = 0; j < np; ++j) s += a.A_eps[e * np + j] * pp[j];
@@ -217,67 +225,71 @@ __device__ double fit_eval(const FitArgs &a, const double *pp, double *grad, dou
         for (int j = 0; j < np; ++j) s += a.A_theta[e * np + j] * pp[j];
         th[e] = s;
     }
+    double *row = part + (size_t)t * kPartW;
+    for (int j = 0; j <= np; ++j) row[j] = 0.0;
     __syncthreads();
-    double dpart = 0.0;
-    double gp[kCP];
-    for (int j = 0; j < np; ++j) gp[j] = 0.0;
-    for (int n = t; n < a.nz; n += blockDim.x) {
+    for (int item = t; item < a.nz * n2; item += blockDim.x) {
+        const int n = item / n2, e = item - n * n2, m = e / L, q = e - m * L;
         const double zr = a.zs[2 * n], zi = a.zs[2 * n + 1], wn = a.w[n];
-        const double *G = a.g0i + 2 * (size_t)L * L * n;
-        for (int m = 0; m < L; ++m)
-            for (int q = 0; q < L; ++q) {
-                const int e = m * L + q;
-                double gr, gi;
-                gamma_entry(nb, th + m * nb, th + q * nb, ep, zr, zi, &gr, &gi);
-                const double Ar = (m == q ? zr : 0.0) - a.tcp[e] - gr - G[2 * e];
-                const double Ai = (m == q ? zi : 0.0) - gi - G[2 * e + 1];
-                dpart += wn * (Ar * Ar + Ai * Ai);
-                // conj(A) w
-                const double cr = wn * Ar, ci = -wn * Ai;
-                for (int b = 0; b < nb; ++b) {
-                    // 1/(z - eps_b) = (dr - i zi) / den
-                    const double dr = zr - ep[b], den = dr * dr + zi * zi;
-                    const double ir = dr / den, ii = -zi / den;
-                    // d/deps_b: -2 Re(cA theta_mb theta_qb / (z - eps_b)^2)
-                    const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
-                    const double ge = -2.0 * th[m * nb + b] * th[q * nb + b] * (cr * i2r - ci * i2i);
-                    // d/dtheta_{m b}: -2 Re(cA theta_qb / (z - eps_b)); d/dtheta_{q b}: theta_mb
-                    const double re1 = cr * ir - ci * ii;
-                    const double gtm = -2.0 * th[q * nb + b] * re1;
-                    const double gtq = -2.0 * th[m * nb + b] * re1;
-                    for (int j = 0; j < np; ++j)
-                        gp[j] += a.A_eps[b * np + j] * ge + a.A_theta[(m * nb + b) * np + j] * gtm +
-                                 a.A_theta[(q * nb + b) * np + j] * gtq;
-                }
-            }
-    }
-    const double d = block_sum(dpart, red);
-    for (int j = 0; j < np; ++j) {
-        const double s = block_sum(gp[j], red);
-        if (t == 0) grad[j] = s;
+        const double *G = a.g0i + 2 * (size_t)n2 * n;
+        double gr, gi;
+        gamma_entry(nb, th + m * nb, th + q * nb, ep, zr, zi, &gr, &gi);
+        const double Ar = (m == q ? zr : 0.0) - a.tcp[e] - gr - G[2 * e];
+        const double Ai = (m == q ? zi : 0.0) - gi - G[2 * e + 1];
+        row[np] += wn * (Ar * Ar + Ai * Ai);
+        // w conj(A)
+        const double cr = wn * Ar, ci = -wn * Ai;
+        for (int b = 0; b < nb; ++b) {
+            // 1/(z - eps_b) = (dr - i zi) / den
+            const double dr = zr - ep[b], den = dr * dr + zi * zi;
+            const double ir = dr / den, ii = -zi / den;
+            // d/deps_b: -2 Re(wcA theta_mb theta_qb / (z - eps_b)^2)
+            const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
+            const double ge = -2.0 * th[m * nb + b] * th[q * nb + b] * (cr * i2r - ci * i2i);
+            // d/dtheta_{m b}: -2 Re(wcA theta_qb / (z - eps_b)); d/dtheta_{q b}: with theta_mb
+            const double re1 = cr * ir - ci * ii;
+            const double gtm = -2.0 * th[q * nb + b] * re1;
+            const double gtq = -2.0 * th[m * nb + b] * re1;
+            for (int j = 0; j < np; ++j)
+                row[j] += a.A_eps[b * np + j] * ge + a.A_theta[(m * nb + b) * np + j] * gtm +
+                          a.A_theta[(q * nb + b) * np + j] * gtq;
+        }
     }
     __syncthreads();
-    return d;
+    __shared__ double dsum;
+    for (int j = t; j <= np; j += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < (int)blockDim.x; ++k) s += part[(size_t)k * kPartW + j];
+        if (j < np)
+            grad[j] = s;
+        else
+            dsum = s;
+    }
+    __syncthreads();
+    return dsum;
 }
 
 __global__ void __launch_bounds__(256) k_cdmft_fit(FitArgs a) {
     __shared__ double p[kCP], g[kCP], pt[kCP], gt[kCP], dir[kCP], sv[kCP], yv[kCP], hy[kCP];
     __shared__ double H[kCP * kCP];
-    __shared__ double th[kCL * kCB], ep[kCB], red[256];
+    __shared__ double th[kCL * kCB], ep[kCB];
+    __shared__ double part[256 * kPartW];
     __shared__ double d_sh, dt_sh, alpha_sh, slope_sh;
-    __shared__ int state;  // 0 continue, 1 converged, 2 line search failed
+    __shared__ int state;  // 0 continue, 1 converged, 2 line search failed (3, 4 in the search)
+    __shared__ bool stall;  // the last step did not lower d
     const int t = threadIdx.x, np = a.np;
+    if (t == 0) stall = false;
     for (int j = t; j < np; j += blockDim.x) p[j] = a.p[j];
     for (int e = t; e < np * np; e += blockDim.x) H[e] = (e / np == e % np) ? 1.0 : 0.0;
     __syncthreads();
-    double d = fit_eval(a, p, g, th, ep, red);
+    double d = fit_eval(a, p, g, th, ep, part);
     int it = 0;
     bool first = true;
     for (; it < a.max_iter; ++it) {
         if (t == 0) {
             double gmax = 0.0;
             for (int j = 0; j < np; ++j) gmax = fmax(gmax, fabs(g[j]));
-            state = gmax <= a.gtol ? 1 : 0;
+            state = (gmax <= a.gtol || stall) ? 1 : 0;
             // direction -H g; a non-descent direction restarts from -g
             double slope = 0.0;
             for (int i = 0; i < np; ++i) {
@@ -305,17 +317,32 @@ __global__ void __launch_bounds__(256) k_cdmft_fit(FitArgs a) {
         for (int ls = 0; ls < 60; ++ls) {
             for (int j = t; j < np; j += blockDim.x) pt[j] = p[j] + alpha_sh * dir[j];
             __syncthreads();
-            const double dt = fit_eval(a, pt, gt, th, ep, red);
+            const double dt = fit_eval(a, pt, gt, th, ep, part);
             if (t == 0) {
                 dt_sh = dt;
                 state = dt <= d_sh + 1e-4 * alpha_sh * slope_sh ? 3 : 0;
-                if (state == 0) alpha_sh *= 0.5;
+                if (state == 0) {
+                    // a trial step below the resolution of p ends the fit there
+                    double dm = 0.0, pm = 1.0;
+                    for (int j = 0; j < np; ++j) {
+                        dm = fmax(dm, fabs(alpha_sh * dir[j]));
+                        pm = fmax(pm, fabs(p[j]));
+                    }
+                    if (dm <= 1e-15 * pm) state = 4;
+                    alpha_sh *= 0.5;
+                }
             }
             __syncthreads();
             if (state == 3) {
                 ok = true;
                 break;
             }
+            if (state == 4) break;
+        }
+        if (state == 4) {
+            if (t == 0) state = 1;
+            __syncthreads();
+            break;
         }
         if (!ok) {
             if (t == 0) state = 2;
@@ -354,6 +381,7 @@ __global__ void __launch_bounds__(256) k_cdmft_fit(FitArgs a) {
                 p[j] = pt[j];
                 g[j] = gt[j];
             }
+            stall = !(d_sh - dt_sh > 1e-15 * fabs(d_sh));
             d_sh = dt_sh;
         }
         __syncthreads();
