@@ -264,3 +264,48 @@ def k_grid_1d(nk: int) -> np.ndarray:
     of 2 pi divided by the period: k = (m / nk, 0, 0), m = 0..nk-1, to be
     used with super-lattice shifts s as the phase exp(2 pi i k . s)."""
     return np.stack([np.arange(nk) / nk, np.zeros(nk), np.zeros(nk)], axis=1)
+
+
+@dataclass
+class VcaSetup:
+    """A VCA problem: the cluster reference system (t_ref with -mu on its
+    diagonal, U per site, sector), the k-independent part of V (the lattice's
+    intra-cluster hopping minus the reference's) and the inter-cluster bonds
+    (shift in super-lattice units, phase exp(2 pi i k . s))."""
+    name: str
+    t_ref: np.ndarray
+    U: np.ndarray
+    nup: int
+    ndn: int
+    dt: np.ndarray
+    bonds: list
+    h0: np.ndarray          # the lattice's intra-cluster one-body matrix (with -mu)
+
+
+def vca_plaquette(U: float = 8.0, mu: float = 4.0, tp: float = -1.0, t: float = -1.0) -> VcaSetup:
+    """The square lattice tiled by 2x2 plaquettes (sites x + 2y, super-lattice
+    2 x 2), nearest-neighbour t; the reference plaquette has hopping tp on its
+    four bonds (the variational parameter); half filling (2, 2)."""
+    def plaq(tt):
+        m = np.zeros((4, 4))
+        for a, b in ((0, 1), (2, 3), (0, 2), (1, 3)):
+            m[a, b] = m[b, a] = tt
+        return m
+    h0 = plaq(t) - mu * np.eye(4)
+    t_ref = plaq(tp) - mu * np.eye(4)
+    bonds = [(1, 0, (1, 0, 0), t), (3, 2, (1, 0, 0), t), (2, 0, (0, 1, 0), t), (3, 1, (0, 1, 0), t)]
+    return VcaSetup(f"plaq_tp{tp}", t_ref, np.full(4, float(U)), 2, 2, h0 - t_ref, bonds, h0)
+
+
+def vca_chain4(U: float = 4.0, mu: float = 2.0, tp: float = -1.0, t: float = -1.0) -> VcaSetup:
+    """The 1D chain tiled by open 4-site clusters (period 4), nearest-neighbour
+    t; the reference cluster has hopping tp on its three bonds; half filling."""
+    def ch(tt):
+        m = np.zeros((4, 4))
+        for i in range(3):
+            m[i, i + 1] = m[i + 1, i] = tt
+        return m
+    h0 = ch(t) - mu * np.eye(4)
+    t_ref = ch(tp) - mu * np.eye(4)
+    return VcaSetup(f"chain4_tp{tp}", t_ref, np.full(4, float(U)), 2, 2, h0 - t_ref,
+                    [(3, 0, (1, 0, 0), t)], h0)
