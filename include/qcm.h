@@ -389,6 +389,34 @@ int qcm_cdmft_fit(int32_t L, int32_t n_bath, int32_t n_par, const double *h_A_ep
                   int32_t max_iter, double *h_dist, int32_t *h_iters, void *d_ws, size_t ws_bytes,
                   size_t *ws_needed, void *stream);
 
+/*
+ * qcm_vca_omega — the Potthoff functional of a cluster reference system by
+ * the analytic pole formula (subsection "Practical calculation of the
+ * Potthoff functional", eq. (omega4)), both spins:
+ *   Omega = E0 + 2 [ (1/n_k) sum_k sum_{w_r(k) < 0} w_r(k) - sum_{w'_r < 0} w'_r ],
+ * where w'_r are the poles of the reference's up-spin G' in its Lehmann form
+ * (eq. (spectral1): electron poles Lambda_e - E0, hole poles E0 - Lambda_h,
+ * e.g. from qcm_green_band) with residues Q, and w_r(k) the eigenvalues of
+ *   L(k) = diag(w') + Q^T V(k) Q,
+ * V(k) = dt + the inter-cluster hopping at k (bonds as for qcm_cdmft_g0inv,
+ * phase exp(2 pi i k.shift)); dt is the lattice's intra-cluster one-body
+ * matrix minus the reference's.  Each L(k) (complex Hermitian) is
+ * diagonalised on the device (one workgroup per k, parallel Jacobi in LDS on
+ * its real 2R x 2R form); the k average is a fixed-order sum.
+ *   L: cluster sites (1..8); R: poles (1..64); h_poles: host [R];
+ *   h_Q: host [L][R]; h_dt: host [L][L]; n_bonds, h_bonds; n_k >= 1,
+ *   h_k: host [n_k][3]; e0: the reference's ground-state energy.
+ *   h_omega: host, the functional; h_per_k: host [n_k] or NULL, the sum of
+ *   the negative w_r(k) of each k (one spin).
+ * Errors: QCM_EARG, QCM_ERANGE, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the
+ * stream.
+ */
+#define QCM_VCA_MAX_R 64
+int qcm_vca_omega(int32_t L, int32_t R, const double *h_poles, const double *h_Q,
+                  const double *h_dt, int32_t n_bonds, const qcm_bond *h_bonds, int32_t n_k,
+                  const double *h_k, double e0, double *h_omega, double *h_per_k, void *d_ws,
+                  size_t ws_bytes, size_t *ws_needed, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched and continuously served solves.
  *

@@ -112,7 +112,7 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
-           "qcm_cdmft_fit"]
+           "qcm_cdmft_fit", "qcm_vca_omega"]
 
 _lib = None
 
@@ -187,6 +187,9 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_cdmft_fit.restype = ctypes.c_int
     lib.qcm_cdmft_fit.argtypes = [I32, I32, I32, _c_d, _c_d, _c_d, I32, _c_d, _c_d, vp, _c_d, D,
                                   I32, _c_d, _c_i32, vp, sz, _c_sz, vp]
+    lib.qcm_vca_omega.restype = ctypes.c_int
+    lib.qcm_vca_omega.argtypes = [I32, I32, _c_d, _c_d, _c_d, I32, P(Bond), I32, _c_d, D, _c_d, _c_d,
+                                  vp, sz, _c_sz, vp]
     _lib = lib
     return lib
 
@@ -566,6 +569,42 @@ def cdmft_fit(g0inv, tcp, A_eps, A_theta, p0, z, w, *, gtol=1e-10, max_iter=500,
                              max_iter, ctypes.byref(dist), ctypes.byref(iters), _ptr(ws), ws.numel(),
                              ctypes.byref(need), _stream(torch, stream)))
     return p, dist.value, iters.value
+
+
+def _bond_array(bonds):
+    bl = list(bonds)
+    barr = (Bond * max(len(bl), 1))()
+    for q, (i, j, sh, t) in enumerate(bl):
+        barr[q].i, barr[q].j, barr[q].t = int(i), int(j), float(t)
+        for a in range(3):
+            barr[q].shift[a] = int(sh[a])
+    return barr, len(bl)
+
+
+def vca_omega(e0, poles, Q, dt, bonds, ks, *, device="cuda", stream=None):
+    """Potthoff functional by the pole formula (both spins) from the
+    reference's Lehmann form: e0, poles [R], Q [L, R] (up spin), dt [L, L]
+    (lattice minus reference intra-cluster matrix), inter-cluster bonds and
+    the wave-vectors ks [n_k, 3].  Returns (Omega, per-k sums of the negative
+    eigenvalues of L(k))."""
+    torch = _torch()
+    lib = load_library()
+    Q = _f64(Q)
+    L, R = Q.shape
+    poles = _f64(poles, (R,))
+    dt = _f64(dt, (L, L))
+    ks = _f64(ks).reshape(-1, 3)
+    barr, nbond = _bond_array(bonds)
+    om = ctypes.c_double(0.0)
+    per = np.zeros(ks.shape[0])
+    need = ctypes.c_size_t(0)
+    args = (L, R, poles.ctypes.data_as(_c_d), Q.ctypes.data_as(_c_d), dt.ctypes.data_as(_c_d), nbond,
+            barr, ks.shape[0], ks.ctypes.data_as(_c_d), float(e0))
+    _check(lib.qcm_vca_omega(*args, None, None, None, 0, ctypes.byref(need), None))
+    ws = _workspace(torch, need.value, device)
+    _check(lib.qcm_vca_omega(*args, ctypes.byref(om), per.ctypes.data_as(_c_d), _ptr(ws), ws.numel(),
+                             ctypes.byref(need), _stream(torch, stream)))
+    return om.value, per
 
 
 # ---------------------------------------------------------------- batched / served solves

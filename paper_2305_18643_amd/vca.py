@@ -1,0 +1,36 @@
+"""Potthoff functional of a cluster reference system on the GPU (paper:
+subsection "Practical calculation of the Potthoff functional", eq. (omega4)).
+
+The reference's ground state comes from qcm_lanczos_gs, its Lehmann form
+(poles and Q on every cluster orbital) from qcm_green_band, and the k sum of
+the pole formula from qcm_vca_omega.  This module is control flow and
+argument marshalling.
+
+A problem is any object with t_ref [L, L] (reference hopping, -mu on the
+diagonal), U [L], nup, ndn, dt [L, L] (lattice minus reference
+intra-cluster matrix) and bonds (inter-cluster, shift in super-lattice
+units)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _binding as B
+
+
+def reference_lehmann(prob, *, max_basis=1000):
+    """(E0, poles [R], Q [L, R]) of the reference's up-spin Green function."""
+    L = np.asarray(prob.t_ref).shape[0]
+    model = (prob.t_ref, prob.U)
+    basis = B.sector_basis(L, prob.nup, prob.ndn)
+    gs = B.lanczos_gs(model, basis)
+    g = B.green_band(model, basis, gs["psi"], gs["e0"], list(range(L)), np.array([1j]),
+                     max_basis=max_basis)
+    poles = np.concatenate([g["lam"][0] - gs["e0"], gs["e0"] - g["lam"][1]])
+    return gs["e0"], poles, np.concatenate(g["Q"], axis=1)
+
+
+def omega(prob, ks, *, max_basis=1000):
+    """The functional (both spins) on the wave-vectors ks."""
+    e0, poles, Q = reference_lehmann(prob, max_basis=max_basis)
+    om, _ = B.vca_omega(e0, poles, Q, prob.dt, prob.bonds, ks)
+    return om
