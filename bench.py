@@ -43,6 +43,7 @@ def parse():
                         "(0: every row, one full product)")
     p.add_argument("--lanczos-steps", type=int, default=300, help="fixed Lanczos steps at 16 sites")
     p.add_argument("--no-cdmft", action="store_true", help="skip the CDMFT loop figures")
+    p.add_argument("--no-vca", action="store_true", help="skip the VCA functional figures")
     p.add_argument("--no-context", action="store_true",
                    help="skip the 14-site chain (the paper's timed workload)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-solve figures")
@@ -186,6 +187,8 @@ def main():
         out["context_chain14"] = context_section(args, torch, q, synth, np)
     if not args.no_cdmft:
         out["cdmft"] = cdmft_section(args, torch, q, synth, np)
+    if not args.no_vca:
+        out["vca"] = vca_section(args, torch, q, synth, np)
     if not args.no_batch:
         out["batched"] = batched_section(args, torch, q, synth, np)
     if not args.no_serve:
@@ -311,6 +314,45 @@ def cdmft_section(args, torch, q, synth, np):
         out["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s per iteration", "cores": 1,
                                "kind": "oracle", "sample": "one CDMFT iteration from p0"}
         msg += f"; one oracle iteration {t_cpu:.2f} s"
+    print(msg, file=sys.stderr, flush=True)
+    return out
+
+
+def vca_section(args, torch, q, synth, np):
+    """The Potthoff functional of the 2x2 plaquette reference system for the
+    square-lattice Hubbard model (U = 8, mu = 4, half filling), scanned over
+    the reference hopping t' (9 values in [-1.4, -0.6]) on a 32 x 32 grid of
+    the reduced zone: per value a GPU ground state, a GPU band Lanczos to
+    exhaustion and the GPU pole formula.  The CPU oracle's pole formula for
+    one value is timed beside it."""
+    tps = np.linspace(-1.4, -0.6, 9)
+    ks = synth.k_grid_2d(32)
+    q.vca.omega(synth.vca_plaquette(tp=-1.0), ks)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om = [q.vca.omega(synth.vca_plaquette(tp=tp), ks) for tp in tps]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = int(np.argmin(om))
+    stat = None
+    if 0 < i < len(tps) - 1:       # vertex of the parabola through the three points
+        a, b, c = np.polyfit(tps[i - 1:i + 2], om[i - 1:i + 2], 2)
+        stat = float(-b / (2 * a))
+    out = {"workload": "2x2 plaquette reference, square lattice t=-1 U=8 mu=4 (2,2); 32x32 k; "
+                       "t' scan of 9 values in [-1.4, -0.6]",
+           "s_per_evaluation": round(dt / len(tps), 4), "omega": [float(x) for x in om],
+           "tp": [float(x) for x in tps], "tp_stationary": stat}
+    msg = f"vca: {len(tps)} evaluations in {dt:.2f} s, stationary t' ~ {stat}"
+    if not args.no_cpu:
+        from oracle import vca as O
+        s = synth.vca_plaquette(tp=-1.0)
+        t1 = time.perf_counter()
+        e0, poles, Q = O.cluster_lehmann(s.t_ref, s.U, s.nup, s.ndn)
+        O.omega_poles(e0, poles, Q, s.dt, s.bonds, ks)
+        t_cpu = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s per evaluation", "cores": 1,
+                               "kind": "oracle", "sample": "one functional value (t' = -1)"}
+        msg += f"; one oracle evaluation {t_cpu:.2f} s"
     print(msg, file=sys.stderr, flush=True)
     return out
 
