@@ -153,7 +153,6 @@ __global__ void __launch_bounds__(256) kbl_normalise(T *__restrict__ base, int64
 }
 
 constexpr int kJacT = 1024;   // threads of the Jacobi workgroup
-constexpr int kJacU = 4;      // rotation items per thread in flight
 
 // sum over the kJacT threads of one workgroup, fixed tree
 __device__ __forceinline__ double jac_sum(double x, double *sh) {
