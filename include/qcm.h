@@ -418,6 +418,126 @@ int qcm_vca_omega(int32_t L, int32_t R, const double *h_poles, const double *h_Q
                   size_t ws_bytes, size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Symmetry-adapted sectors of an abelian point group with real characters
+ * (subsection "Cluster symmetries"; Table 3x4stats).
+ *
+ * A group element permutes the orbitals, the same way for both spins.  On a
+ * basis state it gives g|b> = phi_g(b)|gb>, phi_g(b) the sign of reordering
+ * the permuted creation operators of each spin.  In the irrep with characters
+ * chi (each +1 or -1) an orbit holds at most one state, the normalised
+ * projection of its representative: the orbit member with the smallest
+ * label i_up + d_up i_dn.  The representative is kept when the projection
+ * does not vanish.  Its stabiliser size m gives |P|b>|^2 = m/|G|.
+ *
+ * The Hamiltonian is stored.  For a term with H_r|b1> = c |b'>, b2 the
+ * representative of b', the element is (eq. (matrixElement))
+ *   <b2|H_r|b1> = c S / sqrt(m_b1 m_b2),  S = sum_{g: g b' = b2} chi_g phi_g(b').
+ * The terms of one state are summed before being stored (the paper's
+ * cancellation step).  Sums of magnitude at most 1e-13 max(|t|, |U|) are
+ * dropped.
+ *
+ * Building a sector's matrix takes three calls, each sized by the previous one:
+ *   qcm_sym_sector_build -> dim;
+ *   qcm_sym_csr_count    -> representatives, row pointers, nnz;
+ *   qcm_sym_csr_fill     -> columns and values.
+ * qcm_sym_hv and qcm_sym_lanczos_gs then use the stored matrix.  FP64 only.
+ * ------------------------------------------------------------------------ */
+
+#define QCM_SYM_MAX_G 8        /* group order */
+#define QCM_SYM_MAX_BONDS 128  /* pairs a < b with t_ab != 0 */
+
+typedef struct qcm_group {
+    int32_t n_g;            /* order |G|, 1..QCM_SYM_MAX_G; element 0 is the identity */
+    int32_t pad;
+    const int32_t *perm;    /* host [n_g * L]: perm[g*L + a] = image of orbital a under g */
+    const int32_t *chi;     /* host [n_g]: the irrep's characters, +1 or -1 */
+} qcm_group;
+
+typedef struct qcm_sym_sector {
+    qcm_basis b;                          /* the full sector (copied; its tables must stay alive) */
+    int32_t n_g;
+    int32_t pad;
+    int32_t chi[QCM_SYM_MAX_G];
+    int8_t perm[QCM_SYM_MAX_G * 32];      /* perm[g*32 + a] */
+    int64_t dim;                          /* states of the irrep */
+    int64_t n_words;                      /* ceil(b.dim / 64) */
+    const uint64_t *bits;                 /* device [n_words]: bit i of the full-sector labels
+                                             set iff label i is a kept representative */
+    const int64_t *base;                  /* device [n_words]: kept representatives below word w */
+    const uint32_t *img_up;               /* device [n_g * d_up]: label of g b_up, with bit 31
+                                             set when phi_g(b_up) = -1 */
+    const uint32_t *img_dn;               /* device [n_g * d_dn]: likewise for down strings */
+} qcm_sym_sector;
+
+/* The stored matrix: row k holds the elements <b2|H|b_k> of representative
+ * k, columns ascending (H is real symmetric, so row k is also column k). */
+typedef struct qcm_sym_csr {
+    int64_t dim, nnz;
+    const uint32_t *rep;      /* device [dim]: full-sector label of each representative, ascending */
+    const int64_t *rowptr;    /* device [dim + 1] */
+    const uint32_t *col;      /* device [nnz] */
+    const double *val;        /* device [nnz] */
+} qcm_sym_csr;
+
+/*
+ * qcm_sym_sector_build — the irrep's representatives of a sector.
+ *   b     : a basis from qcm_sector_basis, b->dim < 2^32.
+ *   g     : the group and irrep (host).  Checked: element 0 is the identity,
+ *           every element is a permutation of the b->L orbitals, the set is
+ *           closed under composition, and chi is a representation (chi_gh =
+ *           chi_g chi_h, values +-1).
+ *   d_ws  : device workspace; holds bits, base and the image tables afterwards.
+ *   out   : host; filled (dim too) on success.
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream (dim is
+ * read back).
+ */
+int qcm_sym_sector_build(const qcm_basis *b, const qcm_group *g, void *d_ws, size_t ws_bytes,
+                         size_t *ws_needed, qcm_sym_sector *out, void *stream);
+
+/*
+ * qcm_sym_csr_count — the representatives and the number of stored
+ * elements of each row.
+ *   m       : the model, invariant under the group (t_{g(a)g(b)} = t_ab and
+ *             U_{g(a)} = U_a, bitwise); at most QCM_SYM_MAX_BONDS bonds.
+ *   s       : a sector from qcm_sym_sector_build with s->b.L == m->L.
+ *   d_rep   : device uint32 [s->dim], receives the representatives' labels.
+ *   d_rowptr: device int64 [s->dim + 1], receives the row pointers.
+ *   h_nnz   : host, receives the number of stored elements.
+ *   d_ws    : device workspace (prefix-sum partials).
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_sym_csr_count(const qcm_model *m, const qcm_sym_sector *s, uint32_t *d_rep,
+                      int64_t *d_rowptr, int64_t *h_nnz, void *d_ws, size_t ws_bytes,
+                      size_t *ws_needed, void *stream);
+
+/*
+ * qcm_sym_csr_fill — the columns and values, into d_col (uint32 [nnz]) and
+ * d_val (double [nnz]), device, from the d_rep and d_rowptr of
+ * qcm_sym_csr_count with the same model and sector.  Errors: QCM_EARG,
+ * QCM_EHIP.  Asynchronous.
+ */
+int qcm_sym_csr_fill(const qcm_model *m, const qcm_sym_sector *s, const uint32_t *d_rep,
+                     const int64_t *d_rowptr, uint32_t *d_col, double *d_val, void *stream);
+
+/*
+ * qcm_sym_hv — w = H v with the stored matrix, for nvec consecutive FP64
+ * vectors of length h->dim (device, not overlapping).  Errors: QCM_EARG,
+ * QCM_EHIP.  Asynchronous.
+ */
+int qcm_sym_hv(const qcm_sym_csr *h, const double *d_v, double *d_w, int32_t nvec, void *stream);
+
+/*
+ * qcm_sym_lanczos_gs — the Lanczos ground state of the irrep (the same
+ * recurrence, tests, two passes and results as qcm_lanczos_gs, on the stored
+ * matrix).  o->prec must be QCM_FP64; d_gs is a device double [h->dim] in the
+ * symmetry-adapted basis.  Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.
+ * Synchronises the stream.
+ */
+int qcm_sym_lanczos_gs(const qcm_sym_csr *h, const qcm_lanczos_opts *o, double *h_alpha,
+                       double *h_beta, void *d_gs, qcm_gs_result *h_out, void *d_ws,
+                       size_t ws_bytes, size_t *ws_needed, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched and continuously served solves.
  *
  * A job is a model, a sector and (optionally) a block of orbitals: the

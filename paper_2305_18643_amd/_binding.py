@@ -75,6 +75,23 @@ class Bond(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("t", ctypes.c_double)]
 
 
+class Group(ctypes.Structure):
+    _fields_ = [("n_g", ctypes.c_int32), ("pad", ctypes.c_int32), ("perm", _c_i32), ("chi", _c_i32)]
+
+
+class SymSectorC(ctypes.Structure):
+    _fields_ = [("b", Basis), ("n_g", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("chi", ctypes.c_int32 * 8), ("perm", ctypes.c_int8 * 256),
+                ("dim", ctypes.c_int64), ("n_words", ctypes.c_int64),
+                ("bits", ctypes.c_void_p), ("base", ctypes.c_void_p),
+                ("img_up", ctypes.c_void_p), ("img_dn", ctypes.c_void_p)]
+
+
+class SymCsrC(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rep", ctypes.c_void_p),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class EngineOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("reorth", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("gs_fixed_steps", ctypes.c_int32),
@@ -112,7 +129,8 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
-           "qcm_cdmft_fit", "qcm_vca_omega"]
+           "qcm_cdmft_fit", "qcm_vca_omega", "qcm_sym_sector_build", "qcm_sym_csr_count",
+           "qcm_sym_csr_fill", "qcm_sym_hv", "qcm_sym_lanczos_gs"]
 
 _lib = None
 
@@ -187,6 +205,18 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_cdmft_fit.restype = ctypes.c_int
     lib.qcm_cdmft_fit.argtypes = [I32, I32, I32, _c_d, _c_d, _c_d, I32, _c_d, _c_d, vp, _c_d, D,
                                   I32, _c_d, _c_i32, vp, sz, _c_sz, vp]
+    lib.qcm_sym_sector_build.restype = ctypes.c_int
+    lib.qcm_sym_sector_build.argtypes = [P(Basis), P(Group), vp, sz, _c_sz, P(SymSectorC), vp]
+    lib.qcm_sym_csr_count.restype = ctypes.c_int
+    lib.qcm_sym_csr_count.argtypes = [P(Model), P(SymSectorC), vp, vp, P(ctypes.c_int64), vp, sz,
+                                      _c_sz, vp]
+    lib.qcm_sym_csr_fill.restype = ctypes.c_int
+    lib.qcm_sym_csr_fill.argtypes = [P(Model), P(SymSectorC), vp, vp, vp, vp, vp]
+    lib.qcm_sym_hv.restype = ctypes.c_int
+    lib.qcm_sym_hv.argtypes = [P(SymCsrC), vp, vp, I32, vp]
+    lib.qcm_sym_lanczos_gs.restype = ctypes.c_int
+    lib.qcm_sym_lanczos_gs.argtypes = [P(SymCsrC), P(LanczosOpts), _c_d, _c_d, vp, P(GsResult), vp,
+                                       sz, _c_sz, vp]
     lib.qcm_vca_omega.restype = ctypes.c_int
     lib.qcm_vca_omega.argtypes = [I32, I32, _c_d, _c_d, _c_d, I32, P(Bond), I32, _c_d, D, _c_d, _c_d,
                                   vp, sz, _c_sz, vp]
@@ -761,3 +791,120 @@ def batch_bytes(specs, **opts) -> int:
     need = ctypes.c_size_t(0)
     _check(lib.qcm_batch_solve(ctypes.byref(o), n, jobs, None, None, 0, ctypes.byref(need), None))
     return need.value
+
+
+# ---------------------------------------------------------------- symmetry-adapted sectors
+
+class SymSector:
+    """The representatives of one irrep of an abelian point group in a sector
+    (qcm_sym_sector_build).  perms: [n_g][L] orbital permutations (element 0
+    the identity); chi: the irrep's characters (+1/-1).  Keeps the basis and
+    the workspace alive."""
+
+    def __init__(self, basis: SectorBasis, perms, chi, stream=None):
+        torch = _torch()
+        lib = load_library()
+        self.basis = basis
+        self.perm = np.ascontiguousarray(np.asarray(perms, dtype=np.int32).ravel())
+        self.chi_a = np.ascontiguousarray(np.asarray(chi, dtype=np.int32))
+        self.g = Group(int(self.chi_a.shape[0]), 0, self.perm.ctypes.data_as(_c_i32),
+                       self.chi_a.ctypes.data_as(_c_i32))
+        self.c = SymSectorC()
+        need = ctypes.c_size_t(0)
+        _check(lib.qcm_sym_sector_build(ctypes.byref(basis.c), ctypes.byref(self.g), None, 0,
+                                        ctypes.byref(need), ctypes.byref(self.c), None))
+        self.ws = _workspace(torch, need.value, basis.device)
+        _check(lib.qcm_sym_sector_build(ctypes.byref(basis.c), ctypes.byref(self.g), _ptr(self.ws),
+                                        self.ws.numel(), ctypes.byref(need), ctypes.byref(self.c),
+                                        _stream(torch, stream)))
+        self.device = basis.device
+
+    dim = property(lambda self: self.c.dim)
+
+
+class SymHamiltonian:
+    """The stored matrix of H in a symmetry-adapted sector (qcm_sym_csr_count
+    and qcm_sym_csr_fill); call it as H(v) or H(v, w) for w = H v."""
+
+    def __init__(self, model, sector: SymSector, stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.m = as_model(model)
+        self.sector = sector
+        dim = sector.dim
+        dev = sector.device
+        self.rep = torch.empty(max(dim, 1), dtype=torch.int32, device=dev)
+        self.rowptr = torch.empty(dim + 1, dtype=torch.int64, device=dev)
+        need = ctypes.c_size_t(0)
+        nnz = ctypes.c_int64(0)
+        _check(self.lib.qcm_sym_csr_count(ctypes.byref(self.m.c), ctypes.byref(sector.c), None,
+                                          None, None, None, 0, ctypes.byref(need), None))
+        ws = _workspace(torch, need.value, dev)
+        st = _stream(torch, stream)
+        _check(self.lib.qcm_sym_csr_count(ctypes.byref(self.m.c), ctypes.byref(sector.c),
+                                          _ptr(self.rep), _ptr(self.rowptr), ctypes.byref(nnz),
+                                          _ptr(ws), ws.numel(), ctypes.byref(need), st))
+        self.nnz = nnz.value
+        self.col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.val = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        _check(self.lib.qcm_sym_csr_fill(ctypes.byref(self.m.c), ctypes.byref(sector.c),
+                                         _ptr(self.rep), _ptr(self.rowptr), _ptr(self.col),
+                                         _ptr(self.val), st))
+        self.c = SymCsrC(dim, self.nnz, self.rep.data_ptr(), self.rowptr.data_ptr(),
+                         self.col.data_ptr(), self.val.data_ptr())
+        self.dim = dim
+        self.device = dev
+
+    def __call__(self, v, w=None, stream=None):
+        torch = _torch()
+        if v.dtype != torch.float64 or not v.is_contiguous() or v.numel() % max(self.dim, 1):
+            raise ValueError("v must be contiguous float64 with a multiple of dim elements")
+        nvec = v.numel() // max(self.dim, 1)
+        if w is None:
+            w = torch.empty_like(v)
+        _check(self.lib.qcm_sym_hv(ctypes.byref(self.c), _ptr(v), _ptr(w), nvec,
+                                   _stream(torch, stream)))
+        return w
+
+
+def sym_sector(basis: SectorBasis, perms, chi, stream=None) -> SymSector:
+    return SymSector(basis, perms, chi, stream)
+
+
+def sym_hamiltonian(model, sector: SymSector, stream=None) -> SymHamiltonian:
+    return SymHamiltonian(model, sector, stream)
+
+
+def sym_lanczos_gs(H: SymHamiltonian, *, max_iter=600, fixed_steps=0, want_vector=True,
+                   check_every=1, tol=1e-12, btol=1e-13, seed=1, v0=None, stream=None,
+                   ws=None) -> dict:
+    """Lanczos ground state of a symmetry-adapted sector (FP64); the same
+    results as lanczos_gs, psi in the symmetry-adapted basis."""
+    torch = _torch()
+    lib = load_library()
+    o = LanczosOpts()
+    lib.qcm_lanczos_default_opts(ctypes.byref(o))
+    o.max_iter, o.fixed_steps, o.want_vector = max_iter, fixed_steps, int(want_vector)
+    o.check_every, o.tol, o.btol, o.seed = check_every, tol, btol, seed
+    if v0 is not None:
+        if v0.dtype != torch.float64 or v0.numel() != H.dim:
+            raise ValueError("v0 has the wrong dtype or size")
+        o.d_v0 = v0.data_ptr()
+    need = ctypes.c_size_t(0)
+    _check(lib.qcm_sym_lanczos_gs(ctypes.byref(H.c), ctypes.byref(o), None, None, None, None,
+                                  None, 0, ctypes.byref(need), None))
+    if ws is None or ws.numel() < need.value:
+        ws = _workspace(torch, need.value, H.device)
+    n = max(max_iter, fixed_steps)
+    alpha = np.zeros(n)
+    beta = np.zeros(n)
+    psi = torch.empty(H.dim, dtype=torch.float64, device=H.device) if want_vector else None
+    res = GsResult()
+    _check(lib.qcm_sym_lanczos_gs(ctypes.byref(H.c), ctypes.byref(o), alpha.ctypes.data_as(_c_d),
+                                  beta.ctypes.data_as(_c_d), _ptr(psi), ctypes.byref(res),
+                                  _ptr(ws), ws.numel(), ctypes.byref(need),
+                                  _stream(torch, stream)))
+    M = res.n_iter
+    return dict(e0=res.e0, residual_est=res.residual_est, true_residual=res.true_residual,
+                theta1=res.theta1, n_iter=M, converged=bool(res.converged),
+                breakdown=bool(res.breakdown), alpha=alpha[:M], beta=beta[:M], psi=psi)

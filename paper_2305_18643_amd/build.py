@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqcm.so")
-SOURCES = ["basis.hip", "hv.hip", "hv_split.hip", "lanczos.hip", "green.hip", "cpt.hip", "batch.hip", "band.hip", "cdmft.hip", "vca.hip"]
+SOURCES = ["basis.hip", "hv.hip", "hv_split.hip", "lanczos.hip", "green.hip", "cpt.hip", "batch.hip", "band.hip", "cdmft.hip", "vca.hip", "sym.hip"]
 ARCH = os.environ.get("QCM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

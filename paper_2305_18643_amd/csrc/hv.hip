@@ -314,6 +314,10 @@ int hv_split_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, 
 
 int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s) {
     if (op.dim == 0 || nvec == 0) return QCM_OK;
+    if (op.csr.rowptr) {
+        if (prec != QCM_FP64) return fail(QCM_EARG, "the stored matrix runs in FP64 only");
+        return sym_hv_launch(op.csr, (const double *)v, (double *)w, nvec, s);
+    }
     if (op.split) return hv_split_launch(op, prec, v, w, nvec, s);
     if (prec == QCM_FP64) return hv_launch_t<double>(op, v, w, nvec, s);
     return hv_launch_t<float>(op, v, w, nvec, s);

@@ -181,7 +181,7 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.nchunks = (int)ceil_div(e.dim, kChunk);
     if (e.nchunks < 1) e.nchunks = 1;
     row_shape(op.up.d, op.dn.d, prec, &e.rows, &e.nblk);
-    e.fused = !op.split && op.up.d < 65536 &&
+    e.fused = !op.split && !op.csr.rowptr && op.up.d < 65536 &&
               fused_lds(op.up.d, e.rows, prec, op.md.nbytes, op.md.u_uniform,
                         2 * op.md.nbond) <= kFusedLds;
     e.na = e.fused ? e.nblk : e.nchunks;
@@ -382,19 +382,18 @@ extern "C" void qcm_lanczos_default_opts(qcm_lanczos_opts *o) {
     o->d_v0 = nullptr;
 }
 
-extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_lanczos_opts *o,
-                              double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out,
-                              void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (!ws_needed || !o) return fail(QCM_EARG, "qcm_lanczos_gs: NULL ws_needed or opts");
-    QCM_TRY(validate_model(m));
-    QCM_TRY(check_basis(b, m->L));
+namespace qcm {
+
+int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_opts *o,
+           double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out, void *d_ws,
+           size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!ws_needed || !o) return fail(QCM_EARG, "%s: NULL ws_needed or opts", fn);
     if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
-        return fail(QCM_EARG, "qcm_lanczos_gs: bad prec %d", o->prec);
+        return fail(QCM_EARG, "%s: bad prec %d", fn, o->prec);
     if (o->max_iter < 1 && o->fixed_steps < 1)
-        return fail(QCM_EARG, "qcm_lanczos_gs: max_iter and fixed_steps both < 1");
-    if (o->want_vector && !d_gs && d_ws)
-        return fail(QCM_EARG, "qcm_lanczos_gs: want_vector needs d_gs");
-    if (b->dim < 1) return fail(QCM_EARG, "qcm_lanczos_gs: empty sector");
+        return fail(QCM_EARG, "%s: max_iter and fixed_steps both < 1", fn);
+    if (o->want_vector && !d_gs && d_ws) return fail(QCM_EARG, "%s: want_vector needs d_gs", fn);
+    if (dim < 1) return fail(QCM_EARG, "%s: empty sector", fn);
     const int limit = o->fixed_steps > 0 ? o->fixed_steps : o->max_iter;
     const int every = o->check_every > 0 ? o->check_every : 1;
     // the workspace is laid out by one function, run first without a base to
@@ -404,7 +403,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     double *svec = nullptr, *work = nullptr, *dscal = nullptr;
     GsStatus *status = nullptr;
     auto layout = [&](Carver &cv, hipStream_t st) -> int {
-        QCM_TRY(hv_setup(m, b, cv, &op, st));
+        QCM_TRY(setup(cv, st, &op));
         QCM_TRY(engine_init(e, op, o->prec, 1, limit, o->btol, o->reorth, cv));
         svec = cv.take<double>(limit);
         work = cv.take<double>((size_t)limit * 6);
@@ -417,9 +416,8 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     const size_t need = dry.off + 256;
     *ws_needed = need;
     if (!d_ws) return QCM_OK;
-    if (!h_out) return fail(QCM_EARG, "qcm_lanczos_gs: h_out is NULL");
-    if (ws_bytes < need)
-        return fail(QCM_EWORKSPACE, "qcm_lanczos_gs: workspace %zu < %zu", ws_bytes, need);
+    if (!h_out) return fail(QCM_EARG, "%s: h_out is NULL", fn);
+    if (ws_bytes < need) return fail(QCM_EWORKSPACE, "%s: workspace %zu < %zu", fn, ws_bytes, need);
     hipStream_t s = as_stream(stream);
     Carver cv(d_ws);
     QCM_TRY(layout(cv, s));
@@ -483,7 +481,7 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     if (o->want_vector && d_gs) {
         // second pass: identical recurrence, psi = sum_n s_n v_n
         double *psi = (double *)d_gs;
-        QCM_HIP(hipMemsetAsync(psi, 0, sizeof(double) * b->dim, s));
+        QCM_HIP(hipMemsetAsync(psi, 0, sizeof(double) * dim, s));
         QCM_TRY(engine_reset(e, s));
         QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
         QCM_TRY(engine_normalize(e, s));
@@ -502,6 +500,21 @@ extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_
     }
     *h_out = r;
     return QCM_OK;
+}
+
+}  // namespace qcm
+
+extern "C" int qcm_lanczos_gs(const qcm_model *m, const qcm_basis *b, const qcm_lanczos_opts *o,
+                              double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out,
+                              void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!ws_needed || !o) return fail(QCM_EARG, "qcm_lanczos_gs: NULL ws_needed or opts");
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(b, m->L));
+    auto setup = [&](Carver &cv, hipStream_t st, HvOp *op) -> int {
+        return hv_setup(m, b, cv, op, st);
+    };
+    return gs_run("qcm_lanczos_gs", setup, b->dim, o, h_alpha, h_beta, d_gs, h_out, d_ws,
+                  ws_bytes, ws_needed, stream);
 }
 
 namespace qcm {

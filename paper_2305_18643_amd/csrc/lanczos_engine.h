@@ -2,6 +2,8 @@
 // entry points (internal).
 #pragma once
 
+#include <functional>
+
 #include "qcm_internal.h"
 
 namespace qcm {
@@ -68,5 +70,11 @@ int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, 
                double e0, const int32_t *pidx, double *F, double *G, hipStream_t s);
 int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
                    double *svec, GsStatus *status, hipStream_t s);
+// The ground-state solver of qcm_lanczos_gs over any product: setup carves
+// the product's tables (or, without a base, only sizes them) and fills op.
+using GsSetup = std::function<int(Carver &, hipStream_t, HvOp *)>;
+int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_opts *o,
+           double *h_alpha, double *h_beta, void *d_gs, qcm_gs_result *h_out, void *d_ws,
+           size_t ws_bytes, size_t *ws_needed, void *stream);
 
 }  // namespace qcm

@@ -127,6 +127,15 @@ int build_hop_tables(const ModelDev &md, const SpinTables &st, Carver &cv, HopTa
                      hipStream_t s, int nbond_host, int rowmajor = 0);
 
 // ---------------------------------------------------------------- H.v
+// The stored matrix of a symmetry-adapted sector (sym.hip): rows of H in CSR.
+struct SymCsrDev {
+    int64_t dim = 0;
+    const int64_t *rowptr = nullptr;
+    const uint32_t *col = nullptr;
+    const double *val = nullptr;
+};
+int sym_hv_launch(const SymCsrDev &h, const double *v, double *w, int nvec, hipStream_t s);
+
 struct HvOp {
     ModelDev md;
     SpinTables up, dn;
@@ -137,6 +146,8 @@ struct HvOp {
     uint32_t *inrow_pk = nullptr; // up hops packed for the in-row pass (LDS offset | index | sign)
     HopTables hd_rm;              // down hops, row-major, with neighbour offsets
     int32_t *row_order = nullptr; // rows of V in the order the row-mixing pass takes them
+    // a symmetry-adapted sector's stored matrix; used (FP64 only) when csr.rowptr != nullptr
+    SymCsrDev csr;
 };
 // nvec vectors of length dim, consecutive (stride dim).  prec: QCM_FP64/QCM_FP32V.
 int hv_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s);

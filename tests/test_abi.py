@@ -201,3 +201,61 @@ def test_cdmft_argument_checks(lib):
                              z.ctypes.data_as(b._c_d), None, A.ctypes.data_as(b._c_d), 1e-10, 10,
                              None, None, None, 0, ctypes.byref(need), None) == 0
     assert need.value > 0
+
+
+def test_sym_argument_checks(lib):
+    """The symmetry-adapted calls check the group, its characters, the
+    model's invariance and their sizes before any launch (no GPU needed)."""
+    from paper_2305_18643_amd import _binding as b
+    from oracle import sym as S
+    bas = _fake_basis(b, 4, 2, 2)
+    keep = []
+
+    def build(perms, chi):
+        p = np.ascontiguousarray(np.asarray(perms, dtype=np.int32).ravel())
+        c = np.ascontiguousarray(np.asarray(chi, dtype=np.int32))
+        keep.extend([p, c])
+        g = b.Group(len(c), 0, p.ctypes.data_as(b._c_i32), c.ctypes.data_as(b._c_i32))
+        out = b.SymSectorC()
+        need = ctypes.c_size_t(0)
+        rc = lib.qcm_sym_sector_build(ctypes.byref(bas), ctypes.byref(g), None, 0,
+                                      ctypes.byref(need), ctypes.byref(out), None)
+        return rc, need.value, out
+
+    G = S.c2v_rectangle(2, 2)
+    rc, need, out = build(G, (1, 1, 1, 1))
+    assert rc == 0 and out.n_g == 4 and out.n_words == 1 and out.dim == 0
+    assert need >= 4 * 6 * 4 * 2 + 8 * 2
+    assert list(out.perm[32:36]) == list(G[1])
+    EARG = b.QCM_EARG
+    assert build(G, (1, -1, -1, -1))[0] == EARG          # not a representation
+    assert build(G, (1, 2, 1, 2))[0] == EARG             # characters not +-1
+    assert build([G[1], G[0], G[2], G[3]], (1, 1, 1, 1))[0] == EARG   # identity not first
+    assert build(G[:3], (1, 1, 1))[0] == EARG            # not closed
+    assert build([G[0], [0, 0, 1, 2]], (1, 1))[0] == EARG  # not a permutation
+    assert build([G[0], G[1], G[1], G[0]], (1, 1, 1, 1))[0] == EARG   # repeated element
+    # the count call checks the model against the group before anything else
+    out.bits = out.base = out.img_up = out.img_dn = 4096
+    t = S.nn_hopping(2, 2)
+    U = np.full(4, 4.0)
+    for tt, want in ((t, 0), (t + np.diag([0.1, 0.0, 0.0, 0.0]), EARG)):
+        tt = np.ascontiguousarray(tt)
+        mc = b.Model(4, tt.ctypes.data_as(b._c_d), U.ctypes.data_as(b._c_d))
+        need = ctypes.c_size_t(0)
+        assert lib.qcm_sym_csr_count(ctypes.byref(mc), ctypes.byref(out), None, None, None, None,
+                                     0, ctypes.byref(need), None) == want
+    # the product and the solver
+    h = b.SymCsrC(0, 0, None, None, None, None)
+    assert lib.qcm_sym_hv(ctypes.byref(h), None, None, 1, None) == EARG
+    o = b.LanczosOpts()
+    lib.qcm_lanczos_default_opts(ctypes.byref(o))
+    need = ctypes.c_size_t(0)
+    assert lib.qcm_sym_lanczos_gs(ctypes.byref(h), ctypes.byref(o), None, None, None, None, None,
+                                  0, ctypes.byref(need), None) == EARG     # empty
+    h = b.SymCsrC(10, 30, 4096, 4096, 4096, 4096)
+    assert lib.qcm_sym_lanczos_gs(ctypes.byref(h), ctypes.byref(o), None, None, None, None, None,
+                                  0, ctypes.byref(need), None) == 0
+    assert need.value >= 3 * 8 * 10
+    o.prec = b.QCM_FP32V
+    assert lib.qcm_sym_lanczos_gs(ctypes.byref(h), ctypes.byref(o), None, None, None, None, None,
+                                  0, ctypes.byref(need), None) == EARG
