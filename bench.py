@@ -290,7 +290,6 @@ def cdmft_section(args, torch, q, synth, np):
     Matsubara grid beta = 50 up to omega = 2, uniform weights, stopped when
     no parameter moves by more than 1e-6.  One iteration of the CPU oracle is
     timed beside it (context)."""
-    from oracle import cdmft as C
     s = synth.cdmft_chain_4_4b()
     z = synth.matsubara_grid(s.beta, s.wc)
     w = np.full(z.shape[0], 1.0 / z.shape[0])
@@ -310,6 +309,7 @@ def cdmft_section(args, torch, q, synth, np):
     if not args.no_cpu:
         # CPU baseline: one iteration of the oracle (its Lanczos and continued
         # fractions on one thread, then NumPy / SciPy)
+        from oracle import cdmft as C
         t1 = time.perf_counter()
         Gc, _ = C.cluster_green(s, s.p0, z)
         sig = C.sigma(s, s.p0, z, Gc)
@@ -370,9 +370,8 @@ def sym_section(args, torch, q, synth, np, stream):
     element, the row pointers, v read and w written once) and fixed-step
     Lanczos.  The oracle's one-column routine is timed on a sample of
     columns beside it."""
-    from oracle import sym as S
     m = synth.cluster_4x4(args.U)
-    perms, chi = S.c2v_rectangle(4, 4), S.C2V_IRREPS["A1"]
+    perms, chi = synth.c2v_rectangle(4, 4), synth.C2V_IRREPS["A1"]
     b = q.sector_basis(16, 8, 8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -411,6 +410,7 @@ def sym_section(args, torch, q, synth, np, stream):
            f"({gbs:.0f} GB/s), Lanczos {dt / r['n_iter'] * 1e3:.2f} ms/step, E0 {r['e0']:.12f}")
     if not args.no_cpu:
         from math import comb
+        from oracle import sym as S
         Su = S.strings(16, 8)
         rep = H.rep[:n]
         # exact int64 positions 0 .. n-1, made on the host

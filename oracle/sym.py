@@ -196,49 +196,6 @@ def value_counts(H, digits=9):
     return dict(zip(v.tolist(), c.tolist()))
 
 
-# ---------------------------------------------------------------- groups
-
-def c2v_rectangle(nx: int, ny: int):
-    """The C2v group of an nx x ny rectangle of sites a = x + nx y: the
-    identity, the rotation by pi, the mirror y -> ny-1-y and the mirror
-    x -> nx-1-x, in that order."""
-    def site(x, y):
-        return x + nx * y
-    e, c2, my, mx = [], [], [], []
-    for a in range(nx * ny):
-        x, y = a % nx, a // nx
-        e.append(a)
-        c2.append(site(nx - 1 - x, ny - 1 - y))
-        my.append(site(x, ny - 1 - y))
-        mx.append(site(nx - 1 - x, y))
-    return [e, c2, my, mx]
-
-
-# characters over (identity, C2, mirror y -> -y, mirror x -> -x)
-C2V_IRREPS = {"A1": (1, 1, 1, 1), "A2": (1, 1, -1, -1), "B1": (1, -1, 1, -1), "B2": (1, -1, -1, 1)}
-
-
-def c2_chain(L: int):
-    """The left-right mirror of an L-site chain: identity and a -> L-1-a."""
-    return [list(range(L)), [L - 1 - a for a in range(L)]]
-
-
-C2_IRREPS = {"A": (1, 1), "B": (1, -1)}
-
-
-def nn_hopping(nx: int, ny: int, t: float = -1.0) -> np.ndarray:
-    """Nearest-neighbour hopping matrix of the nx x ny rectangle (a = x + nx y)."""
-    L = nx * ny
-    h = np.zeros((L, L))
-    for a in range(L):
-        x, y = a % nx, a // nx
-        if x + 1 < nx:
-            h[a, a + 1] = h[a + 1, a] = t
-        if y + 1 < ny:
-            h[a, a + nx] = h[a + nx, a] = t
-    return h
-
-
 # ---------------------------------------------------------------- one column at a time
 # The same elements computed for one representative with plain loops and the
 # combinatorial labels of the strings (subsection "Coding of the basis

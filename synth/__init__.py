@@ -2,8 +2,9 @@
 
 This module only builds inputs: hopping matrices t_ij (with the chemical
 potential and bath energies on the diagonal), on-site interactions U_i,
-sectors (N_up, N_dn), frequency grids, momentum grids and CPT lattice
-descriptions.  It holds none of the method's arithmetic.
+sectors (N_up, N_dn), frequency grids, momentum grids, CPT lattice
+descriptions and point-group tables.  It holds none of the method's
+arithmetic.
 
 Conventions:
   * a model is (t, U): t is L x L real symmetric, t_ii = eps_i - mu; U has
@@ -12,6 +13,8 @@ Conventions:
   * "t = -1" means the matrix element t_ij = -1 on every nearest-neighbour
     bond, "t' = 0.3" means t_ij = +0.3 on both diagonals of every plaquette;
   * rectangular clusters number their sites x + nx*y;
+  * a point group is a list of orbital permutations (identity first) and an
+    irrep a tuple of characters, one per element;
   * cluster orbitals come first and bath orbitals after them.
 """
 from __future__ import annotations
@@ -309,3 +312,48 @@ def vca_chain4(U: float = 4.0, mu: float = 2.0, tp: float = -1.0, t: float = -1.
     t_ref = ch(tp) - mu * np.eye(4)
     return VcaSetup(f"chain4_tp{tp}", t_ref, np.full(4, float(U)), 2, 2, h0 - t_ref,
                     [(3, 0, (1, 0, 0), t)], h0)
+
+
+# ---------------------------------------------------------------- point groups
+# Input data of symmetry-adapted sectors: orbital permutations (the same for
+# both spins) and the characters of one-dimensional irreps.
+
+def c2v_rectangle(nx: int, ny: int):
+    """The C2v group of an nx x ny rectangle of sites a = x + nx y: the
+    identity, the rotation by pi, the mirror y -> ny-1-y and the mirror
+    x -> nx-1-x, in that order."""
+    def site(x, y):
+        return x + nx * y
+    e, c2, my, mx = [], [], [], []
+    for a in range(nx * ny):
+        x, y = a % nx, a // nx
+        e.append(a)
+        c2.append(site(nx - 1 - x, ny - 1 - y))
+        my.append(site(x, ny - 1 - y))
+        mx.append(site(nx - 1 - x, y))
+    return [e, c2, my, mx]
+
+
+# characters over (identity, C2, mirror y -> -y, mirror x -> -x)
+C2V_IRREPS = {"A1": (1, 1, 1, 1), "A2": (1, 1, -1, -1), "B1": (1, -1, 1, -1), "B2": (1, -1, -1, 1)}
+
+
+def c2_chain(L: int):
+    """The left-right mirror of an L-site chain: identity and a -> L-1-a."""
+    return [list(range(L)), [L - 1 - a for a in range(L)]]
+
+
+C2_IRREPS = {"A": (1, 1), "B": (1, -1)}
+
+
+def nn_hopping(nx: int, ny: int, t: float = -1.0) -> np.ndarray:
+    """Nearest-neighbour hopping matrix of the nx x ny rectangle (a = x + nx y)."""
+    L = nx * ny
+    h = np.zeros((L, L))
+    for a in range(L):
+        x, y = a % nx, a // nx
+        if x + 1 < nx:
+            h[a, a + 1] = h[a + 1, a] = t
+        if y + 1 < ny:
+            h[a, a + nx] = h[a + nx, a] = t
+    return h

@@ -206,8 +206,8 @@ def test_cdmft_argument_checks(lib):
 def test_sym_argument_checks(lib):
     """The symmetry-adapted calls check the group, its characters, the
     model's invariance and their sizes before any launch (no GPU needed)."""
+    import synth
     from paper_2305_18643_amd import _binding as b
-    from oracle import sym as S
     bas = _fake_basis(b, 4, 2, 2)
     keep = []
 
@@ -222,7 +222,7 @@ def test_sym_argument_checks(lib):
                                       ctypes.byref(need), ctypes.byref(out), None)
         return rc, need.value, out
 
-    G = S.c2v_rectangle(2, 2)
+    G = synth.c2v_rectangle(2, 2)
     rc, need, out = build(G, (1, 1, 1, 1))
     assert rc == 0 and out.n_g == 4 and out.n_words == 1 and out.dim == 0
     assert need >= 4 * 6 * 4 * 2 + 8 * 2
@@ -236,7 +236,7 @@ def test_sym_argument_checks(lib):
     assert build([G[0], G[1], G[1], G[0]], (1, 1, 1, 1))[0] == EARG   # repeated element
     # the count call checks the model against the group before anything else
     out.bits = out.base = out.img_up = out.img_dn = 4096
-    t = S.nn_hopping(2, 2)
+    t = synth.nn_hopping(2, 2)
     U = np.full(4, 4.0)
     for tt, want in ((t, 0), (t + np.diag([0.1, 0.0, 0.0, 0.0]), EARG)):
         tt = np.ascontiguousarray(tt)

@@ -64,8 +64,8 @@ def test_table_3x4stats(q, irrep):
             f = line.split()
             rows[f[0]] = (int(f[1]), [int(x) for x in f[2:]])
     dim, counts = rows[irrep]
-    sec, H = _build(q, S.nn_hopping(4, 3), np.zeros(12), 6, 6, S.c2v_rectangle(4, 3),
-                    S.C2V_IRREPS[irrep])
+    sec, H = _build(q, synth.nn_hopping(4, 3), np.zeros(12), 6, 6, synth.c2v_rectangle(4, 3),
+                    synth.C2V_IRREPS[irrep])
     _, _, _, val = _host(H)
     v, c = np.unique(np.round(val, 9), return_counts=True)
     print(f"  {irrep}: dim {sec.dim}, nnz {H.nnz}")
@@ -74,13 +74,13 @@ def test_table_3x4stats(q, irrep):
 
 
 def _plaquette(tp=0.3, U=4.0, mu=2.0):
-    t = S.nn_hopping(2, 2)
+    t = synth.nn_hopping(2, 2)
     t[0, 3] = t[3, 0] = t[1, 2] = t[2, 1] = tp
     return t - mu * np.eye(4), np.full(4, U)
 
 
 def _ladder():
-    t = S.nn_hopping(3, 2)
+    t = synth.nn_hopping(3, 2)
     t[0, 4] = t[4, 0] = t[1, 3] = t[3, 1] = t[1, 5] = t[5, 1] = t[2, 4] = t[4, 2] = 0.2
     return t - np.diag([2.5, 1.5, 2.5, 2.5, 1.5, 2.5]), np.array([5.0, 3.0, 5.0, 5.0, 3.0, 5.0])
 
@@ -98,10 +98,10 @@ def _m3x4():
 
 
 SMALL = [
-    ("plaquette", _plaquette, S.c2v_rectangle(2, 2), S.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4), (0, 0)]),
-    ("ladder3x2", _ladder, S.c2v_rectangle(3, 2), S.C2V_IRREPS, [(3, 3), (2, 3), (6, 5)]),
-    ("chain6", _chain, S.c2_chain(6), S.C2_IRREPS, [(3, 3), (3, 2)]),
-    ("3x4_B2", _m3x4, S.c2v_rectangle(4, 3), {"B2": S.C2V_IRREPS["B2"]}, [(6, 6)]),
+    ("plaquette", _plaquette, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4), (0, 0)]),
+    ("ladder3x2", _ladder, synth.c2v_rectangle(3, 2), synth.C2V_IRREPS, [(3, 3), (2, 3), (6, 5)]),
+    ("chain6", _chain, synth.c2_chain(6), synth.C2_IRREPS, [(3, 3), (3, 2)]),
+    ("3x4_B2", _m3x4, synth.c2v_rectangle(4, 3), {"B2": synth.C2V_IRREPS["B2"]}, [(6, 6)]),
 ]
 
 
@@ -130,7 +130,7 @@ def test_stored_matrix_matches_oracle(q, name, make, perms, irreps, sectors):
 
 def test_empty_irrep_is_rejected_by_the_solver(q):
     t, U = _plaquette()
-    sec, H = _build(q, t, U, 0, 0, S.c2v_rectangle(2, 2), S.C2V_IRREPS["B1"])
+    sec, H = _build(q, t, U, 0, 0, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS["B1"])
     assert sec.dim == 0 and H.nnz == 0
     with pytest.raises(q.QcmError):
         q.sym_lanczos_gs(H)
@@ -139,7 +139,7 @@ def test_empty_irrep_is_rejected_by_the_solver(q):
 def test_product_matches_oracle(q):
     import torch
     t, U = _m3x4()
-    perms, chi = S.c2v_rectangle(4, 3), S.C2V_IRREPS["A1"]
+    perms, chi = synth.c2v_rectangle(4, 3), synth.C2V_IRREPS["A1"]
     _, Ho = S.sym_hamiltonian(t, U, 6, 6, perms, chi)
     sec, H = _build(q, t, U, 6, 6, perms, chi)
     rng = np.random.default_rng(7)
@@ -159,11 +159,11 @@ def test_ground_state_plaquette_all_irreps(q):
     for nup, ndn in ((2, 2), (2, 1)):
         e_full = np.linalg.eigvalsh(dense.dense_h(t, U, nup, ndn))[0]
         lows = []
-        for irrep, chi in S.C2V_IRREPS.items():
-            basis, Ho = S.sym_hamiltonian(t, U, nup, ndn, S.c2v_rectangle(2, 2), chi)
+        for irrep, chi in synth.C2V_IRREPS.items():
+            basis, Ho = S.sym_hamiltonian(t, U, nup, ndn, synth.c2v_rectangle(2, 2), chi)
             if len(basis) == 0:
                 continue
-            sec, H = _build(q, t, U, nup, ndn, S.c2v_rectangle(2, 2), chi)
+            sec, H = _build(q, t, U, nup, ndn, synth.c2v_rectangle(2, 2), chi)
             r = q.sym_lanczos_gs(H)
             eo = np.linalg.eigvalsh(Ho.toarray())[0]
             assert abs(r["e0"] - eo) <= 1e-10 * max(1.0, abs(eo)), (nup, ndn, irrep)
@@ -174,7 +174,7 @@ def test_ground_state_plaquette_all_irreps(q):
 def test_ground_state_3x4_a1(q):
     g = json.load(open(os.path.join(GOLD, "cluster_3x4.json")))
     t, U = _m3x4()
-    sec, H = _build(q, t, U, 6, 6, S.c2v_rectangle(4, 3), S.C2V_IRREPS["A1"])
+    sec, H = _build(q, t, U, 6, 6, synth.c2v_rectangle(4, 3), synth.C2V_IRREPS["A1"])
     r = q.sym_lanczos_gs(H)
     print(f"  3x4 A1: E0 {r['e0']:.14f} (full sector {g['e0']:.14f}), {r['n_iter']} steps, "
           f"residual {r['true_residual']:.1e}")
@@ -186,7 +186,7 @@ def test_ground_state_3x4_a1(q):
 def test_4x4_a1_full_size_sampled(q):
     import torch
     m = synth.cluster_4x4(8.0)
-    perms, chi = S.c2v_rectangle(4, 4), S.C2V_IRREPS["A1"]
+    perms, chi = synth.c2v_rectangle(4, 4), synth.C2V_IRREPS["A1"]
     sec, H = _build(q, m.t, m.U, 8, 8, perms, chi)
     print(f"  4x4 A1: dim {sec.dim}, nnz {H.nnz}", flush=True)
     assert abs(sec.dim - 165636900 // 4) <= 20000

@@ -21,6 +21,7 @@ import os
 import numpy as np
 import pytest
 
+import synth
 from oracle import dense, sym as S
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table_3x4stats.txt")
@@ -40,8 +41,8 @@ def _table():
 @pytest.mark.parametrize("irrep", ["A1", "A2", "B1", "B2"])
 def test_table_3x4stats(irrep):
     dim, counts = _table()[irrep]
-    G = S.c2v_rectangle(4, 3)
-    basis, H = S.sym_hamiltonian(S.nn_hopping(4, 3), np.zeros(12), 6, 6, G, S.C2V_IRREPS[irrep])
+    G = synth.c2v_rectangle(4, 3)
+    basis, H = S.sym_hamiltonian(synth.nn_hopping(4, 3), np.zeros(12), 6, 6, G, synth.C2V_IRREPS[irrep])
     assert len(basis) == dim
     got = S.value_counts(H)
     want = {round(v, 9): c for v, c in zip(VALUES, counts) if c}
@@ -79,13 +80,13 @@ def _projector_route(t, U, nup, ndn, perms, chi):
 
 
 def _plaquette(tp=0.3, U=4.0, mu=2.0):
-    t = S.nn_hopping(2, 2)
+    t = synth.nn_hopping(2, 2)
     t[0, 3] = t[3, 0] = t[1, 2] = t[2, 1] = tp
     return t - mu * np.eye(4), np.full(4, U)
 
 
 def _ladder():
-    t = S.nn_hopping(3, 2)
+    t = synth.nn_hopping(3, 2)
     t[0, 4] = t[4, 0] = t[1, 3] = t[3, 1] = t[1, 5] = t[5, 1] = t[2, 4] = t[4, 2] = 0.2
     U = np.array([5.0, 3.0, 5.0, 5.0, 3.0, 5.0])
     return t - np.diag([2.5, 1.5, 2.5, 2.5, 1.5, 2.5]), U
@@ -99,9 +100,9 @@ def _chain(L=6):
 
 
 CASES = [
-    ("plaquette", _plaquette, S.c2v_rectangle(2, 2), S.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4)]),
-    ("ladder3x2", _ladder, S.c2v_rectangle(3, 2), S.C2V_IRREPS, [(3, 3), (2, 3), (0, 0)]),
-    ("chain6", _chain, S.c2_chain(6), S.C2_IRREPS, [(3, 3), (3, 2)]),
+    ("plaquette", _plaquette, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4)]),
+    ("ladder3x2", _ladder, synth.c2v_rectangle(3, 2), synth.C2V_IRREPS, [(3, 3), (2, 3), (0, 0)]),
+    ("chain6", _chain, synth.c2_chain(6), synth.C2_IRREPS, [(3, 3), (3, 2)]),
 ]
 
 
@@ -131,9 +132,9 @@ def test_rejects_broken_symmetry():
     t2 = t.copy()
     t2[0, 1] = t2[1, 0] = -1.1
     with pytest.raises(AssertionError):
-        S.sym_hamiltonian(t2, U, 2, 2, S.c2v_rectangle(2, 2), S.C2V_IRREPS["A1"])
+        S.sym_hamiltonian(t2, U, 2, 2, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS["A1"])
     with pytest.raises(AssertionError):
-        S.sym_hamiltonian(t, U, 2, 2, S.c2v_rectangle(2, 2), (1, -1, -1, -1))
+        S.sym_hamiltonian(t, U, 2, 2, synth.c2v_rectangle(2, 2), (1, -1, -1, -1))
 
 
 def test_column_routine_matches_whole_matrix():
@@ -142,14 +143,14 @@ def test_column_routine_matches_whole_matrix():
     first and last 40 columns."""
     from math import comb
     t, U = _ladder()
-    cases = [(t, U, 3, 3, S.c2v_rectangle(3, 2), chi, None) for chi in S.C2V_IRREPS.values()]
-    m3 = S.nn_hopping(4, 3)
+    cases = [(t, U, 3, 3, synth.c2v_rectangle(3, 2), chi, None) for chi in synth.C2V_IRREPS.values()]
+    m3 = synth.nn_hopping(4, 3)
     m3[0, 5] = m3[5, 0] = m3[1, 4] = m3[4, 1] = 0.3     # a t' pair and its mirror images
     m3[2, 7] = m3[7, 2] = m3[3, 6] = m3[6, 3] = 0.3
     m3[4, 9] = m3[9, 4] = m3[5, 8] = m3[8, 5] = 0.3
     m3[6, 11] = m3[11, 6] = m3[7, 10] = m3[10, 7] = 0.3
-    cases.append((m3 - 4 * np.eye(12), np.full(12, 8.0), 6, 6, S.c2v_rectangle(4, 3),
-                  S.C2V_IRREPS["B1"], 40))
+    cases.append((m3 - 4 * np.eye(12), np.full(12, 8.0), 6, 6, synth.c2v_rectangle(4, 3),
+                  synth.C2V_IRREPS["B1"], 40))
     for t_, U_, nup, ndn, perms, chi, edge in cases:
         L = t_.shape[0]
         basis, H = S.sym_hamiltonian(t_, U_, nup, ndn, perms, chi)
@@ -177,6 +178,6 @@ def test_ground_state_3x4_equals_full_sector():
     import synth
     m = synth.cluster_3x4()
     g = json.load(open(os.path.join(os.path.dirname(GOLD), "cluster_3x4.json")))
-    _, H = S.sym_hamiltonian(m.t, m.U, 6, 6, S.c2v_rectangle(4, 3), S.C2V_IRREPS["A1"])
+    _, H = S.sym_hamiltonian(m.t, m.U, 6, 6, synth.c2v_rectangle(4, 3), synth.C2V_IRREPS["A1"])
     e0 = eigsh(H, k=1, which="SA", tol=1e-14)[0][0]
     assert abs(e0 - g["e0"]) <= 1e-10 * abs(g["e0"])
