@@ -417,6 +417,37 @@ int qcm_vca_omega(int32_t L, int32_t R, const double *h_poles, const double *h_Q
                   const double *h_k, double e0, double *h_omega, double *h_per_k, void *d_ws,
                   size_t ws_bytes, size_t *ws_needed, void *stream);
 
+/*
+ * qcm_vca_omega_quad — the same functional by the frequency integral of
+ * eq. (sef4) along the imaginary axis (its numerical form):
+ *   Omega = e0 + 2 mean_k [ -(1/pi) int_0^inf Re ln det(1 - V(k) G'(iw)) dw
+ *                           + tr V(k) / 2 ],
+ * with G'(iw) = Q diag(1/(iw - poles)) Q^T; Re ln det(1 - X), X = V G', comes
+ * from the LU factors of 1 - X, or from -sum_n Re tr(X^n)/n where
+ * |X|_F <= 1/4 (there the determinant is 1 - O(|X|^2) and would lose the
+ * result to rounding).  Global adaptive Gauss-Kronrod
+ * (7, 15) quadrature on w = c x / (1 - x), x in [0, 1), c = max(1, max |pole|),
+ * starting from 8 equal intervals: each round bisects every interval whose
+ * error estimate |K15 - G7| is at least a quarter of the largest, until the sum
+ * of the estimates is at most max(rtol |integral|, 1e-15 n_k) or max_intervals
+ * is reached.  Its cost grows as R (pole sum) and n_k L^3 per node, not R^3,
+ * so it suits reference systems with many poles.
+ *   arguments as in qcm_vca_omega, with 1 <= R <= QCM_VCA_QUAD_MAX_R, and
+ *   rtol         : relative tolerance of the integral (> 0);
+ *   max_intervals: 8..65536;
+ *   h_omega      : host, receives Omega;
+ *   h_err        : host or NULL, the error estimate carried into Omega;
+ *   h_intervals  : host or NULL, the number of intervals at the end.
+ * Errors: QCM_ERANGE, QCM_EARG (also when 1 - V G' is singular at a node),
+ * QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+#define QCM_VCA_QUAD_MAX_R 4096
+int qcm_vca_omega_quad(int32_t L, int32_t R, const double *h_poles, const double *h_Q,
+                       const double *h_dt, int32_t n_bonds, const qcm_bond *h_bonds, int32_t n_k,
+                       const double *h_k, double e0, double rtol, int32_t max_intervals,
+                       double *h_omega, double *h_err, int32_t *h_intervals, void *d_ws,
+                       size_t ws_bytes, size_t *ws_needed, void *stream);
+
 /* ------------------------------------------------------------------------
  * Symmetry-adapted sectors of an abelian point group with real characters
  * (subsection "Cluster symmetries"; Table 3x4stats).

@@ -129,7 +129,7 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_job_bytes", "qcm_engine_submit", "qcm_engine_step", "qcm_engine_poll",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
-           "qcm_cdmft_fit", "qcm_vca_omega", "qcm_sym_sector_build", "qcm_sym_csr_count",
+           "qcm_cdmft_fit", "qcm_vca_omega", "qcm_vca_omega_quad", "qcm_sym_sector_build", "qcm_sym_csr_count",
            "qcm_sym_csr_fill", "qcm_sym_hv", "qcm_sym_lanczos_gs"]
 
 _lib = None
@@ -217,6 +217,9 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_sym_lanczos_gs.restype = ctypes.c_int
     lib.qcm_sym_lanczos_gs.argtypes = [P(SymCsrC), P(LanczosOpts), _c_d, _c_d, vp, P(GsResult), vp,
                                        sz, _c_sz, vp]
+    lib.qcm_vca_omega_quad.restype = ctypes.c_int
+    lib.qcm_vca_omega_quad.argtypes = [I32, I32, _c_d, _c_d, _c_d, I32, P(Bond), I32, _c_d, D, D, I32,
+                                       _c_d, _c_d, _c_i32, vp, sz, _c_sz, vp]
     lib.qcm_vca_omega.restype = ctypes.c_int
     lib.qcm_vca_omega.argtypes = [I32, I32, _c_d, _c_d, _c_d, I32, P(Bond), I32, _c_d, D, _c_d, _c_d,
                                   vp, sz, _c_sz, vp]
@@ -635,6 +638,31 @@ def vca_omega(e0, poles, Q, dt, bonds, ks, *, device="cuda", stream=None):
     _check(lib.qcm_vca_omega(*args, ctypes.byref(om), per.ctypes.data_as(_c_d), _ptr(ws), ws.numel(),
                              ctypes.byref(need), _stream(torch, stream)))
     return om.value, per
+
+
+def vca_omega_quad(e0, poles, Q, dt, bonds, ks, *, rtol=1e-12, max_intervals=4096,
+                   device="cuda", stream=None):
+    """The same functional by the adaptive frequency integral of eq. (sef4)
+    (qcm_vca_omega_quad).  Returns (Omega, error estimate, intervals)."""
+    torch = _torch()
+    lib = load_library()
+    Q = _f64(Q)
+    L, R = Q.shape
+    poles = _f64(poles, (R,))
+    dt = _f64(dt, (L, L))
+    ks = _f64(ks).reshape(-1, 3)
+    barr, nbond = _bond_array(bonds)
+    om = ctypes.c_double(0.0)
+    err = ctypes.c_double(0.0)
+    niv = ctypes.c_int32(0)
+    need = ctypes.c_size_t(0)
+    args = (L, R, poles.ctypes.data_as(_c_d), Q.ctypes.data_as(_c_d), dt.ctypes.data_as(_c_d), nbond,
+            barr, ks.shape[0], ks.ctypes.data_as(_c_d), float(e0), float(rtol), int(max_intervals))
+    _check(lib.qcm_vca_omega_quad(*args, None, None, None, None, 0, ctypes.byref(need), None))
+    ws = _workspace(torch, need.value, device)
+    _check(lib.qcm_vca_omega_quad(*args, ctypes.byref(om), ctypes.byref(err), ctypes.byref(niv),
+                                  _ptr(ws), ws.numel(), ctypes.byref(need), _stream(torch, stream)))
+    return om.value, err.value, niv.value
 
 
 # ---------------------------------------------------------------- batched / served solves

@@ -3,8 +3,9 @@ subsection "Practical calculation of the Potthoff functional", eq. (omega4)).
 
 The reference's ground state comes from qcm_lanczos_gs, its Lehmann form
 (poles and Q on every cluster orbital) from qcm_green_band, and the k sum of
-the pole formula from qcm_vca_omega.  This module is control flow and
-argument marshalling.
+the pole formula from qcm_vca_omega (or, by the frequency integral of eq.
+(sef4), from qcm_vca_omega_quad).  This module is control flow and argument
+marshalling.
 
 A problem is any object with t_ref [L, L] (reference hopping, -mu on the
 diagonal), U [L], nup, ndn, dt [L, L] (lattice minus reference
@@ -29,8 +30,14 @@ def reference_lehmann(prob, *, max_basis=1000):
     return gs["e0"], poles, np.concatenate(g["Q"], axis=1)
 
 
-def omega(prob, ks, *, max_basis=1000):
-    """The functional (both spins) on the wave-vectors ks."""
+def omega(prob, ks, *, max_basis=1000, method="poles", rtol=1e-12):
+    """The functional (both spins) on the wave-vectors ks, by the pole formula
+    (method "poles") or the adaptive frequency integral ("quad")."""
     e0, poles, Q = reference_lehmann(prob, max_basis=max_basis)
+    if method == "quad":
+        om, _, _ = B.vca_omega_quad(e0, poles, Q, prob.dt, prob.bonds, ks, rtol=rtol)
+        return om
+    if method != "poles":
+        raise ValueError(f"unknown method {method!r}")
     om, _ = B.vca_omega(e0, poles, Q, prob.dt, prob.bonds, ks)
     return om

@@ -259,3 +259,26 @@ def test_sym_argument_checks(lib):
     o.prec = b.QCM_FP32V
     assert lib.qcm_sym_lanczos_gs(ctypes.byref(h), ctypes.byref(o), None, None, None, None, None,
                                   0, ctypes.byref(need), None) == EARG
+
+
+def test_vca_quad_argument_checks(lib):
+    """qcm_vca_omega_quad validates its sizes and tolerances before any
+    launch (no GPU needed)."""
+    from paper_2305_18643_amd import _binding as b
+    L, R = 4, 8
+    poles = np.linspace(-2, 2, R)
+    Q = np.ones((L, R)) / np.sqrt(R)
+    dt = np.zeros((L, L))
+    ks = np.zeros((2, 3))
+    need = ctypes.c_size_t(0)
+
+    def call(R_=R, rtol=1e-10, mi=64, nk=2):
+        return lib.qcm_vca_omega_quad(L, R_, poles.ctypes.data_as(b._c_d), Q.ctypes.data_as(b._c_d),
+                                      dt.ctypes.data_as(b._c_d), 0, None, nk,
+                                      ks.ctypes.data_as(b._c_d), 0.0, rtol, mi, None, None, None,
+                                      None, 0, ctypes.byref(need), None)
+    assert call() == 0 and need.value > 0
+    assert call(rtol=0.0) == b.QCM_EARG
+    assert call(mi=4) == b.QCM_EARG
+    assert call(R_=0) == b.QCM_ERANGE
+    assert call(nk=0) == b.QCM_EARG

@@ -6,7 +6,12 @@
     sum) against the oracle's pole formula, 1e-9, on the 2x2 plaquette at
     U = 8 for three reference hoppings;
   * at U = 0 the functional equals the free lattice grand potential per
-    cluster for any reference hopping (4-site chain), 1e-9.
+    cluster for any reference hopping (4-site chain), 1e-9;
+  * the adaptive frequency integral of eq. (sef4) on the GPU against the
+    oracle's pole formula (1e-9) and its own numerical integral (1e-9), with
+    its error estimate below 1e-9, on the plaquette and the 4-site chain
+    (R = 54); along the whole path against the GPU pole formula, and in the
+    free limit.
 """
 import numpy as np
 import pytest
@@ -59,3 +64,37 @@ def test_vca_noninteracting_is_exact(q, tp):
     ref = O.omega_free(s.h0, s.bonds, ks)
     print(f"  vca chain4 U=0 tp={tp}: omega {om:.12f}, exact {ref:.12f}")
     assert abs(om - ref) <= 1e-9 * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------- frequency integral
+
+@pytest.mark.parametrize("make,grid", [(lambda: synth.vca_plaquette(tp=-1.2), lambda: synth.k_grid_2d(8)),
+                                       (lambda: synth.vca_chain4(tp=-1.1), lambda: synth.k_grid_1d(16))],
+                         ids=["plaquette", "chain4"])
+def test_vca_quad_matches_pole_formula(q, make, grid):
+    """The GPU's adaptive frequency integral against the oracle's pole formula
+    and against the oracle's own numerical integral, from the same Lehmann
+    form (the chain's has R = 54 poles)."""
+    s = make()
+    e0, poles, Q = O.cluster_lehmann(s.t_ref, s.U, s.nup, s.ndn)
+    ks = grid()
+    om, err, niv = q.vca_omega_quad(e0, poles, Q, s.dt, s.bonds, ks, rtol=1e-12)
+    ref = O.omega_poles(e0, poles, Q, s.dt, s.bonds, ks)
+    num = O.omega_numeric(e0, poles, Q, s.dt, s.bonds, ks[:4])
+    om4, _, _ = q.vca_omega_quad(e0, poles, Q, s.dt, s.bonds, ks[:4], rtol=1e-12)
+    print(f"  quad {om:.12f} (pole formula {ref:.12f}), error estimate {err:.1e}, "
+          f"{niv} intervals, R = {len(poles)}")
+    assert abs(om - ref) <= 1e-9 * abs(ref)
+    assert err <= 1e-9 * abs(ref)
+    assert abs(om4 - num) <= 1e-9 * abs(num)
+
+
+def test_vca_quad_full_path_and_free_limit(q):
+    s = synth.vca_plaquette(tp=-1.0)
+    ks = synth.k_grid_2d(16)
+    a = q.vca.omega(s, ks)
+    b = q.vca.omega(s, ks, method="quad")
+    assert abs(a - b) <= 1e-9 * abs(a)
+    f = synth.vca_chain4(U=0.0, mu=0.0, tp=-0.7)
+    k1 = synth.k_grid_1d(32)
+    assert abs(q.vca.omega(f, k1, method="quad") - O.omega_free(f.h0, f.bonds, k1)) <= 1e-9
