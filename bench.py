@@ -343,11 +343,20 @@ def vca_section(args, torch, q, synth, np):
     if 0 < i < len(tps) - 1:       # vertex of the parabola through the three points
         a, b, c = np.polyfit(tps[i - 1:i + 2], om[i - 1:i + 2], 2)
         stat = float(-b / (2 * a))
+    # the same scan by the adaptive frequency integral (eq. (sef4))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    omq = [q.vca.omega(synth.vca_plaquette(tp=tp), ks, method="quad") for tp in tps]
+    torch.cuda.synchronize()
+    dtq = time.perf_counter() - t0
     out = {"workload": "2x2 plaquette reference, square lattice t=-1 U=8 mu=4 (2,2); 32x32 k; "
                        "t' scan of 9 values in [-1.4, -0.6]",
            "s_per_evaluation": round(dt / len(tps), 4), "omega": [float(x) for x in om],
-           "tp": [float(x) for x in tps], "tp_stationary": stat}
-    msg = f"vca: {len(tps)} evaluations in {dt:.2f} s, stationary t' ~ {stat}"
+           "tp": [float(x) for x in tps], "tp_stationary": stat,
+           "quad": {"s_per_evaluation": round(dtq / len(tps), 4),
+                    "max_abs_diff_vs_pole_formula": float(np.max(np.abs(np.array(omq) - om)))}}
+    msg = (f"vca: {len(tps)} evaluations in {dt:.2f} s (quadrature {dtq:.2f} s, max diff "
+           f"{out['quad']['max_abs_diff_vs_pole_formula']:.1e}), stationary t' ~ {stat}")
     if not args.no_cpu:
         from oracle import vca as O
         s = synth.vca_plaquette(tp=-1.0)
