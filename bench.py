@@ -59,7 +59,7 @@ def parse():
 
 
 def measured_traffic(U: float, name="hv_4x4_fp64_hbm_traffic.txt",
-                     sources=("hv.hip", "hv_split.hip")):
+                     sources=("hv.hip", "hv_split.hip"), key="traffic_bytes_per_hv"):
     """HBM bytes per product from a committed counter summary, or None when
     the product kernels changed since the counters were taken (source hash)
     or the workload differs from the one counted (U = 8)."""
@@ -75,9 +75,9 @@ def measured_traffic(U: float, name="hv_4x4_fp64_hbm_traffic.txt",
     h = hashlib.sha256()
     for f in sources:
         h.update(open(os.path.join(ROOT, "paper_2305_18643_amd", "csrc", f), "rb").read())
-    if vals.get("source_sha256") != h.hexdigest():
+    if vals.get("source_sha256") != h.hexdigest() or key not in vals:
         return None
-    return int(vals["traffic_bytes_per_hv"])
+    return int(vals[key])
 
 
 def time_calls(torch, fn, steps, warmup, stream):
@@ -396,13 +396,36 @@ def sym_section(args, torch, q, synth, np, stream):
     ms, _ = time_calls(torch, lambda: H(v, w), args.steps, args.warmup, stream)
     bytes_alg = 12 * nnz + 8 * (n + 1) + 16 * n
     gbs = bytes_alg / (ms * 1e-3) / 1e9
-    del v, w
     steps = args.lanczos_steps
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r = q.sym_lanczos_gs(H, fixed_steps=steps, want_vector=False, check_every=steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
+    # the packed form: one index per distinct value (4 bytes per element)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    nvals = H.pack()
+    torch.cuda.synchronize()
+    t_pack = time.perf_counter() - t3
+    packed = None
+    if nvals:
+        ms_p, _ = time_calls(torch, lambda: H(v, w), args.steps, args.warmup, stream)
+        bytes_p = 4 * nnz + 8 * (n + 1) + 16 * n
+        gbs_p = bytes_p / (ms_p * 1e-3) / 1e9
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rp = q.sym_lanczos_gs(H, fixed_steps=steps, want_vector=False, check_every=steps)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t1
+        packed = {"values": nvals, "pack_s": round(t_pack, 3), "ms": round(ms_p, 4),
+                  "GBps": round(gbs_p, 2), "frac_of_hbm_peak": round(gbs_p / HBM_PEAK_GBS, 4),
+                  "bytes_per_launch": bytes_p, "kernel": "k_sym_spmv_pk",
+                  "traffic": measured_traffic(args.U, "sym_4x4_a1_hbm_traffic.txt", ("sym.hip",),
+                                              "traffic_bytes_per_hv_packed"),
+                  "lanczos_s_per_step": round(dtp / rp["n_iter"], 5),
+                  "e0_rel_diff_vs_explicit": abs(rp["e0"] - r["e0"]) / abs(r["e0"])}
+    del v, w
     gold = os.path.join(ROOT, "tests", "golden", "cluster_4x4.json")
     e_ref = json.load(open(gold))["e0"] if (os.path.exists(gold) and args.U == 8.0) else None
     out = {"workload": f"4x4 Hubbard cluster t=-1 U={args.U:g} mu=U/2 (8,8), C2v irrep A1",
@@ -412,11 +435,15 @@ def sym_section(args, torch, q, synth, np, stream):
                   "kernel": "k_sym_spmv",
                   "traffic": measured_traffic(args.U, "sym_4x4_a1_hbm_traffic.txt", ("sym.hip",))},
            "lanczos": {"steps": r["n_iter"], "s_per_step": round(dt / r["n_iter"], 5),
-                       "e0": r["e0"]}}
+                       "e0": r["e0"]},
+           "packed": packed}
     if e_ref is not None:
         out["lanczos"]["e0_rel_diff_vs_full_sector_oracle"] = abs(r["e0"] - e_ref) / abs(e_ref)
     msg = (f"sym 4x4 A1: dim {n}, nnz {nnz}, build {t_build:.2f} s, H.v {ms:.3f} ms "
            f"({gbs:.0f} GB/s), Lanczos {dt / r['n_iter'] * 1e3:.2f} ms/step, E0 {r['e0']:.12f}")
+    if packed:
+        msg += (f"; packed ({nvals} values, {t_pack:.2f} s): H.v {packed['ms']:.3f} ms "
+                f"({packed['GBps']:.0f} GB/s), Lanczos {packed['lanczos_s_per_step'] * 1e3:.2f} ms/step")
     if not args.no_cpu:
         from math import comb
         from oracle import sym as S

@@ -508,7 +508,13 @@ typedef struct qcm_sym_csr {
     const int64_t *rowptr;    /* device [dim + 1] */
     const uint32_t *col;      /* device [nnz] */
     const double *val;        /* device [nnz] */
+    const uint32_t *packed;   /* device [nnz] or NULL: col | (index into table) << 26, from
+                                 qcm_sym_csr_pack; when set, the product reads it instead of
+                                 col and val */
+    const double *table;      /* device [QCM_SYM_MAX_VALUES] or NULL: the distinct values */
 } qcm_sym_csr;
+
+#define QCM_SYM_MAX_VALUES 64
 
 /*
  * qcm_sym_sector_build — the irrep's representatives of a sector.
@@ -549,6 +555,24 @@ int qcm_sym_csr_count(const qcm_model *m, const qcm_sym_sector *s, uint32_t *d_r
  */
 int qcm_sym_csr_fill(const qcm_model *m, const qcm_sym_sector *s, const uint32_t *d_rep,
                      const int64_t *d_rowptr, uint32_t *d_col, double *d_val, void *stream);
+
+/*
+ * qcm_sym_csr_pack — the stored matrix with one index per value (the paper
+ * suggests storing, for each distinct value, only the positions of its
+ * elements).  When the matrix holds at most QCM_SYM_MAX_VALUES distinct
+ * values and h->dim <= 2^26, writes every element as
+ * col | (index of its value) << 26 into d_packed (device uint32 [nnz]) and the
+ * distinct values, ascending, into d_table (device double
+ * [QCM_SYM_MAX_VALUES]); *h_n_values receives their number.  Otherwise
+ * *h_n_values = 0 and nothing is written.  h itself is not modified: set its
+ * packed and table fields to use the result.  The packed product reads four
+ * bytes per element instead of twelve; it sums the same products in another
+ * order than the explicit one (equal up to rounding).
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ */
+int qcm_sym_csr_pack(const qcm_sym_csr *h, uint32_t *d_packed, double *d_table,
+                     int32_t *h_n_values, void *d_ws, size_t ws_bytes, size_t *ws_needed,
+                     void *stream);
 
 /*
  * qcm_sym_hv — w = H v with the stored matrix, for nvec consecutive FP64

@@ -89,7 +89,8 @@ class SymSectorC(ctypes.Structure):
 
 class SymCsrC(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rep", ctypes.c_void_p),
-                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p), ("table", ctypes.c_void_p)]
 
 
 class EngineOpts(ctypes.Structure):
@@ -130,7 +131,7 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
            "qcm_cdmft_fit", "qcm_vca_omega", "qcm_vca_omega_quad", "qcm_sym_sector_build", "qcm_sym_csr_count",
-           "qcm_sym_csr_fill", "qcm_sym_hv", "qcm_sym_lanczos_gs"]
+           "qcm_sym_csr_fill", "qcm_sym_csr_pack", "qcm_sym_hv", "qcm_sym_lanczos_gs"]
 
 _lib = None
 
@@ -212,6 +213,8 @@ def load_library(path: str = LIB_PATH):
                                       _c_sz, vp]
     lib.qcm_sym_csr_fill.restype = ctypes.c_int
     lib.qcm_sym_csr_fill.argtypes = [P(Model), P(SymSectorC), vp, vp, vp, vp, vp]
+    lib.qcm_sym_csr_pack.restype = ctypes.c_int
+    lib.qcm_sym_csr_pack.argtypes = [P(SymCsrC), vp, vp, _c_i32, vp, sz, _c_sz, vp]
     lib.qcm_sym_hv.restype = ctypes.c_int
     lib.qcm_sym_hv.argtypes = [P(SymCsrC), vp, vp, I32, vp]
     lib.qcm_sym_lanczos_gs.restype = ctypes.c_int
@@ -879,9 +882,40 @@ class SymHamiltonian:
                                          _ptr(self.rep), _ptr(self.rowptr), _ptr(self.col),
                                          _ptr(self.val), st))
         self.c = SymCsrC(dim, self.nnz, self.rep.data_ptr(), self.rowptr.data_ptr(),
-                         self.col.data_ptr(), self.val.data_ptr())
+                         self.col.data_ptr(), self.val.data_ptr(), None, None)
         self.dim = dim
         self.device = dev
+        self.packed = None
+        self.table = None
+        self.n_values = 0
+
+    def pack(self, stream=None) -> int:
+        """Store one index per value (qcm_sym_csr_pack); afterwards the product
+        and the solver read the packed elements.  Returns the number of
+        distinct values, or 0 when the matrix does not fit the format (then the
+        explicit elements stay in use)."""
+        torch = _torch()
+        need = ctypes.c_size_t(0)
+        _check(self.lib.qcm_sym_csr_pack(ctypes.byref(self.c), None, None, None, None, 0,
+                                         ctypes.byref(need), None))
+        ws = _workspace(torch, need.value, self.device)
+        pk = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        tab = torch.zeros(64, dtype=torch.float64, device=self.device)
+        n = ctypes.c_int32(0)
+        _check(self.lib.qcm_sym_csr_pack(ctypes.byref(self.c), _ptr(pk), _ptr(tab), ctypes.byref(n),
+                                         _ptr(ws), ws.numel(), ctypes.byref(need),
+                                         _stream(torch, stream)))
+        self.n_values = n.value
+        if n.value:
+            self.packed, self.table = pk, tab
+            self.c.packed, self.c.table = pk.data_ptr(), tab.data_ptr()
+        return n.value
+
+    def unpack(self):
+        """Go back to the explicit elements."""
+        self.packed = self.table = None
+        self.c.packed = self.c.table = None
+        self.n_values = 0
 
     def __call__(self, v, w=None, stream=None):
         torch = _torch()

@@ -133,6 +133,8 @@ struct SymCsrDev {
     const int64_t *rowptr = nullptr;
     const uint32_t *col = nullptr;
     const double *val = nullptr;
+    const uint32_t *pk = nullptr;    // col | value index << 26, or null
+    const double *tab = nullptr;     // the distinct values when pk is set
 };
 int sym_hv_launch(const SymCsrDev &h, const double *v, double *w, int nvec, hipStream_t s);
 

@@ -35,7 +35,15 @@ constexpr int kSymBonds = QCM_SYM_MAX_BONDS;
 constexpr int kSymE = 2 * kSymBonds + 1;   // entries of one column before merging
 constexpr int kCsrWaves = 4;               // columns per 256-thread workgroup
 constexpr int kScanB = 1024;               // elements per prefix-sum block
-constexpr int kSpmvLanes = 8;              // lanes per stored row
+constexpr int kSpmvLanes = 8;              // lanes per stored row (explicit elements)
+constexpr int kPkLanes = 4;                // lanes per stored row (packed elements)
+constexpr int kMaxVals = QCM_SYM_MAX_VALUES;
+constexpr int kColBits = 26;               // packed element: column in the low 26 bits
+constexpr uint32_t kColMask = (1u << kColBits) - 1u;
+constexpr int kPackChunk = 16384;          // values per deduplicating workgroup
+constexpr int kBlockSet = 256;             // its LDS hash set
+constexpr int kMergeSet = 1024;            // the merging workgroup's set
+constexpr unsigned long long kEmptyKey = ~0ull;   // a NaN pattern: never a stored value
 
 struct SymPerm {
     int32_t n_g, L;
@@ -342,10 +350,144 @@ __global__ void __launch_bounds__(256)
         for (int64_t k = rowptr[r] + sub; k < e; k += kSpmvLanes)
             acc = fma(val[k], v[off + col[k]], acc);
     }
-    acc += __shfl_xor(acc, 4);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 1);
+    for (int m = kSpmvLanes / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
     if (sub == 0 && r < dim) w[off + r] = acc;
+}
+
+// w = H v from the packed elements (kPkLanes lanes per row: with 4-byte
+// elements, more rows per wave in flight pay more than longer row segments)
+__global__ void __launch_bounds__(256)
+    k_sym_spmv_pk(const int64_t *__restrict__ rowptr, const uint32_t *__restrict__ pk,
+                  const double *__restrict__ table, int64_t dim, const double *__restrict__ v,
+                  double *__restrict__ w) {
+    __shared__ double tab[kMaxVals];
+    if (threadIdx.x < kMaxVals) tab[threadIdx.x] = table[threadIdx.x];
+    __syncthreads();
+    const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kPkLanes;
+    const int sub = threadIdx.x & (kPkLanes - 1);
+    const int64_t off = (int64_t)blockIdx.y * dim;
+    double acc = 0.0;
+    if (r < dim) {
+        const int64_t e = rowptr[r + 1];
+        for (int64_t k = rowptr[r] + sub; k < e; k += kPkLanes) {
+            const uint32_t x = pk[k];
+            acc = fma(tab[x >> kColBits], v[off + (x & kColMask)], acc);
+        }
+    }
+    for (int m = kPkLanes / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    if (sub == 0 && r < dim) w[off + r] = acc;
+}
+
+__device__ __forceinline__ uint32_t mix64(unsigned long long x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+
+// Insert a 64-bit key into an LDS open-addressing set of cap (a power of two)
+// slots; false when the set is full.
+__device__ bool lds_set_insert(unsigned long long *set, int cap, unsigned long long key) {
+    uint32_t h = mix64(key) & (uint32_t)(cap - 1);
+    for (int probe = 0; probe < cap; ++probe) {
+        const unsigned long long cur = set[h];
+        if (cur == key) return true;
+        if (cur == kEmptyKey) {
+            const unsigned long long old = atomicCAS(&set[h], kEmptyKey, key);
+            if (old == kEmptyKey || old == key) return true;
+        }
+        h = (h + 1) & (uint32_t)(cap - 1);
+    }
+    return false;
+}
+
+// The distinct values of one chunk of kPackChunk stored values, into the
+// chunk's own segment of kMaxVals slots; flag when there are more.
+__global__ void __launch_bounds__(256)
+    k_sym_vals_block(const double *__restrict__ val, int64_t nnz, unsigned long long *__restrict__ seg,
+                     int32_t *__restrict__ segn, int32_t *__restrict__ overflow) {
+    __shared__ unsigned long long set[kBlockSet];
+    __shared__ int full;
+    const int t = threadIdx.x;
+    for (int e = t; e < kBlockSet; e += blockDim.x) set[e] = kEmptyKey;
+    if (t == 0) full = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kPackChunk;
+    const int64_t end = base + kPackChunk < nnz ? base + kPackChunk : nnz;
+    for (int64_t i = base + t; i < end; i += blockDim.x)
+        if (!lds_set_insert(set, kBlockSet, (unsigned long long)__double_as_longlong(val[i]))) full = 1;
+    __syncthreads();
+    if (t == 0) {
+        int n = 0;
+        for (int e = 0; e < kBlockSet; ++e)
+            if (set[e] != kEmptyKey) {
+                if (n < kMaxVals) seg[(int64_t)blockIdx.x * kMaxVals + n] = set[e];
+                ++n;
+            }
+        segn[blockIdx.x] = n < kMaxVals ? n : kMaxVals;
+        if (n > kMaxVals || full) overflow[0] = 1;
+    }
+}
+
+// Merge the segments in one workgroup; the table is the distinct values in
+// ascending order (each value's index is its rank).
+__global__ void __launch_bounds__(1024)
+    k_sym_vals_merge(const unsigned long long *__restrict__ seg, const int32_t *__restrict__ segn,
+                     int64_t nb, double *__restrict__ table, int32_t *__restrict__ nvals,
+                     int32_t *__restrict__ overflow) {
+    __shared__ unsigned long long set[kMergeSet];
+    __shared__ unsigned long long vals[kMaxVals];
+    __shared__ int full, m;
+    const int t = threadIdx.x;
+    for (int e = t; e < kMergeSet; e += blockDim.x) set[e] = kEmptyKey;
+    if (t == 0) {
+        full = 0;
+        m = 0;
+    }
+    __syncthreads();
+    for (int64_t e = t; e < nb * kMaxVals; e += blockDim.x) {
+        const int64_t b = e / kMaxVals;
+        const int j = (int)(e % kMaxVals);
+        if (j < segn[b] && !lds_set_insert(set, kMergeSet, seg[e])) full = 1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int n = 0;
+        for (int e = 0; e < kMergeSet; ++e)
+            if (set[e] != kEmptyKey) {
+                if (n < kMaxVals) vals[n] = set[e];
+                ++n;
+            }
+        m = n;
+        if (n > kMaxVals || full) overflow[0] = 1;
+    }
+    __syncthreads();
+    const int n = m < kMaxVals ? m : kMaxVals;
+    if (t < n) {
+        const double x = __longlong_as_double((long long)vals[t]);
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += __longlong_as_double((long long)vals[j]) < x;
+        table[rank] = x;
+    }
+    if (t == 0) nvals[0] = m;
+}
+
+__global__ void __launch_bounds__(256)
+    k_sym_pack(const uint32_t *__restrict__ col, const double *__restrict__ val, int64_t nnz,
+               const double *__restrict__ table, int n, uint32_t *__restrict__ pk) {
+    __shared__ double tab[kMaxVals];
+    if (threadIdx.x < n) tab[threadIdx.x] = table[threadIdx.x];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnz) return;
+    const double x = val[i];
+    int lo = 0, hi = n - 1;   // x is in the table
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    pk[i] = col[i] | ((uint32_t)lo << kColBits);
 }
 
 // ---------------------------------------------------------------- host
@@ -467,8 +609,13 @@ static int model_args(const qcm_model *m, const qcm_sym_sector *s, SymModelDev *
 
 int sym_hv_launch(const SymCsrDev &h, const double *v, double *w, int nvec, hipStream_t s) {
     if (h.dim == 0 || nvec == 0) return QCM_OK;
-    const dim3 grid((unsigned)ceil_div((size_t)h.dim * kSpmvLanes, 256), (unsigned)nvec);
-    k_sym_spmv<<<grid, 256, 0, s>>>(h.rowptr, h.col, h.val, h.dim, v, w);
+    if (h.pk) {
+        const dim3 grid((unsigned)ceil_div((size_t)h.dim * kPkLanes, 256), (unsigned)nvec);
+        k_sym_spmv_pk<<<grid, 256, 0, s>>>(h.rowptr, h.pk, h.tab, h.dim, v, w);
+    } else {
+        const dim3 grid((unsigned)ceil_div((size_t)h.dim * kSpmvLanes, 256), (unsigned)nvec);
+        k_sym_spmv<<<grid, 256, 0, s>>>(h.rowptr, h.col, h.val, h.dim, v, w);
+    }
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }
@@ -594,8 +741,75 @@ static int check_csr(const qcm_sym_csr *h, const char *fn) {
     if (!h) return fail(QCM_EARG, "%s: matrix is NULL", fn);
     if (h->dim < 0 || h->dim >= ((int64_t)1 << 32) || h->nnz < 0)
         return fail(QCM_EARG, "%s: bad sizes", fn);
+    if (h->packed) {
+        if (!h->table) return fail(QCM_EARG, "%s: packed elements without their table", fn);
+        if (h->dim > ((int64_t)1 << kColBits))
+            return fail(QCM_EARG, "%s: packed elements need dim <= 2^%d", fn, kColBits);
+        if (h->dim > 0 && !h->rowptr) return fail(QCM_EARG, "%s: NULL row pointers", fn);
+        return QCM_OK;
+    }
     if (h->dim > 0 && (!h->rowptr || (h->nnz > 0 && (!h->col || !h->val))))
         return fail(QCM_EARG, "%s: NULL matrix array", fn);
+    return QCM_OK;
+}
+
+static SymCsrDev csr_dev(const qcm_sym_csr *h) {
+    SymCsrDev d;
+    d.dim = h->dim;
+    d.rowptr = h->rowptr;
+    d.col = h->col;
+    d.val = h->val;
+    d.pk = h->packed;
+    d.tab = h->table;
+    return d;
+}
+
+extern "C" int qcm_sym_csr_pack(const qcm_sym_csr *h, uint32_t *d_packed, double *d_table,
+                                int32_t *h_n_values, void *d_ws, size_t ws_bytes, size_t *ws_needed,
+                                void *stream) {
+    const char *who = "qcm_sym_csr_pack";
+    if (!ws_needed) return fail(QCM_EARG, "%s: ws_needed is NULL", who);
+    QCM_TRY(check_csr(h, who));
+    if (h->nnz > 0 && (!h->col || !h->val))
+        return fail(QCM_EARG, "%s: packing needs the explicit columns and values", who);
+    const int64_t nb = h->nnz > 0 ? (int64_t)ceil_div((size_t)h->nnz, kPackChunk) : 0;
+    struct {
+        unsigned long long *seg;
+        int32_t *segn, *flags;
+        double *tab;
+    } P;
+    auto layout = [&](Carver &cv) {
+        P.seg = cv.take<unsigned long long>((size_t)(nb > 0 ? nb : 1) * kMaxVals);
+        P.segn = cv.take<int32_t>(nb > 0 ? nb : 1);
+        P.flags = cv.take<int32_t>(2);
+        P.tab = cv.take<double>(kMaxVals);
+    };
+    Carver dry(nullptr);
+    layout(dry);
+    const size_t need = dry.off + 256;
+    *ws_needed = need;
+    if (!d_ws) return QCM_OK;
+    if (ws_bytes < need) return fail(QCM_EWORKSPACE, "%s: workspace %zu < %zu", who, ws_bytes, need);
+    if (!h_n_values || !d_packed || !d_table) return fail(QCM_EARG, "%s: NULL output", who);
+    *h_n_values = 0;
+    if (h->nnz == 0 || h->dim > ((int64_t)1 << kColBits)) return QCM_OK;
+    hipStream_t s = as_stream(stream);
+    Carver cv(d_ws);
+    layout(cv);
+    QCM_HIP(hipMemsetAsync(P.flags, 0, 2 * sizeof(int32_t), s));
+    k_sym_vals_block<<<(unsigned)nb, 256, 0, s>>>(h->val, h->nnz, P.seg, P.segn, P.flags);
+    k_sym_vals_merge<<<1, 1024, 0, s>>>(P.seg, P.segn, nb, P.tab, P.flags + 1, P.flags);
+    QCM_LAUNCH_CHECK();
+    int32_t fl[2] = {0, 0};
+    QCM_HIP(hipMemcpyAsync(fl, P.flags, sizeof fl, hipMemcpyDeviceToHost, s));
+    QCM_HIP(hipStreamSynchronize(s));
+    if (fl[0] || fl[1] < 1 || fl[1] > kMaxVals) return QCM_OK;   // does not fit the format
+    QCM_HIP(hipMemcpyAsync(d_table, P.tab, sizeof(double) * fl[1], hipMemcpyDeviceToDevice, s));
+    k_sym_pack<<<(unsigned)ceil_div((size_t)h->nnz, 256), 256, 0, s>>>(h->col, h->val, h->nnz, P.tab,
+                                                                     fl[1], d_packed);
+    QCM_LAUNCH_CHECK();
+    QCM_HIP(hipStreamSynchronize(s));
+    *h_n_values = fl[1];
     return QCM_OK;
 }
 
@@ -608,8 +822,7 @@ extern "C" int qcm_sym_hv(const qcm_sym_csr *h, const double *d_v, double *d_w, 
     const char *v = (const char *)d_v, *w = (const char *)d_w;
     if (h->dim > 0 && v < w + bytes && w < v + bytes)
         return fail(QCM_EARG, "qcm_sym_hv: v and w overlap");
-    SymCsrDev d{h->dim, h->rowptr, h->col, h->val};
-    return sym_hv_launch(d, d_v, d_w, nvec, as_stream(stream));
+    return sym_hv_launch(csr_dev(h), d_v, d_w, nvec, as_stream(stream));
 }
 
 extern "C" int qcm_sym_lanczos_gs(const qcm_sym_csr *h, const qcm_lanczos_opts *o,
@@ -623,7 +836,7 @@ extern "C" int qcm_sym_lanczos_gs(const qcm_sym_csr *h, const qcm_lanczos_opts *
         op->dim = h->dim;
         op->up.d = h->dim;
         op->dn.d = 1;
-        op->csr = SymCsrDev{h->dim, h->rowptr, h->col, h->val};
+        op->csr = csr_dev(h);
         return QCM_OK;
     };
     return gs_run("qcm_sym_lanczos_gs", setup, h->dim, o, h_alpha, h_beta, d_gs, h_out, d_ws,

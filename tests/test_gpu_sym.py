@@ -16,7 +16,12 @@
   * the 4x4 cluster's A1 sector at full size (165,636,900 states, about
     41 million representatives): sampled rows against the oracle's
     one-column routine, sampled label windows against its representative
-    test, and the symmetry of the stored matrix.
+    test, the symmetry of the stored matrix, and its packed form;
+  * the packed form (one index per distinct value): its table is the
+    distinct values, its elements decode to the explicit ones, its product
+    matches the oracle to 64 eps (|H| |v|)_i and its ground state the
+    explicit one to 1e-12; a matrix with more than 64 distinct values is not
+    packed.
 """
 import json
 import os
@@ -92,6 +97,14 @@ def _chain(L=6):
     return t - 2.0 * np.eye(L), np.full(L, 4.0)
 
 
+def _chain7():
+    t = np.zeros((7, 7))
+    for a in range(6):
+        t[a, a + 1] = t[a + 1, a] = -1.0 - 0.05 * min(a, 5 - a)
+    t[0, 6] = t[6, 0] = 0.3
+    return t - np.diag([1.0, 2.0, 3.0, 4.0, 3.0, 2.0, 1.0]), np.array([3.0, 4.0, 5.0, 6.0, 5.0, 4.0, 3.0])
+
+
 def _m3x4():
     m = synth.cluster_3x4()
     return m.t, m.U
@@ -101,6 +114,8 @@ SMALL = [
     ("plaquette", _plaquette, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4), (0, 0)]),
     ("ladder3x2", _ladder, synth.c2v_rectangle(3, 2), synth.C2V_IRREPS, [(3, 3), (2, 3), (6, 5)]),
     ("chain6", _chain, synth.c2_chain(6), synth.C2_IRREPS, [(3, 3), (3, 2)]),
+    ("chain7_odd", _chain7, synth.c2_chain(7), synth.C2_IRREPS, [(3, 4), (4, 2), (7, 0)]),
+    ("trivial_group", _chain7, [list(range(7))], {"A": (1,)}, [(3, 3)]),
     ("3x4_B2", _m3x4, synth.c2v_rectangle(4, 3), {"B2": synth.C2V_IRREPS["B2"]}, [(6, 6)]),
 ]
 
@@ -219,6 +234,74 @@ def test_4x4_a1_full_size_sampled(q):
     gen = torch.Generator(device="cuda").manual_seed(5)
     u = torch.rand(sec.dim, dtype=torch.float64, device="cuda", generator=gen) - 0.5
     v = torch.rand(sec.dim, dtype=torch.float64, device="cuda", generator=gen) - 0.5
-    a = torch.dot(u, H(v)).item()
+    Hv = H(v)
+    a = torch.dot(u, Hv).item()
     b = torch.dot(H(u), v).item()
     assert abs(a - b) <= 1e-10 * abs(a)
+    # packed at full size: a handful of values, the same product up to rounding
+    # (a row holds a diagonal of magnitude <= 64 = U N/2 and at most 48 other
+    # elements of magnitude <= 2, and |v| <= 1/2: (|H| |v|)_i <= 80, and
+    # 64 eps of that is 1.14e-12)
+    n = H.pack()
+    print(f"  4x4 A1: {n} distinct values", flush=True)
+    assert 0 < n <= 64
+    assert torch.max(torch.abs(H(v) - Hv)).item() <= 1.2e-12
+
+
+def test_packed_matrix_matches_explicit(q):
+    """The packed form (one index per value) holds the distinct values,
+    ascending, and its elements decode to the explicit ones; its product (four
+    lanes per row instead of eight, so another summation order) agrees with
+    the oracle's matrix to 64 eps (|H| |v|)_i, and its ground state with the
+    explicit one to 1e-12."""
+    import torch
+    t, U = _m3x4()
+    perms, chi = synth.c2v_rectangle(4, 3), synth.C2V_IRREPS["A1"]
+    _, Ho = S.sym_hamiltonian(t, U, 6, 6, perms, chi)
+    sec, H = _build(q, t, U, 6, 6, perms, chi)
+    val = H.val[:H.nnz].cpu().numpy()
+    vh = np.random.default_rng(3).uniform(-1, 1, (2, sec.dim))
+    v = torch.from_numpy(vh.ravel()).to("cuda")
+    r_exp = q.sym_lanczos_gs(H)
+    n = H.pack()
+    uniq = np.unique(val)
+    print(f"  3x4 A1 with t': {n} distinct values")
+    assert n == len(uniq) and 0 < n <= 64
+    assert np.array_equal(H.table[:n].cpu().numpy(), uniq)
+    pk = H.packed[:H.nnz].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    col = H.col[:H.nnz].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    assert np.array_equal(pk & ((1 << 26) - 1), col)
+    assert np.array_equal(uniq[pk >> 26], val)
+    w = H(v).cpu().numpy().reshape(2, -1)
+    absH = abs(Ho)
+    for k in range(2):
+        bound = 64 * np.finfo(float).eps * (absH @ np.abs(vh[k]))
+        assert np.all(np.abs(w[k] - Ho @ vh[k]) <= bound)
+    r_pk = q.sym_lanczos_gs(H)
+    assert abs(r_pk["e0"] - r_exp["e0"]) <= 1e-12 * abs(r_exp["e0"])
+    H.unpack()
+    assert H.packed is None and torch.equal(H(v), H(v))
+
+
+def test_pack_declines_many_values(q):
+    """A model with random mirror-symmetric hoppings, orbital energies and U
+    has far more than 64 distinct values: the pack reports 0 and the explicit
+    elements stay in use."""
+    import torch
+    rng = np.random.default_rng(11)
+    L = 8
+    t = np.zeros((L, L))
+    for a in range(L):
+        for b in range(a, L):
+            t[a, b] = t[b, a] = rng.normal()
+    perm = [L - 1 - a for a in range(L)]
+    t = 0.5 * (t + t[np.ix_(perm, perm)])
+    U = rng.uniform(1.0, 5.0, L)
+    U = 0.5 * (U + U[perm])
+    sec, H = _build(q, t, U, 4, 4, synth.c2_chain(L), synth.C2_IRREPS["A"])
+    assert len(np.unique(H.val[:H.nnz].cpu().numpy())) > 64
+    assert H.pack() == 0 and H.packed is None
+    basis, Ho = S.sym_hamiltonian(t, U, 4, 4, synth.c2_chain(L), synth.C2_IRREPS["A"])
+    v = np.random.default_rng(2).uniform(-1, 1, sec.dim)
+    w = H(torch.from_numpy(v).to("cuda")).cpu().numpy()
+    assert np.abs(w - Ho @ v).max() <= 1e-12 * np.abs(abs(Ho) @ np.abs(v)).max()

@@ -99,8 +99,18 @@ def _chain(L=6):
     return t - 2.0 * np.eye(L), np.full(L, 4.0)
 
 
+def _chain7():
+    t = np.zeros((7, 7))
+    for a in range(6):
+        t[a, a + 1] = t[a + 1, a] = -1.0 - 0.05 * min(a, 5 - a)
+    t[0, 6] = t[6, 0] = 0.3                  # a long bond the mirror maps to itself
+    return t - np.diag([1.0, 2.0, 3.0, 4.0, 3.0, 2.0, 1.0]), np.array([3.0, 4.0, 5.0, 6.0, 5.0, 4.0, 3.0])
+
+
 CASES = [
     ("plaquette", _plaquette, synth.c2v_rectangle(2, 2), synth.C2V_IRREPS, [(2, 2), (2, 1), (1, 0), (4, 4)]),
+    ("chain7_odd", _chain7, synth.c2_chain(7), synth.C2_IRREPS, [(3, 4), (4, 2), (7, 0)]),
+    ("trivial_group", _chain7, [list(range(7))], {"A": (1,)}, [(3, 3)]),
     ("ladder3x2", _ladder, synth.c2v_rectangle(3, 2), synth.C2V_IRREPS, [(3, 3), (2, 3), (0, 0)]),
     ("chain6", _chain, synth.c2_chain(6), synth.C2_IRREPS, [(3, 3), (3, 2)]),
 ]
