@@ -140,6 +140,10 @@ def main():
     ms, wall = time_calls(torch, hv64, args.steps, args.warmup, stream)
     bytes_alg = 2 * 8 * d
     gbs = bytes_alg / (ms * 1e-3) / 1e9
+    # a plain copy of one vector (read 8 d, write 8 d bytes): the bandwidth a
+    # streaming kernel reaches on this GPU, beside the published peak
+    ms_copy, _ = time_calls(torch, lambda: w.copy_(v), args.steps, args.warmup, stream)
+    copy_gbs = bytes_alg / (ms_copy * 1e-3) / 1e9
 
     out = {
         "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1,
@@ -154,7 +158,9 @@ def main():
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.U),
                      "kernel": "H.v (k_hv_inrow_pk + k_hv_down_acc)",
-                     "bytes_per_launch": bytes_alg},
+                     "bytes_per_launch": bytes_alg,
+                     "copy_kernel_GBps": round(copy_gbs, 1),
+                     "frac_of_copy_kernel": round(gbs / copy_gbs, 4)},
     }
 
     if not args.no_extra:
@@ -209,11 +215,20 @@ def main():
         oracle.hv_rows(m.t, m.U, 8, 8, vh, rows, nthreads=threads)
         dt = time.perf_counter() - t0
         cpu_gbs = 2 * 8 * nrows / dt / 1e9
+        # one core, on every 32nd row
+        rows1 = np.arange(d // 32, dtype=np.int64) * 32
+        t1 = time.perf_counter()
+        oracle.hv_rows(m.t, m.U, 8, 8, vh, rows1, nthreads=1)
+        dt1 = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": round(cpu_gbs, 4), "unit": "GB/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"{nrows} of {d} rows of the same sector (one full "
                                          f"product when equal), FP64, {dt:.1f} s; GB/s counts "
-                                         f"16 bytes per row like the GPU figure"}
+                                         f"16 bytes per row like the GPU figure",
+                               "one_core": {"value": round(2 * 8 * len(rows1) / dt1 / 1e9, 4),
+                                            "unit": "GB/s",
+                                            "sample": f"every 32nd row ({len(rows1)} rows), "
+                                                      f"{dt1:.1f} s"}}
         del vh
     print(json.dumps(out), flush=True)
 

@@ -70,7 +70,7 @@ struct BStat {
 __global__ void __launch_bounds__(256) kb_control(const BCtl *__restrict__ C,
                                                   BStat *__restrict__ out) {
     const BCtl &c = C[blockIdx.x];
-    if (c.test) tridiag_status_block(c.alpha, c.beta, c.m, c.tol, c.work, c.svec, c.status);
+    if (c.test) tridiag_status_block(c.alpha, c.beta, c.m, c.tol, c.work, c.svec, c.status, false);
     if (threadIdx.x == 0) {
         BStat r;
         r.gs = *c.status;

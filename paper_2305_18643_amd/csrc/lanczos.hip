@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict
                                                         const double *__restrict__ beta, int M,
                                                         double tol, double *__restrict__ work,
                                                         double *__restrict__ svec,
-                                                        GsStatus *__restrict__ status) {
-    tridiag_status_block(alpha, beta, M, tol, work, svec, status);
+                                                        GsStatus *__restrict__ status, int want1) {
+    tridiag_status_block(alpha, beta, M, tol, work, svec, status, want1 != 0);
 }
 
 // ---------------------------------------------------------------- engine
@@ -335,8 +335,8 @@ int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t 
 }
 
 int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
-                   double *svec, GsStatus *status, hipStream_t s) {
-    k_tridiag_status<<<1, 256, 0, s>>>(alpha, beta, M, tol, work, svec, status);
+                   double *svec, GsStatus *status, hipStream_t s, int want1) {
+    k_tridiag_status<<<1, 256, 0, s>>>(alpha, beta, M, tol, work, svec, status, want1);
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }
@@ -440,7 +440,7 @@ int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_
         if (check) {
             QCM_HIP(hipMemcpyAsync(&done, e.cs.done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             if (o->fixed_steps <= 0) {
-                QCM_TRY(tridiag_status(e.cs.alpha, e.cs.beta, M, o->tol, work, svec, status, s));
+                QCM_TRY(tridiag_status(e.cs.alpha, e.cs.beta, M, o->tol, work, svec, status, s, 0));
                 QCM_HIP(hipMemcpyAsync(&hs, status, sizeof hs, hipMemcpyDeviceToHost, s));
             }
             QCM_HIP(hipStreamSynchronize(s));

@@ -152,14 +152,16 @@ __device__ inline void tridiag_vector(int M, const double *a, const double *b, d
 constexpr int kTriLds = 640;
 
 // The ground-state test of one workgroup (256 threads) on T_M: theta_0,
-// theta_1, the eigenvector of theta_0 in svec, residual estimate
-// beta[M-1] |s[M-1]| and the convergence flag, written to *status.  Up to
-// kTriLds steps the work happens in LDS; longer T_M use `work` (5 M doubles)
-// and beta^2 in work + 5 M (M doubles).
+// theta_1 (only when want1; the convergence test does not need it, so the
+// tests between steps skip it and the final one takes it), the eigenvector
+// of theta_0 in svec, residual estimate beta[M-1] |s[M-1]| and the
+// convergence flag, written to *status.  Up to kTriLds steps the work happens
+// in LDS; longer T_M use `work` (5 M doubles) and beta^2 in work + 5 M (M
+// doubles).
 __device__ inline void tridiag_status_block(const double *__restrict__ alpha,
                                             const double *__restrict__ beta, int M, double tol,
                                             double *__restrict__ work, double *__restrict__ svec,
-                                            GsStatus *__restrict__ status) {
+                                            GsStatus *__restrict__ status, bool want1 = true) {
     __shared__ double lo, hi;
     __shared__ double la[kTriLds], lb[kTriLds], lb2[kTriLds], lx[kTriLds], lw[5 * kTriLds];
     const bool in_lds = M <= kTriLds;
@@ -181,7 +183,7 @@ __device__ inline void tridiag_status_block(const double *__restrict__ alpha,
     }
     __syncthreads();
     double th0 = tridiag_kth(M, a, b, b2, 0, &lo, &hi);
-    double th1 = M > 1 ? tridiag_kth(M, a, b, b2, 1, &lo, &hi) : NAN;
+    double th1 = (want1 && M > 1) ? tridiag_kth(M, a, b, b2, 1, &lo, &hi) : NAN;
     if (threadIdx.x == 0) {
         const int S = in_lds ? kTriLds : M;
         tridiag_vector(M, a, b, th0, x, w, w + S, w + 2 * S, w + 3 * S, w + 4 * S);

@@ -68,8 +68,9 @@ int green_store(const Engine *e, int npairs, int part, double *coef, int32_t *le
                 hipStream_t s);
 int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, const double *zd,
                double e0, const int32_t *pidx, double *F, double *G, hipStream_t s);
+// want1 = 0: skip theta_1 (status->theta1 = NaN); the tests between steps
 int tridiag_status(const double *alpha, const double *beta, int M, double tol, double *work,
-                   double *svec, GsStatus *status, hipStream_t s);
+                   double *svec, GsStatus *status, hipStream_t s, int want1 = 1);
 // The ground-state solver of qcm_lanczos_gs over any product: setup carves
 // the product's tables (or, without a base, only sizes them) and fills op.
 using GsSetup = std::function<int(Carver &, hipStream_t, HvOp *)>;
