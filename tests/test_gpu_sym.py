@@ -305,3 +305,35 @@ def test_pack_declines_many_values(q):
     v = np.random.default_rng(2).uniform(-1, 1, sec.dim)
     w = H(torch.from_numpy(v).to("cuda")).cpu().numpy()
     assert np.abs(w - Ho @ v).max() <= 1e-12 * np.abs(abs(Ho) @ np.abs(v)).max()
+
+
+def test_chain14_reflection_even_sector(q):
+    """The paper's timed workload in the paper's own sector: the 14-site chain
+    (t = -1, U = 4, mu = 2, (7,7)) in the reflection-even irrep.  With 7
+    particles per spin no state is its own mirror image, so the irrep holds
+    exactly half of the 11,778,624 states (5,889,312, the paper's figure);
+    sampled rows match the oracle's one-column routine, and the ground-state
+    energy equals the full sector's."""
+    m = synth.chain(14, U=4.0, mu=2.0, nup=7, ndn=7)
+    perms, chi = synth.c2_chain(14), synth.C2_IRREPS["A"]
+    sec, H = _build(q, m.t, m.U, 7, 7, perms, chi)
+    assert sec.dim == 5889312
+    d_up = comb(14, 7)
+    Su = S.strings(14, 7)
+    rowptr = H.rowptr.cpu().numpy()
+    import torch
+    for c in np.concatenate([[0, sec.dim - 1], np.random.default_rng(14).integers(0, sec.dim, 60)]):
+        c = int(c)
+        lab = int(H.rep[c].item()) & 0xFFFFFFFF
+        lo, hi = int(rowptr[c]), int(rowptr[c + 1])
+        cols = H.col[lo:hi].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        labs = H.rep[torch.from_numpy(cols).to("cuda")].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        want = S.sym_column(m.t, m.U, int(Su[lab % d_up]), int(Su[lab // d_up]), perms, chi)
+        assert set(labs.tolist()) == set(want)
+        vals = H.val[lo:hi].cpu().numpy()
+        assert max(abs(v - want[int(k)]) for k, v in zip(labs, vals)) <= 1e-13
+    assert H.pack() > 0
+    ra = q.sym_lanczos_gs(H)
+    rf = q.lanczos_gs(m, q.sector_basis(14, 7, 7), want_vector=False)
+    print(f"  chain14 A: E0 {ra['e0']:.12f} (full sector {rf['e0']:.12f}), {ra['n_iter']} steps")
+    assert ra["converged"] and abs(ra["e0"] - rf["e0"]) <= 1e-10 * abs(rf["e0"])
