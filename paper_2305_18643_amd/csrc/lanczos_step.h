@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     double pa = 0.0;
     // one element: diagonal, in-row hops through the packed entries, row-mixing
     // hops from global memory, -beta vp, rounded once
-    auto element = [&](uint32_t r, uint32_t iu, int64_t idn, uint32_t sdn, double edn, int nhd,
-                       const int32_t *__restrict__ cold_r, const double *__restrict__ cfd_r) {
+    // diagonal and in-row part of one element: returns the partial sum and v_i
+    auto in_row = [&](uint32_t r, uint32_t iu, uint32_t sdn, double edn, double *vi_out) -> double {
         const uint32_t dbl = q.su[iu] & sdn;
         double diag = q.eu[iu] + edn;
         if (q.u_uniform >= 0.0) {
@@ -159,8 +159,8 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
         }
         const T *rr = row + (int64_t)r * d_up;
         const double vi = (double)rr[iu];
+        *vi_out = vi;
         double acc = diag * vi;
-        // in-row term
         const int nhu = q.nhu[iu];
         const uint32_t *pp = q.pku + iu;
         int s = 0;
@@ -178,9 +178,24 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             const uint32_t p0 = pp[(int64_t)s * d_up];
             acc = fma(ct[p0 >> 16], (double)rr[p0 & 0xffffu], acc);
         }
+        return acc;
+    };
+    // -beta vp, round once, store, and the <v, w> partial
+    auto finish = [&](int64_t i, double acc, double vi) {
+        if (sub) acc = fma(-b, ldd(vp + i), acc);
+        const T wt = (T)acc;
+        w[i] = wt;
+        pa = fma(vi, (double)wt, pa);
+    };
+    // one element: diagonal, in-row hops through the packed entries, row-mixing
+    // hops from global memory, -beta vp, rounded once
+    auto element = [&](uint32_t r, uint32_t iu, int64_t idn, uint32_t sdn, double edn, int nhd,
+                       const int32_t *__restrict__ cold_r, const double *__restrict__ cfd_r) {
+        double vi;
+        double acc = in_row(r, iu, sdn, edn, &vi);
         // row-mixing term (hop s of row idn at cold_r[s * d_dn])
         const T *vc = v + iu;
-        s = 0;
+        int s = 0;
         for (; s + 4 <= nhd; s += 4) {
             const int64_t e0 = (int64_t)s * d_dn, e1 = e0 + d_dn;
             const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
@@ -197,23 +212,60 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             const int64_t e0 = (int64_t)s * d_dn;
             acc = fma(cfd_r[e0], (double)vc[(int64_t)cold_r[e0] * d_up], acc);
         }
-        const int64_t i = idn * d_up + iu;
-        if (sub) acc = fma(-b, ldd(vp + i), acc);
-        const T wt = (T)acc;
-        w[i] = wt;
-        pa = fma(vi, (double)wt, pa);
+        finish(idn * d_up + iu, acc, vi);
     };
     if (d_up >= 1024) {
         // long rows: the rows one after another, so the row index and its
         // down-hop list are wave-uniform (scalar loads) and no division is
-        // needed; shorter rows keep the packed mapping, which leaves no lane idle
+        // needed.  Each thread takes two elements of the row at a time (iu and
+        // iu + 256): they share the down-hop list, so their row-mixing gathers
+        // are issued together; each element's sum keeps its own order.
         for (uint32_t r = 0; r < (uint32_t)nr; ++r) {
             const int64_t idn = row0 + r;
             const uint32_t sdn = q.sd[idn];
             const double edn = q.ed[idn];
             const int nhd = q.nhd[idn];
-            for (uint32_t iu = threadIdx.x; iu < du; iu += 256)
-                element(r, iu, idn, sdn, edn, nhd, q.cold + idn, q.cfd + idn);
+            const int32_t *__restrict__ cold_r = q.cold + idn;
+            const double *__restrict__ cfd_r = q.cfd + idn;
+            for (uint32_t iu = threadIdx.x; iu < du; iu += 512) {
+                const uint32_t iu2 = iu + 256;
+                if (iu2 >= du) {
+                    element(r, iu, idn, sdn, edn, nhd, cold_r, cfd_r);
+                    continue;
+                }
+                double vi1, vi2;
+                double a1 = in_row(r, iu, sdn, edn, &vi1);
+                double a2 = in_row(r, iu2, sdn, edn, &vi2);
+                const T *vc1 = v + iu, *vc2 = v + iu2;
+                int s = 0;
+                for (; s + 4 <= nhd; s += 4) {
+                    const int64_t e0 = (int64_t)s * d_dn, e1 = e0 + d_dn;
+                    const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
+                    const int64_t o0 = (int64_t)cold_r[e0] * d_up, o1 = (int64_t)cold_r[e1] * d_up;
+                    const int64_t o2 = (int64_t)cold_r[e2] * d_up, o3 = (int64_t)cold_r[e3] * d_up;
+                    const double x0 = (double)vc1[o0], y0 = (double)vc2[o0];
+                    const double x1 = (double)vc1[o1], y1 = (double)vc2[o1];
+                    const double x2 = (double)vc1[o2], y2 = (double)vc2[o2];
+                    const double x3 = (double)vc1[o3], y3 = (double)vc2[o3];
+                    const double c0 = cfd_r[e0], c1 = cfd_r[e1], c2 = cfd_r[e2], c3 = cfd_r[e3];
+                    a1 = fma(c0, x0, a1);
+                    a2 = fma(c0, y0, a2);
+                    a1 = fma(c1, x1, a1);
+                    a2 = fma(c1, y1, a2);
+                    a1 = fma(c2, x2, a1);
+                    a2 = fma(c2, y2, a2);
+                    a1 = fma(c3, x3, a1);
+                    a2 = fma(c3, y3, a2);
+                }
+                for (; s < nhd; ++s) {
+                    const int64_t e0 = (int64_t)s * d_dn;
+                    const int64_t o0 = (int64_t)cold_r[e0] * d_up;
+                    a1 = fma(cfd_r[e0], (double)vc1[o0], a1);
+                    a2 = fma(cfd_r[e0], (double)vc2[o0], a2);
+                }
+                finish(idn * d_up + iu, a1, vi1);
+                finish(idn * d_up + iu2, a2, vi2);
+            }
         }
     } else {
         for (int64_t e = threadIdx.x; e < nel; e += 256) {
