@@ -152,8 +152,9 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_pk(
 
 // Pass B: W += K_dn V on column slabs, hopping lists row-contiguous and
 // wave-uniform (scalar loads), RI rows of a wave with 8 neighbour segments
-// each in flight (RI = 4 with two columns per lane: 2.5 % faster than 2 on
-// the 4x4 sector; 1, 6 or 8 rows, or 32-row slabs, were slower).  When
+// each in flight (FP64 with two columns per lane: RI = 4, 2.5 % faster than 2
+// on the 4x4 sector, while 1, 6 or 8 rows, or 32-row slabs, were slower;
+// FP32 vectors keep RI = 2, four rows slowed them from 2.95 to 4.06 ms).  When
 // d_up is even a lane takes two adjacent columns (one 2-element load per
 // neighbour), which halves the load instructions.  Within a slab the rows are
 // taken in row_order: grouped by the popcount of the high half of the down
@@ -319,8 +320,12 @@ static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipS
     const int64_t total = nslab * nrb;
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
-    if (cw == 2)
+    if (cw == 2 && sizeof(T) == 8)
         k_hv_down_acc<T, 4, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
+                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
+                                                  per, op.row_order);
+    else if (cw == 2)
+        k_hv_down_acc<T, 2, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
                                                   hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
                                                   per, op.row_order);
     else
