@@ -100,7 +100,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sector product "
-              "is not sharded across GPUs in this build", file=sys.stderr)
+              "is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
