@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "lanczos_device.h"
 #include "qcm_internal.h"
 
 namespace qcm {
@@ -181,16 +182,25 @@ struct Pair<float> {
     typedef float2 type;
 };
 
-template <typename T, int RI, int CW>
+// With SP (a Lanczos step): each stored element becomes w - beta' vp (after
+// the product's own rounding, as a separate pass would do it), and every
+// workgroup writes its partial <v, w> to sp.pa[vec * gridDim.x + block] (0
+// for workgroups without rows), a fixed-order block sum.
+
+template <typename T, int RI, int CW, bool SP>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
     const int64_t *__restrict__ offs, const double *__restrict__ cfd, const T *__restrict__ v,
     T *__restrict__ w, const int R, const int64_t nrb, const int64_t total, const int64_t per,
-    const int32_t *__restrict__ order) {
+    const int32_t *__restrict__ order, const SubPrev sp) {
     typedef typename Pair<T>::type T2;
+    __shared__ double sh[256];
     const int64_t p = blockIdx.x;
     const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
-    if (lg >= total) return;
+    if (lg >= total) {
+        if (SP && threadIdx.x == 0) sp.pa[(int64_t)blockIdx.y * gridDim.x + p] = 0.0;
+        return;
+    }
     const int64_t slab = lg / nrb, rb = lg - slab * nrb;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -199,6 +209,19 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t vb = (int64_t)blockIdx.y * d_up * d_dn;
     const T *vv = v + vb;
     T *ww = w + vb;
+    const T *vpp = SP ? (const T *)sp.vp + vb : nullptr;
+    const double bprev = (SP && sp.n > 0) ? sp.beta[(int64_t)blockIdx.y * sp.maxs + sp.n - 1] : 0.0;
+    double part = 0.0;
+    // the element as a separate pass would leave it: product rounded once,
+    // then w - beta' vp rounded once; and its share of <v, w>
+    auto fin = [&](double a, int64_t i) -> T {
+        T t = (T)a;
+        if (SP) {
+            if (sp.n > 0) t = (T)fma(-bprev, (double)vpp[i], (double)t);
+            part = fma((double)vv[i], (double)t, part);
+        }
+        return t;
+    };
     for (int k = wave * RI; k < R; k += 4 * RI) {
         int64_t rr[RI];
         int nh[RI];
@@ -253,16 +276,21 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
 #pragma unroll
             for (int q = 0; q < RI; ++q)
                 if (rb * R + k + q < d_dn) {
+                    const int64_t i = rr[q] * d_up + c0;
                     if (CW == 2) {
                         T2 o2;
-                        o2.x = (T)acc[q][0];
-                        o2.y = (T)acc[q][CW - 1];
-                        *reinterpret_cast<T2 *>(ww + rr[q] * d_up + c0) = o2;
+                        o2.x = fin(acc[q][0], i);
+                        o2.y = fin(acc[q][CW - 1], i + 1);
+                        *reinterpret_cast<T2 *>(ww + i) = o2;
                     } else {
-                        ww[rr[q] * d_up + c0] = (T)acc[q][0];
+                        ww[i] = fin(acc[q][0], i);
                     }
                 }
         }
+    }
+    if (SP) {
+        const double t = block_sum(part, sh);
+        if (threadIdx.x == 0) sp.pa[(int64_t)blockIdx.y * gridDim.x + p] = t;
     }
 }
 
@@ -287,7 +315,8 @@ static size_t inrow_lds_bytes(const HvOp &op, int prec) {
 }
 
 template <typename T>
-static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipStream_t s) {
+static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipStream_t s,
+                          const SubPrev *sp) {
     const int64_t d_up = op.up.d, d_dn = op.dn.d;
     const HopTables &hd_rm = op.hd_rm;
     const size_t lds = inrow_lds_bytes(op, sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V);
@@ -320,20 +349,38 @@ static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipS
     const int64_t total = nslab * nrb;
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
+    const SubPrev none{};
+#define QCM_DACC(RI, CW)                                                                     \
+    do {                                                                                     \
+        if (sp)                                                                              \
+            k_hv_down_acc<T, RI, CW, true><<<g1, 256, 0, s>>>(                               \
+                d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
+                (T *)w, R, nrb, total, per, op.row_order, *sp);                              \
+        else                                                                                 \
+            k_hv_down_acc<T, RI, CW, false><<<g1, 256, 0, s>>>(                              \
+                d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
+                (T *)w, R, nrb, total, per, op.row_order, none);                             \
+    } while (0)
     if (cw == 2 && sizeof(T) == 8)
-        k_hv_down_acc<T, 4, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
-                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
-                                                  per, op.row_order);
+        QCM_DACC(4, 2);
     else if (cw == 2)
-        k_hv_down_acc<T, 2, 2><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
-                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
-                                                  per, op.row_order);
+        QCM_DACC(2, 2);
     else
-        k_hv_down_acc<T, 2, 1><<<g1, 256, 0, s>>>(d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off,
-                                                  hd_rm.coef, (const T *)v, (T *)w, R, nrb, total,
-                                                  per, op.row_order);
+        QCM_DACC(2, 1);
+#undef QCM_DACC
     QCM_LAUNCH_CHECK();
     return QCM_OK;
+}
+
+// Workgroups of the row-mixing pass per vector: the length of the partial
+// <v, w> array a fused Lanczos step writes per chain.
+int64_t split_pa_count(const HvOp &op) {
+    const int64_t d_up = op.up.d, d_dn = op.dn.d;
+    const int R = 16;
+    const int cw = (d_up % 2 == 0) ? 2 : 1;
+    const int64_t nslab = (d_up + 64 * cw - 1) / (64 * cw);
+    const int64_t total = nslab * ((d_dn + R - 1) / R);
+    return 8 * ((total + 7) / 8);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -385,8 +432,14 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
 }
 
 int hv_split_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s) {
-    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s);
-    return split_launch_t<float>(op, v, w, nvec, s);
+    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s, nullptr);
+    return split_launch_t<float>(op, v, w, nvec, s, nullptr);
+}
+
+int hv_split_launch_sub(const HvOp &op, int prec, const void *v, void *w, int nvec,
+                        const SubPrev &sp, hipStream_t s) {
+    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s, &sp);
+    return split_launch_t<float>(op, v, w, nvec, s, &sp);
 }
 
 }  // namespace qcm

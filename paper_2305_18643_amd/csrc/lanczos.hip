@@ -184,9 +184,13 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.fused = !op.split && !op.csr.rowptr && op.up.d < 65536 &&
               fused_lds(op.up.d, e.rows, prec, op.md.nbytes, op.md.u_uniform,
                         2 * op.md.nbond) <= kFusedLds;
-    e.na = e.fused ? e.nblk : e.nchunks;
+    // alpha partials: per fused-product block, per row-mixing workgroup when
+    // the step's first pass rides on the two-pass product, else per chunk
+    e.na = e.fused ? e.nblk : (op.split ? (int32_t)split_pa_count(op) : e.nchunks);
     e.partial = cv.take<double>((size_t)nvec * e.nchunks);
-    e.pa = cv.take<double>((size_t)nvec * (e.nblk > e.nchunks ? e.nblk : e.nchunks));
+    int64_t npa = e.nblk > e.nchunks ? e.nblk : e.nchunks;
+    if (e.na > npa) npa = e.na;
+    e.pa = cv.take<double>((size_t)nvec * npa);
     e.pn = cv.take<double>((size_t)nvec * 3 * e.nchunks);
     e.cs.maxs = maxs;
     e.cs.btol = btol;
@@ -271,6 +275,15 @@ static int step_t(Engine &e, int n, hipStream_t s) {
         const size_t lds = fused_lds(e.op.up.d, e.rows, e.prec, e.op.md.nbytes,
                                      e.op.md.u_uniform, 2 * e.op.md.nbond);
         ks_hv<T, OneSrc><<<(unsigned)e.nvec * e.nblk, 256, lds, s>>>(src);
+    } else if (e.op.split) {
+        // the first pass (w -= beta' vp, partial <v, w>) inside the row-mixing pass
+        SubPrev sp;
+        sp.vp = e.vbuf[e.ivp];
+        sp.beta = e.cs.beta;
+        sp.maxs = e.cs.maxs;
+        sp.n = n;
+        sp.pa = e.pa;
+        QCM_TRY(hv_split_launch_sub(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, sp, s));
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
         ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);

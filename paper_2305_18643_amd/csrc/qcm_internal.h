@@ -159,6 +159,19 @@ int hv_setup(const qcm_model *m, const qcm_basis *b, Carver &cv, HvOp *op, hipSt
 // the two-pass path: whether it applies, its workspace, and its set-up
 bool split_applies(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn);
 int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s);
+// The first pass of a Lanczos step fused into the two-pass product's row-mixing
+// pass: w = H v - beta' vp (beta' = beta[c * maxs + n - 1] of chain c; none
+// when n = 0) and the partial <v, w> of every row-mixing workgroup in
+// pa[c * split_pa_count(op) + workgroup].
+struct SubPrev {
+    const void *vp = nullptr;
+    const double *beta = nullptr;
+    int maxs = 0, n = 0;
+    double *pa = nullptr;
+};
+int64_t split_pa_count(const HvOp &op);
+int hv_split_launch_sub(const HvOp &op, int prec, const void *v, void *w, int nvec,
+                        const SubPrev &sp, hipStream_t s);
 int check_basis(const qcm_basis *b, int L);
 
 // ---------------------------------------------------------------- misc
