@@ -369,6 +369,22 @@ __global__ void __launch_bounds__(256) ks_norm(Src src) {
     }
 }
 
+// sum over k = threadIdx.x, + 256, ... < n of p[k], added in that order; the
+// loads go out eight at a time ahead of the additions
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int64_t n) {
+    double acc = 0.0;
+    int64_t k = threadIdx.x;
+    for (; k + 7 * 256 < n; k += 8 * 256) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = p[k + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += x[u];
+    }
+    for (; k < n; k += 256) acc += p[k];
+    return acc;
+}
+
 // per-chain sums of the partials and the recurrence bookkeeping
 // mode 0: alpha_n; mode 1: reorthogonalisation terms, beta_n, breakdown.
 template <class Src>
@@ -381,8 +397,7 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
     const int n = q.n;
     if (mode == 0) {
         const double *p = q.pa + (int64_t)c * q.na;
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < q.na; k += 256) acc += p[k];
+        double acc = strided_sum(p, q.na);
         const double s = block_sum(acc, sh);
         if (threadIdx.x == 0) {
             cs.alpha[(int64_t)c * cs.maxs + n] = s;
@@ -393,17 +408,11 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         return;
     }
     const double *p = q.pn + (int64_t)c * 3 * q.nchunks;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int k = threadIdx.x; k < q.nchunks; k += 256) a0 += p[k];
-    const double s0 = block_sum(a0, sh);
+    const double s0 = block_sum(strided_sum(p, q.nchunks), sh);
     double s1 = 0.0, s2 = 0.0;
     if (q.reorth) {
-        for (int k = threadIdx.x; k < q.nchunks; k += 256) {
-            a1 += p[q.nchunks + k];
-            a2 += p[2 * q.nchunks + k];
-        }
-        s1 = block_sum(a1, sh);
-        s2 = block_sum(a2, sh);
+        s1 = block_sum(strided_sum(p + q.nchunks, q.nchunks), sh);
+        s2 = block_sum(strided_sum(p + 2 * q.nchunks, q.nchunks), sh);
     }
     if (threadIdx.x != 0) return;
     if (q.reorth) cs.alpha[(int64_t)c * cs.maxs + n] += s1;
