@@ -326,6 +326,110 @@ __global__ void __launch_bounds__(kJacT) kbl_jacobi(double *__restrict__ A, int 
     }
 }
 
+// Lowest eigenvalue of the symmetric R x R matrix A (leading block, row
+// stride lda; overwritten) for the stopping rule: Householder reduction to
+// tridiagonal form (step k reflects the column below the diagonal onto its
+// first entry: A22 <- (I - tau v v^T) A22 (I - tau v v^T), applied as
+// A22 -= v q^T + q v^T with p = tau A22 v, q = p - (tau v.p / 2) v), then a
+// 1025-point Sturm multisection on the tridiagonal, stopped at floating-point
+// resolution.  Backward stable like the Jacobi method, at the cost of R
+// reflections instead of several sweeps of R - 1 rotation rounds.  One
+// workgroup of kJacT threads; info[2] receives the eigenvalue.
+__global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int lda, int R,
+                                                    double *__restrict__ info) {
+    __shared__ double sh[kJacT];
+    __shared__ double v[kBandMaxR], q[kBandMaxR], dg[kBandMaxR], of[kBandMaxR];
+    __shared__ double blo, bhi;
+    __shared__ int first;
+    const int t = threadIdx.x;
+    for (int k = 0; k + 2 < R; ++k) {
+        const int m = R - k - 1;                     // entries below the diagonal
+        const int64_t b = (int64_t)(k + 1) * lda + (k + 1);   // A22 origin
+        double tail = 0.0;
+        for (int i = t; i < m; i += kJacT) {
+            const double x = A[(int64_t)(k + 1 + i) * lda + k];
+            v[i] = x;
+            if (i > 0) tail = fma(x, x, tail);
+        }
+        const double s_tail = jac_sum(tail, sh);     // synchronises: v is complete
+        const double x0 = v[0];
+        if (t == 0) dg[k] = A[(int64_t)k * lda + k];
+        if (!(s_tail > 0.0)) {                       // the column is reduced already
+            if (t == 0) of[k] = x0;
+            __syncthreads();
+            continue;
+        }
+        const double nrm = sqrt(fma(x0, x0, s_tail));
+        const double alpha = x0 > 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;                // no cancellation: opposite signs
+        const double tau = 2.0 / fma(v0, v0, s_tail);
+        if (t == 0) of[k] = alpha;
+        __syncthreads();
+        if (t == 0) v[0] = v0;
+        __syncthreads();
+        // p = tau A22 v, one thread per entry, reading a column of the
+        // symmetric A22 (lanes of a wave stay within one row)
+        double part = 0.0;
+        for (int i = t; i < m; i += kJacT) {
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) acc = fma(A[b + (int64_t)j * lda + i], v[j], acc);
+            q[i] = tau * acc;
+            part = fma(v[i], q[i], part);
+        }
+        const double K = 0.5 * tau * jac_sum(part, sh);
+        for (int i = t; i < m; i += kJacT) q[i] = fma(-K, v[i], q[i]);
+        __syncthreads();
+        for (int64_t e = t; e < (int64_t)m * m; e += kJacT) {
+            const int i = (int)(e / m), j = (int)(e % m);
+            A[b + (int64_t)i * lda + j] -= v[i] * q[j] + q[i] * v[j];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (R >= 2) {
+            dg[R - 2] = A[(int64_t)(R - 2) * lda + (R - 2)];
+            of[R - 2] = A[(int64_t)(R - 1) * lda + (R - 2)];
+        }
+        dg[R - 1] = A[(int64_t)(R - 1) * lda + (R - 1)];
+        double lo = dg[0], hi = dg[0];               // Gershgorin
+        for (int i = 0; i < R; ++i) {
+            const double r = (i > 0 ? fabs(of[i - 1]) : 0.0) + (i < R - 1 ? fabs(of[i]) : 0.0);
+            lo = fmin(lo, dg[i] - r);
+            hi = fmax(hi, dg[i] + r);
+        }
+        const double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
+        blo = lo - pad;
+        bhi = hi + pad;
+    }
+    __syncthreads();
+    for (int i = t; i < R - 1; i += kJacT) of[i] = of[i] * of[i];   // squares from here on
+    __syncthreads();
+    for (int round = 0; round < 12; ++round) {
+        const double lo = blo, hi = bhi;
+        if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)))) break;
+        const double x = lo + (hi - lo) * (double)(t + 1) / (double)(kJacT + 1);
+        // no eigenvalue below x  <=>  every pivot of the LDL^T of T - x is positive
+        double piv = 1.0;
+        bool below = false;
+        for (int i = 0; i < R && !below; ++i) {
+            piv = (dg[i] - x) - (i > 0 ? of[i - 1] / piv : 0.0);
+            if (piv == 0.0) piv = -1e-300;
+            below = piv < 0.0;
+        }
+        if (t == 0) first = kJacT;
+        __syncthreads();
+        if (below) atomicMin(&first, t);
+        __syncthreads();
+        if (t == 0) {
+            const int j = first;
+            blo = j == 0 ? lo : lo + (hi - lo) * (double)j / (double)(kJacT + 1);
+            bhi = j == kJacT ? hi : lo + (hi - lo) * (double)(j + 1) / (double)(kJacT + 1);
+        }
+        __syncthreads();
+    }
+    if (t == 0) info[2] = 0.5 * (blo + bhi);
+}
+
 // Jacobi of the leading R x R block of A; U only when want_u
 static int jacobi_launch(double *A, int lda, int R, double *Uo, int max_sweeps, double *info,
                          bool want_u, hipStream_t s) {
@@ -592,11 +696,12 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
             }
         }
         // the paper's stopping rule, once per block: the lowest eigenvalue of
-        // T_j (Jacobi on a copy) against the one a block earlier
+        // T_j (on a copy) against the one a block earlier
         if (o->etol > 0.0 && j % p == 0) {
             QCM_HIP(hipMemcpy2DAsync(P.Tc, sizeof(double) * ldt, P.Tm, sizeof(double) * ldt,
                                      sizeof(double) * j, j, hipMemcpyDeviceToDevice, s));
-            QCM_TRY(jacobi_launch(P.Tc, ldt, j, P.Uo, o->max_sweeps, P.info, false, s));
+            kbl_lowest<<<1, kJacT, 0, s>>>(P.Tc, ldt, j, P.info);
+            QCM_LAUNCH_CHECK();
             double th = 0.0;
             QCM_HIP(hipMemcpyAsync(&th, P.info + 2, sizeof(double), hipMemcpyDeviceToHost, s));
             QCM_HIP(hipStreamSynchronize(s));
