@@ -248,7 +248,8 @@ typedef struct qcm_band_opts {
     int32_t max_basis;    /* basis vectors per part, 1..1024 */
     int32_t prec;         /* QCM_FP64 or QCM_FP32V vector storage */
     double dtol;          /* deflation: candidate norm <= dtol * max(1, max |T_kk|) */
-    int32_t max_sweeps;   /* Jacobi sweeps for the eigenproblem of T (40) */
+    int32_t max_sweeps;   /* eigenproblem of T: at most max_sweeps * R implicit QR
+                             steps in all (40; about 2 R are needed) */
     int32_t pad1;
     double etol;          /* > 0: stop once the lowest eigenvalue of T has moved by at
                              most etol * max(1, |theta|) over one block of n_orb basis
@@ -256,7 +257,7 @@ typedef struct qcm_band_opts {
                              n_orb); 0: run to max_basis or exhaustion */
 } qcm_band_opts;
 
-/* Fill `o` with defaults: max_basis 400, FP64, dtol 1e-10, 40 sweeps, etol 0
+/* Fill `o` with defaults: max_basis 400, FP64, dtol 1e-10, max_sweeps 40, etol 0
  * (no orbitals). */
 void qcm_band_default_opts(qcm_band_opts *o);
 
@@ -271,7 +272,9 @@ void qcm_band_default_opts(qcm_band_opts *o);
  * (etol > 0) when the lowest eigenvalue of T has converged, the paper's rule
  * against orthogonality leaks.
  * The projected Hamiltonian T of each part is diagonalised on the device
- * (parallel Jacobi), giving the Lehmann representation
+ * (Householder reduction to tridiagonal form, then implicit QR steps with
+ * Wilkinson shifts, both applied to the start-state projections), giving the
+ * Lehmann representation
  *   G_ij(z) = sum_r Qe_ir Qe_jr / (z + E0 - Le_r) + sum_r Qh_ir Qh_jr / (z - E0 + Lh_r),
  * with [Qe Qh][Qe Qh]^T = 1 (the anticommutator).
  *   gs, d_gs, e0: as in qcm_green_cf.
@@ -280,9 +283,10 @@ void qcm_band_default_opts(qcm_band_opts *o);
  *   h_lambda: host [2][max_basis] or NULL, Lambda of each part (first R used).
  *   h_Q     : host [2][n_orb][max_basis] or NULL, Q of each part.
  *   n_z, h_z, d_G: as in qcm_green_cf (device complex128 [n_z][n_orb][n_orb]).
- * Workspace: 3 n_orb + 3 vectors per part plus two max_basis^2 FP64 matrices
- * (three with etol > 0).
- * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
+ * Workspace: 3 n_orb + 3 vectors per part plus one max_basis^2 FP64 matrix
+ * (two with etol > 0).
+ * Errors: QCM_EARG (also when the QR steps run out, which takes a non-finite
+ * T), QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
  */
 int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs, double e0,
                    const qcm_band_opts *o, int32_t *h_R, double *h_lambda, double *h_Q,

@@ -11,8 +11,9 @@
 // and against v_j and the deflated look-back set (coefficients computed).
 // The coefficients form the projected Hamiltonian T (a band of 2p diagonals
 // plus the entries deflation adds) and the projections rho of the start
-// states.  T = U diag(Lambda) U^T by a parallel Jacobi method in one
-// workgroup; Q = rho^T U; G(z) = sum_r Q_mu,r Q_nu,r / (z -+ ...).
+// states.  T = U diag(Lambda) U^T in one workgroup (Householder reduction,
+// then implicit QR steps on the tridiagonal, both applied to rho^T, which
+// ends as Q = rho^T U); G(z) = sum_r Q_mu,r Q_nu,r / (z -+ ...).
 //
 // The host runs the recurrence's bookkeeping (which vectors are candidates,
 // basis vectors or deflated) and reads back one norm per step for the
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(256) kbl_normalise(T *__restrict__ base, int64
     }
 }
 
-constexpr int kJacT = 1024;   // threads of the Jacobi workgroup
+constexpr int kJacT = 1024;   // threads of the eigen-solver workgroup
 
 // sum over the kJacT threads of one workgroup, fixed tree
 __device__ __forceinline__ double jac_sum(double x, double *sh) {
@@ -168,180 +169,23 @@ __device__ __forceinline__ double jac_sum(double x, double *sh) {
     return r;
 }
 
-// Eigen-decomposition of the symmetric R x R matrix A (leading block, row
-// stride lda) by the cyclic parallel Jacobi method: each round applies the
-// rotations of R/2 disjoint index pairs (round-robin tournament ordering),
-// rows first, then columns (and U).  One workgroup of kJacT threads.  With
-// IN_LDS the matrix is staged in LDS (R <= kJacLdsR); otherwise it stays in
-// global memory and each thread loads NU items before it writes any, so that
-// many L2 accesses are in flight.  The column pass walks the pairs along one
-// row at a time, so the lanes of a wave stay within one row.  On return the
-// diagonal of A holds Lambda and, with WANT_U, U (R x R, row stride R) the
-// eigenvectors (columns); info = {sweeps, off-diagonal fraction, lowest
-// eigenvalue}.
-constexpr int kJacLdsR = 128;
-
-template <bool IN_LDS, bool WANT_U, int NU>
-__global__ void __launch_bounds__(kJacT) kbl_jacobi(double *__restrict__ A, int lda, int R,
-                                                    double *__restrict__ Uo, int max_sweeps,
-                                                    double *__restrict__ info) {
-    __shared__ double cs[kBandMaxR / 2 + 1], sn[kBandMaxR / 2 + 1];
-    __shared__ int pa[kBandMaxR / 2 + 1], pb[kBandMaxR / 2 + 1];
-    __shared__ double sh[kJacT];
-    extern __shared__ double sA[];
-    const int tid = threadIdx.x;
-    const int ld = IN_LDS ? R : lda;
-    auto at = [&](int64_t i) -> double & {
-        if constexpr (IN_LDS)
-            return sA[i];
-        else
-            return A[i];
-    };
-    if (IN_LDS)
-        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT)
-            sA[e] = A[(e / R) * lda + e % R];
-    if (WANT_U)
-        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT) Uo[e] = (e / R == e % R) ? 1.0 : 0.0;
-    const int m = (R % 2 == 0) ? R : R + 1;   // with a dummy index R when R is odd
-    const int np = m / 2;
-    const int64_t nitem = (int64_t)np * R;
-    __syncthreads();
-    int sweep = 0;
-    double off = 0.0, tot = 0.0;
-    for (; sweep < max_sweeps; ++sweep) {
-        // convergence: off-diagonal mass against the whole
-        double a0 = 0.0, a1 = 0.0;
-        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT) {
-            const int r = (int)(e / R), c = (int)(e % R);
-            const double v = at((int64_t)r * ld + c);
-            if (r != c) a0 += v * v;
-            a1 += v * v;
-        }
-        off = jac_sum(a0, sh);
-        tot = jac_sum(a1, sh);
-        if (!(off > 1e-30 * tot)) break;
-        for (int rd = 0; rd < m - 1; ++rd) {
-            for (int k = tid; k < np; k += kJacT) {
-                int a, b;
-                if (k == 0) {
-                    a = m - 1;
-                    b = rd;
-                } else {
-                    a = (rd + k) % (m - 1);
-                    b = (rd - k + (m - 1)) % (m - 1);
-                }
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
-                if (q < R) {
-                    const double app = at((int64_t)p * ld + p), aqq = at((int64_t)q * ld + q);
-                    const double apq = at((int64_t)p * ld + q);
-                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * (fabs(app) + fabs(aqq))) {
-                        const double th = (aqq - app) / (2.0 * apq);
-                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                    }
-                }
-                pa[k] = p;
-                pb[k] = q;
-                cs[k] = c;
-                sn[k] = s;
-            }
-            __syncthreads();
-            // rows p, q of A: item e = (pair k, column), consecutive lanes along a row
-            for (int64_t e0 = tid; e0 < nitem; e0 += (int64_t)NU * kJacT) {
-                double xp[NU], xq[NU];
-                int64_t ip[NU], iq[NU];
-                bool ok[NU];
-                int kk[NU];
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int64_t e = e0 + (int64_t)u * kJacT;
-                    const bool in = e < nitem;
-                    const int k = in ? (int)(e / R) : 0, col = in ? (int)(e % R) : 0;
-                    ok[u] = in && pb[k] < R && sn[k] != 0.0;
-                    kk[u] = k;
-                    ip[u] = (int64_t)pa[k] * ld + col;
-                    iq[u] = (int64_t)pb[k] * ld + col;
-                    xp[u] = ok[u] ? at(ip[u]) : 0.0;
-                    xq[u] = ok[u] ? at(iq[u]) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    if (!ok[u]) continue;
-                    const double c = cs[kk[u]], s = sn[kk[u]];
-                    at(ip[u]) = c * xp[u] - s * xq[u];
-                    at(iq[u]) = s * xp[u] + c * xq[u];
-                }
-            }
-            __syncthreads();
-            // columns p, q of A (and U): item e = (row, pair k), consecutive
-            // lanes take the pairs of one row
-            for (int64_t e0 = tid; e0 < nitem; e0 += (int64_t)NU * kJacT) {
-                double xp[NU], xq[NU], up[NU], uq[NU];
-                int64_t ap[NU], aq[NU], bp[NU], bq[NU];
-                bool ok[NU];
-                int kk[NU];
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int64_t e = e0 + (int64_t)u * kJacT;
-                    const bool in = e < nitem;
-                    const int row = in ? (int)(e / np) : 0, k = in ? (int)(e % np) : 0;
-                    ok[u] = in && pb[k] < R && sn[k] != 0.0;
-                    kk[u] = k;
-                    const int p = pa[k], q = pb[k];
-                    ap[u] = (int64_t)row * ld + p;
-                    aq[u] = (int64_t)row * ld + q;
-                    bp[u] = (int64_t)row * R + p;
-                    bq[u] = (int64_t)row * R + q;
-                    xp[u] = ok[u] ? at(ap[u]) : 0.0;
-                    xq[u] = ok[u] ? at(aq[u]) : 0.0;
-                    up[u] = (WANT_U && ok[u]) ? Uo[bp[u]] : 0.0;
-                    uq[u] = (WANT_U && ok[u]) ? Uo[bq[u]] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    if (!ok[u]) continue;
-                    const double c = cs[kk[u]], s = sn[kk[u]];
-                    at(ap[u]) = c * xp[u] - s * xq[u];
-                    at(aq[u]) = s * xp[u] + c * xq[u];
-                    if (WANT_U) {
-                        Uo[bp[u]] = c * up[u] - s * uq[u];
-                        Uo[bq[u]] = s * up[u] + c * uq[u];
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (IN_LDS)
-        for (int64_t e = tid; e < (int64_t)R * R; e += kJacT)
-            A[(e / R) * lda + e % R] = sA[e];
-    if (tid == 0) {
-        double lo = R > 0 ? at(0) : 0.0;
-        for (int r = 1; r < R; ++r) lo = fmin(lo, at((int64_t)r * ld + r));
-        info[0] = sweep;
-        info[1] = tot > 0.0 ? off / tot : 0.0;
-        info[2] = lo;
-    }
+// sum over the 64 lanes of a wave (xor butterfly: every lane gets the same bits)
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
 }
 
-// Lowest eigenvalue of the symmetric R x R matrix A (leading block, row
-// stride lda; overwritten) for the stopping rule: Householder reduction to
-// tridiagonal form (step k reflects the column below the diagonal onto its
-// first entry: A22 <- (I - tau v v^T) A22 (I - tau v v^T), applied as
-// A22 -= v q^T + q v^T with p = tau A22 v, q = p - (tau v.p / 2) v), then a
-// 1025-point Sturm multisection on the tridiagonal, stopped at floating-point
-// resolution.  Backward stable like the Jacobi method, at the cost of R
-// reflections instead of several sweeps of R - 1 rotation rounds.  One
-// workgroup of kJacT threads; info[2] receives the eigenvalue.
-__global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int lda, int R,
-                                                    double *__restrict__ info) {
-    __shared__ double sh[kJacT];
-    __shared__ double v[kBandMaxR], q[kBandMaxR], dg[kBandMaxR], of[kBandMaxR];
-    __shared__ double blo, bhi;
-    __shared__ int first;
-    const int t = threadIdx.x;
+// Householder reduction of the symmetric R x R matrix A (leading block, row
+// stride lda; overwritten) to tridiagonal form, diagonal into dg[0..R-1] and
+// couplings into of[0..R-2] (LDS).  Step k reflects the column below the
+// diagonal onto its first entry: A22 <- (I - tau v v^T) A22 (I - tau v v^T),
+// applied as A22 -= v q^T + q v^T with p = tau A22 v, q = p - (tau v.p / 2) v.
+// The p rows of W (row stride ldw) are reflected too, W <- W (I - tau v v^T),
+// one wave per row, so that W = B^T on entry ends as B^T P with T = P Tri P^T.
+// Called by all kJacT threads; ends synchronised.
+__device__ void house_tridiag(double *__restrict__ A, int lda, int R, double *v, double *q,
+                              double *dg, double *of, double *sh, double *W, int p, int ldw) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int k = 0; k + 2 < R; ++k) {
         const int m = R - k - 1;                     // entries below the diagonal
         const int64_t b = (int64_t)(k + 1) * lda + (k + 1);   // A22 origin
@@ -367,6 +211,13 @@ __global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int 
         __syncthreads();
         if (t == 0) v[0] = v0;
         __syncthreads();
+        for (int mu = wv; mu < p; mu += kJacT / 64) {
+            double *w = W + (int64_t)mu * ldw + (k + 1);
+            double d = 0.0;
+            for (int i = lane; i < m; i += 64) d = fma(w[i], v[i], d);
+            d = tau * wave_sum(d);
+            for (int i = lane; i < m; i += 64) w[i] = fma(-d, v[i], w[i]);
+        }
         // p = tau A22 v, one thread per entry, reading a column of the
         // symmetric A22 (lanes of a wave stay within one row)
         double part = 0.0;
@@ -391,6 +242,24 @@ __global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int 
             of[R - 2] = A[(int64_t)(R - 1) * lda + (R - 2)];
         }
         dg[R - 1] = A[(int64_t)(R - 1) * lda + (R - 1)];
+    }
+    __syncthreads();
+}
+
+// Lowest eigenvalue of the symmetric R x R matrix A (leading block, row
+// stride lda; overwritten) for the stopping rule: Householder reduction to
+// tridiagonal form, then a 1025-point Sturm multisection on the tridiagonal,
+// stopped at floating-point resolution.  One workgroup of kJacT threads;
+// info[2] receives the eigenvalue.
+__global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int lda, int R,
+                                                    double *__restrict__ info) {
+    __shared__ double sh[kJacT];
+    __shared__ double v[kBandMaxR], q[kBandMaxR], dg[kBandMaxR], of[kBandMaxR];
+    __shared__ double blo, bhi;
+    __shared__ int first;
+    const int t = threadIdx.x;
+    house_tridiag(A, lda, R, v, q, dg, of, sh, nullptr, 0, 0);
+    if (t == 0) {
         double lo = dg[0], hi = dg[0];               // Gershgorin
         for (int i = 0; i < R; ++i) {
             const double r = (i > 0 ? fabs(of[i - 1]) : 0.0) + (i < R - 1 ? fabs(of[i]) : 0.0);
@@ -430,36 +299,131 @@ __global__ void __launch_bounds__(kJacT) kbl_lowest(double *__restrict__ A, int 
     if (t == 0) info[2] = 0.5 * (blo + bhi);
 }
 
-// Jacobi of the leading R x R block of A; U only when want_u
-static int jacobi_launch(double *A, int lda, int R, double *Uo, int max_sweeps, double *info,
-                         bool want_u, hipStream_t s) {
-    if (R <= kJacLdsR) {
-        const size_t lds = sizeof(double) * (size_t)R * R;
-        if (want_u)
-            kbl_jacobi<true, true, 4><<<1, kJacT, lds, s>>>(A, lda, R, Uo, max_sweeps, info);
-        else
-            kbl_jacobi<true, false, 4><<<1, kJacT, lds, s>>>(A, lda, R, Uo, max_sweeps, info);
-    } else {
-        if (want_u)
-            kbl_jacobi<false, true, 4><<<1, kJacT, 0, s>>>(A, lda, R, Uo, max_sweeps, info);
-        else
-            kbl_jacobi<false, false, 8><<<1, kJacT, 0, s>>>(A, lda, R, Uo, max_sweeps, info);
+// Lambda and Q = B^T U for the symmetric R x R matrix T = U diag(Lambda) U^T
+// (leading block of A, row stride lda; overwritten) and the R x p matrix B
+// (row stride p).  Householder reduction to tridiagonal form, its reflections
+// applied to W = B^T from the right, then implicit symmetric QR steps with
+// Wilkinson shifts on the tridiagonal (each step a rotation chase from the
+// top of an unreduced block to its bottom; a coupling at most eps times a
+// Gershgorin bound of |T| is set to zero), each rotation applied to the
+// columns of W too.  The QR phase runs in wave 0: every lane follows the same
+// recurrence and lane mu (< p <= 32) carries row mu of W.  W stays in LDS
+// when W_LDS (p R doubles of dynamic LDS), else it is worked on in Q itself.
+// Q is p x R (row stride R).  info[0] = QR steps; info[1] = 1 if max_steps
+// ran out before every coupling vanished (Lambda, Q then unusable).
+constexpr size_t kEighLdsBytes = 96 * 1024;
+
+template <bool W_LDS>
+__global__ void __launch_bounds__(kJacT) kbl_eigh(double *__restrict__ A, int lda, int R,
+                                                  const double *__restrict__ Bm, int p,
+                                                  int max_steps, double *__restrict__ lam,
+                                                  double *__restrict__ Q, double *__restrict__ info) {
+    __shared__ double sh[kJacT];
+    __shared__ double v[kBandMaxR], q[kBandMaxR], dg[kBandMaxR], of[kBandMaxR];
+    extern __shared__ double sW[];
+    double *W = W_LDS ? sW : Q;
+    const int t = threadIdx.x;
+    for (int64_t e = t; e < (int64_t)p * R; e += kJacT) {
+        const int mu = (int)(e / R), c = (int)(e % R);
+        W[e] = Bm[(int64_t)c * p + mu];
     }
-    QCM_LAUNCH_CHECK();
-    return QCM_OK;
+    __syncthreads();
+    house_tridiag(A, lda, R, v, q, dg, of, sh, W, p, R);
+    if (t >= 64) return;
+    const int lane = t;
+    const bool own = lane < p;
+    double *wr = W + (int64_t)(own ? lane : 0) * R;
+    // couplings at most eps times a Gershgorin bound of |T| count as zero
+    double tn = 0.0;
+    for (int r = lane; r < R; r += 64)
+        tn = fmax(tn, fabs(dg[r]) + (r > 0 ? fabs(of[r - 1]) : 0.0) + (r + 1 < R ? fabs(of[r]) : 0.0));
+    for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o));
+    const double thr = 2.220446049250313e-16 * tn;
+    int hi = R - 1, steps = 0, ok = 1;
+    while (hi > 0) {
+        // lo: first index of the unreduced block that ends at hi
+        int lo = 0;
+        for (int top = hi - 1; top >= 0; top -= 64) {
+            const int i = top - lane;
+            bool neg = false;
+            if (i >= 0) neg = !(fabs(of[i]) > thr);
+            const uint64_t mk = __ballot(neg);
+            if (mk) {
+                const int l = __ffsll((unsigned long long)mk) - 1;   // highest such index
+                lo = top - l + 1;
+                if (lane == l) of[i] = 0.0;
+                break;
+            }
+        }
+        if (lo == hi) {
+            --hi;
+            continue;
+        }
+        if (steps >= max_steps) {
+            ok = 0;
+            break;
+        }
+        ++steps;
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 nearer its last entry
+        const double a = dg[hi - 1], bb = of[hi - 1], cN = dg[hi];
+        const double dl = 0.5 * (a - cN);
+        const double h = hypot(dl, bb);
+        const double shift = cN - bb * (bb / (dl + (dl >= 0.0 ? h : -h)));
+        // chase: the rotation in plane (k, k+1) maps rows (k, k+1) to
+        // (c r_k + s r_k+1, -s r_k + c r_k+1) and the columns alike; the first
+        // one follows the shifted first column, the others remove the bulge
+        // at (k+1, k-1) that the previous one left
+        double x = dg[lo] - shift, z = of[lo];
+        double dk = dg[lo], ek = of[lo];
+        double wk = own ? wr[lo] : 0.0;
+        for (int k = lo; k < hi; ++k) {
+            const double dk1 = dg[k + 1];
+            const double ek1 = k + 1 < hi ? of[k + 1] : 0.0;
+            const double wk1 = own ? wr[k + 1] : 0.0;
+            const double r = hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r > 0.0) {
+                const double ir = 1.0 / r;
+                c = x * ir;
+                s = z * ir;
+            }
+            if (k > lo) of[k - 1] = r;
+            const double cs = c * s, c2 = c * c, s2 = s * s, tb = 2.0 * cs * ek;
+            dg[k] = c2 * dk + s2 * dk1 + tb;
+            const double ne = cs * (dk1 - dk) + (c2 - s2) * ek;
+            dk = s2 * dk + c2 * dk1 - tb;
+            if (own) wr[k] = c * wk + s * wk1;
+            wk = c * wk1 - s * wk;
+            if (k + 1 < hi) {
+                x = ne;
+                z = s * ek1;
+                ek = c * ek1;
+            } else {
+                of[k] = ne;
+            }
+        }
+        dg[hi] = dk;
+        if (own) wr[hi] = wk;
+    }
+    for (int r = lane; r < R; r += 64) lam[r] = dg[r];
+    if (W_LDS)
+        for (int64_t e = lane; e < (int64_t)p * R; e += 64) Q[e] = sW[e];
+    if (lane == 0) {
+        info[0] = steps;
+        info[1] = ok ? 0.0 : 1.0;
+    }
 }
 
-// lam[r] = A[r][r]; Q[mu][r] = sum_k rho[k][mu] U[k][r]
-__global__ void kbl_lehmann(const double *__restrict__ A, int lda, const double *__restrict__ Uo,
-                            int R, const double *__restrict__ rho, int p,
-                            double *__restrict__ lam, double *__restrict__ Q) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < R) lam[e] = A[e * lda + e];
-    if (e >= (int64_t)p * R) return;
-    const int mu = (int)(e / R), r = (int)(e % R);
-    double s = 0.0;
-    for (int k = 0; k < R; ++k) s = fma(rho[(int64_t)k * p + mu], Uo[(int64_t)k * R + r], s);
-    Q[(int64_t)mu * R + r] = s;
+// Lambda and Q of one part (T in A, the start-state projections in Bm)
+static int eigh_launch(double *A, int lda, int R, const double *Bm, int p, int max_steps,
+                       double *lam, double *Q, double *info, hipStream_t s) {
+    const size_t wl = sizeof(double) * (size_t)p * R;
+    if (wl <= kEighLdsBytes)
+        kbl_eigh<true><<<1, kJacT, wl, s>>>(A, lda, R, Bm, p, max_steps, lam, Q, info);
+    else
+        kbl_eigh<false><<<1, kJacT, 0, s>>>(A, lda, R, Bm, p, max_steps, lam, Q, info);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
 }
 
 // G[z][mu][nu] = sum_r Qe_mu,r Qe_nu,r / (z + E0 - le_r) + Qh_mu,r Qh_nu,r / (z - E0 + lh_r)
@@ -499,7 +463,7 @@ struct BandPart {
     int nchunks = 1;
     char *pool = nullptr;        // slots of dim elements
     int nslot = 0;
-    double *Tm = nullptr, *rho = nullptr, *Uo = nullptr, *lam = nullptr, *Q = nullptr;
+    double *Tm = nullptr, *rho = nullptr, *lam = nullptr, *Q = nullptr;
     double *Tc = nullptr;        // copy of T for the convergence test (etol > 0)
     double *partial = nullptr, *res = nullptr, *scal = nullptr, *info = nullptr;
     int R = 0;
@@ -542,7 +506,6 @@ static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_o
         P.pool = cv.take<char>(vs * (size_t)P.dim * P.nslot);
         P.Tm = cv.take<double>((size_t)Rm * Rm);
         P.rho = cv.take<double>((size_t)Rm * p);
-        P.Uo = cv.take<double>((size_t)Rm * Rm);
         if (o->etol > 0.0) P.Tc = cv.take<double>((size_t)Rm * Rm);
         P.lam = cv.take<double>(Rm);
         P.Q = cv.take<double>((size_t)p * Rm);
@@ -785,11 +748,8 @@ extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const dou
             QCM_TRY(band_run<float>(o, P, d_gs, gs->d_up, upg, part, B.ops, s));
         Rs[part] = P.R;
         if (P.R > 0) {
-            QCM_TRY(jacobi_launch(P.Tm, o->max_basis, P.R, P.Uo, o->max_sweeps, P.info, true, s));
-            const int64_t nth = std::max<int64_t>(P.R, (int64_t)p * P.R);
-            kbl_lehmann<<<ceil_div(nth, 256), 256, 0, s>>>(P.Tm, o->max_basis, P.Uo, P.R, P.rho, p,
-                                                          P.lam, P.Q);
-            QCM_LAUNCH_CHECK();
+            const int max_steps = (int)std::min<int64_t>((int64_t)o->max_sweeps * P.R, 1 << 30);
+            QCM_TRY(eigh_launch(P.Tm, o->max_basis, P.R, P.rho, p, max_steps, P.lam, P.Q, P.info, s));
         }
     }
     if (n_z > 0) {
@@ -816,6 +776,15 @@ extern "C" int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const dou
                                        P.Q + (size_t)mu * R, sizeof(double) * R,
                                        hipMemcpyDeviceToHost, s));
     }
+    double einfo[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int part = 0; part < 2; ++part)
+        if (Rs[part] > 0)
+            QCM_HIP(hipMemcpyAsync(einfo[part], B.part[part].info, sizeof einfo[part],
+                                   hipMemcpyDeviceToHost, s));
     QCM_HIP(hipStreamSynchronize(s));
+    for (int part = 0; part < 2; ++part)
+        if (einfo[part][1] != 0.0)
+            return fail(QCM_EARG, "qcm_green_band: the eigenproblem of T (part %d) did not converge "
+                        "in %d QR steps (non-finite input?)", part, (int)einfo[part][0]);
     return QCM_OK;
 }
