@@ -400,6 +400,41 @@ def test_band_lanczos_edge_sectors(q, m, orbs):
     assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
 
 
+def test_band_lanczos_many_orbitals(q):
+    """16 start states and up to 800 basis vectors per part, so that the
+    start-state projections (p R doubles) exceed the 96 KB the eigen-solver
+    of T keeps in LDS and its global-memory path runs: for each part the
+    moments Q Lambda^k Q^T against B^T H^k B formed directly from the
+    oracle's start states and products (k <= 3, relative 1e-9), and
+    Q Q^T = 1 over both parts (1e-12)."""
+    torch = _torch()
+    m = synth.random_model(507, 16, 2, 1)
+    orbs = list(range(16))
+    print(f"band many orbitals {m.name} p={len(orbs)}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=800)
+    print(f"  R {list(g['R'])}")
+    assert max(g["R"]) * len(orbs) * 8 > 96 * 1024
+    worst = 0.0
+    for part in range(2):
+        nup2 = m.nup + 1 if part == 0 else m.nup - 1
+        B = np.stack([oracle.apply_op(m.L, m.nup, m.ndn, ro["psi"], part, mu) for mu in orbs],
+                     axis=1)
+        X = B.copy()
+        for k in range(4):
+            Mo = B.T @ X
+            Mg = _moments(g["lam"][part], g["Q"][part], k)
+            worst = max(worst, np.abs(Mg - Mo).max() / max(1.0, np.abs(Mo).max()))
+            X = np.stack([oracle.hv(m.t, m.U, nup2, m.ndn, X[:, i]) for i in range(len(orbs))],
+                         axis=1)
+    print(f"  moments 0..3: max relative difference {worst:.2e}")
+    assert worst <= 1e-9
+    Q = np.concatenate(g["Q"], axis=1)
+    assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
+
+
 def test_band_lanczos_fp32v_errors_reported(q):
     """FP32 vectors (FP64 sums and coefficients): against the FP64 run from
     the same start states, the lowest Ritz value of each part and the
