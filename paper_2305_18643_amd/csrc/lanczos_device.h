@@ -33,16 +33,28 @@ __device__ __forceinline__ void st(T *p, double x) {
     *p = (T)x;
 }
 
-// number of eigenvalues of T_M below x (Sturm sequence of the LDL^T pivots);
-// b2[i] = b[i]^2
+// number of eigenvalues of T_M below x: the sign changes of the Sturm
+// sequence p_i = (a_i - x) p_{i-1} - b_{i-1}^2 p_{i-2} (p_{-1} = 1, p_{-2} = 0),
+// i.e. the negative pivots q_i = p_i / p_{i-1} of the LDL^T of T_M - x, counted
+// without a division.  The pair (p_i, p_{i-1}) is rescaled by a power of two
+// whenever p_i leaves [2^-256, 2^256] (exact), and a vanishing p_i becomes
+// -1e-300 p_{i-1} (a pivot of -1e-300).  b2[i] = b[i]^2.
 __device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b2,
                            double x) {
     int cnt = 0;
-    double q = 1.0;
+    double pm = 1.0, pmm = 0.0;
     for (int i = 0; i < M; ++i) {
-        q = (a[i] - x) - (i > 0 ? b2[i - 1] / q : 0.0);
-        if (q == 0.0) q = -1e-300;
-        cnt += q < 0.0;
+        double p = (a[i] - x) * pm;
+        if (i > 0) p = fma(-b2[i - 1], pmm, p);
+        if (p == 0.0) p = -1e-300 * pm;
+        cnt += (p < 0.0) != (pm < 0.0);
+        pmm = pm;
+        pm = p;
+        const int e = ilogb(p);
+        if (e > 256 || e < -256) {
+            pm = ldexp(pm, -e);
+            pmm = ldexp(pmm, -e);
+        }
     }
     return cnt;
 }
@@ -92,50 +104,60 @@ __device__ inline double tridiag_kth(int M, const double *a, const double *b, co
     return r;
 }
 
-// Eigenvector for theta by inverse iteration; Gaussian elimination with
-// row pivoting on the tridiagonal (T - theta).  One thread.
+// Eigenvector for theta by inverse iteration: T - theta factored once by
+// Gaussian elimination with row pivoting on the tridiagonal (multipliers in
+// dl, swaps flagged in piv, reciprocal pivots in d, superdiagonals du, du2),
+// then three solves in place on x, each normalised.  One thread.
 __device__ inline void tridiag_vector(int M, const double *a, const double *b, double theta, double *x,
-                               double *d, double *du, double *du2, double *dl, double *y) {
+                               double *d, double *du, double *du2, double *dl, double *piv) {
     double scale = 1.0;
     for (int i = 0; i < M; ++i) scale = fmax(scale, fabs(a[i]));
     const double tiny = 1e-15 * scale;
-    for (int i = 0; i < M; ++i) x[i] = 1.0;
-    for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i < M; ++i) {
-            d[i] = a[i] - theta;
-            du[i] = i < M - 1 ? b[i] : 0.0;
-            dl[i] = i < M - 1 ? b[i] : 0.0;
-            du2[i] = 0.0;
-            y[i] = x[i];
-        }
-        for (int i = 0; i < M - 1; ++i) {
-            if (fabs(dl[i]) > fabs(d[i])) {
-                double t0 = d[i];
-                d[i] = dl[i];
-                dl[i] = t0;
-                double t1 = du[i];
-                du[i] = d[i + 1];
-                d[i + 1] = t1;
-                if (i < M - 2) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = 0.0;
-                }
-                double ty = y[i];
-                y[i] = y[i + 1];
-                y[i + 1] = ty;
+    for (int i = 0; i < M; ++i) {
+        d[i] = a[i] - theta;
+        du[i] = i < M - 1 ? b[i] : 0.0;
+        dl[i] = i < M - 1 ? b[i] : 0.0;
+        du2[i] = 0.0;
+        piv[i] = 0.0;
+        x[i] = 1.0;
+    }
+    for (int i = 0; i < M - 1; ++i) {
+        if (fabs(dl[i]) > fabs(d[i])) {
+            double t0 = d[i];
+            d[i] = dl[i];
+            dl[i] = t0;
+            double t1 = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = t1;
+            if (i < M - 2) {
+                du2[i] = du[i + 1];
+                du[i + 1] = 0.0;
             }
-            if (d[i] == 0.0) d[i] = tiny;
-            double m = dl[i] / d[i];
-            d[i + 1] -= m * du[i];
-            if (i < M - 2) du[i + 1] -= m * du2[i];
-            y[i + 1] -= m * y[i];
+            piv[i] = 1.0;
         }
-        if (d[M - 1] == 0.0) d[M - 1] = tiny;
+        if (d[i] == 0.0) d[i] = tiny;
+        d[i] = 1.0 / d[i];
+        const double m = dl[i] * d[i];
+        dl[i] = m;
+        d[i + 1] -= m * du[i];
+        if (i < M - 2) du[i + 1] -= m * du2[i];
+    }
+    if (d[M - 1] == 0.0) d[M - 1] = tiny;
+    d[M - 1] = 1.0 / d[M - 1];
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i < M - 1; ++i) {
+            if (piv[i] != 0.0) {
+                const double ty = x[i];
+                x[i] = x[i + 1];
+                x[i + 1] = ty;
+            }
+            x[i + 1] -= dl[i] * x[i];
+        }
         for (int i = M - 1; i >= 0; --i) {
-            double s = y[i];
+            double s = x[i];
             if (i + 1 < M) s -= du[i] * x[i + 1];
             if (i + 2 < M) s -= du2[i] * x[i + 2];
-            x[i] = s / d[i];
+            x[i] = s * d[i];
         }
         double nr = 0.0;
         for (int i = 0; i < M; ++i) nr += x[i] * x[i];
