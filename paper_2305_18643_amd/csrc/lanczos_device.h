@@ -41,20 +41,19 @@ __device__ __forceinline__ void st(T *p, double x) {
 // -1e-300 p_{i-1} (a pivot of -1e-300).  b2[i] = b[i]^2.
 __device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b2,
                            double x) {
+    // branch-free body, so that the loads of later steps can go out early
     int cnt = 0;
     double pm = 1.0, pmm = 0.0;
+#pragma unroll 4
     for (int i = 0; i < M; ++i) {
-        double p = (a[i] - x) * pm;
-        if (i > 0) p = fma(-b2[i - 1], pmm, p);
-        if (p == 0.0) p = -1e-300 * pm;
+        const double bi = i > 0 ? b2[i - 1] : 0.0;
+        double p = fma(-bi, pmm, (a[i] - x) * pm);
+        p = p == 0.0 ? -1e-300 * pm : p;
         cnt += (p < 0.0) != (pm < 0.0);
-        pmm = pm;
-        pm = p;
         const int e = ilogb(p);
-        if (e > 256 || e < -256) {
-            pm = ldexp(pm, -e);
-            pmm = ldexp(pmm, -e);
-        }
+        const int k = (e > 256 || e < -256) ? -e : 0;
+        pmm = ldexp(pm, k);
+        pm = ldexp(p, k);
     }
     return cnt;
 }
@@ -108,56 +107,69 @@ __device__ inline double tridiag_kth(int M, const double *a, const double *b, co
 // Gaussian elimination with row pivoting on the tridiagonal (multipliers in
 // dl, swaps flagged in piv, reciprocal pivots in d, superdiagonals du, du2),
 // then three solves in place on x, each normalised.  One thread.
-__device__ inline void tridiag_vector(int M, const double *a, const double *b, double theta, double *x,
-                               double *d, double *du, double *du2, double *dl, double *piv) {
+__device__ inline void tridiag_vector(int M, const double *__restrict__ a, const double *__restrict__ b,
+                                      double theta, double *__restrict__ x, double *__restrict__ d,
+                                      double *__restrict__ du, double *__restrict__ du2,
+                                      double *__restrict__ dl, double *__restrict__ piv) {
     double scale = 1.0;
     for (int i = 0; i < M; ++i) scale = fmax(scale, fabs(a[i]));
     const double tiny = 1e-15 * scale;
-    for (int i = 0; i < M; ++i) {
-        d[i] = a[i] - theta;
-        du[i] = i < M - 1 ? b[i] : 0.0;
-        dl[i] = i < M - 1 ? b[i] : 0.0;
-        du2[i] = 0.0;
-        piv[i] = 0.0;
-        x[i] = 1.0;
-    }
+    // factorisation, the current row (di, dui) and the next one carried in
+    // registers: row i is [di, dui, 0], row i+1 is [b_i, dn, dun]
+    double di = a[0] - theta, dui = M > 1 ? b[0] : 0.0;
     for (int i = 0; i < M - 1; ++i) {
-        if (fabs(dl[i]) > fabs(d[i])) {
-            double t0 = d[i];
-            d[i] = dl[i];
-            dl[i] = t0;
-            double t1 = du[i];
-            du[i] = d[i + 1];
-            d[i + 1] = t1;
-            if (i < M - 2) {
-                du2[i] = du[i + 1];
-                du[i + 1] = 0.0;
-            }
-            piv[i] = 1.0;
+        double dli = b[i];
+        double dn = a[i + 1] - theta;
+        double dun = i < M - 2 ? b[i + 1] : 0.0;
+        double du2i = 0.0;
+        const bool sw = fabs(dli) > fabs(di);
+        if (sw) {
+            const double t0 = di;
+            di = dli;
+            dli = t0;
+            const double t1 = dui;
+            dui = dn;
+            dn = t1;
+            du2i = dun;
+            dun = 0.0;
         }
-        if (d[i] == 0.0) d[i] = tiny;
-        d[i] = 1.0 / d[i];
-        const double m = dl[i] * d[i];
+        if (di == 0.0) di = tiny;
+        const double inv = 1.0 / di;
+        const double m = dli * inv;
+        d[i] = inv;
+        du[i] = dui;
+        du2[i] = du2i;
         dl[i] = m;
-        d[i + 1] -= m * du[i];
-        if (i < M - 2) du[i + 1] -= m * du2[i];
+        piv[i] = sw ? 1.0 : 0.0;
+        dn -= m * dui;
+        dun -= m * du2i;
+        di = dn;
+        dui = dun;
     }
-    if (d[M - 1] == 0.0) d[M - 1] = tiny;
-    d[M - 1] = 1.0 / d[M - 1];
+    if (di == 0.0) di = tiny;
+    d[M - 1] = 1.0 / di;
+    for (int i = 0; i < M; ++i) x[i] = 1.0;
     for (int it = 0; it < 3; ++it) {
+        // forward: the row swaps and multipliers, x_i carried
+        double cur = x[0];
         for (int i = 0; i < M - 1; ++i) {
-            if (piv[i] != 0.0) {
-                const double ty = x[i];
-                x[i] = x[i + 1];
-                x[i + 1] = ty;
-            }
-            x[i + 1] -= dl[i] * x[i];
+            const double nxt = x[i + 1];
+            const bool sw = piv[i] != 0.0;
+            const double lo = sw ? nxt : cur, hi = sw ? cur : nxt;
+            x[i] = lo;
+            cur = hi - dl[i] * lo;
         }
+        x[M - 1] = cur;
+        // back substitution, x_{i+1} and x_{i+2} carried
+        double x1 = 0.0, x2 = 0.0;
         for (int i = M - 1; i >= 0; --i) {
             double s = x[i];
-            if (i + 1 < M) s -= du[i] * x[i + 1];
-            if (i + 2 < M) s -= du2[i] * x[i + 2];
-            x[i] = s * d[i];
+            if (i + 1 < M) s -= du[i] * x1;
+            if (i + 2 < M) s -= du2[i] * x2;
+            const double xi = s * d[i];
+            x[i] = xi;
+            x2 = x1;
+            x1 = xi;
         }
         double nr = 0.0;
         for (int i = 0; i < M; ++i) nr += x[i] * x[i];
