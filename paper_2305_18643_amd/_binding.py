@@ -463,7 +463,8 @@ def green_band(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_basis=
     """Band Lanczos up-spin G_ij(z) for i, j in orbs; returns G (device
     complex128 [n_z, n, n]), R (numpy [2]), lam (list of two numpy arrays) and
     Q (list of two numpy [n, R] arrays), electron part first.  etol > 0 stops
-    each part once its lowest Ritz value has converged (the paper's rule)."""
+    each part once its lowest Ritz value has converged (the paper's rule);
+    max_sweeps caps the eigen-solver of T at max_sweeps * R QR steps."""
     torch = _torch()
     lib = load_library()
     m = as_model(model)
