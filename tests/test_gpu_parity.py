@@ -435,6 +435,51 @@ def test_band_lanczos_many_orbitals(q):
     assert np.abs(Q @ Q.T - np.eye(len(orbs))).max() <= 1e-12
 
 
+@pytest.mark.parametrize("R", [1, 2, 3, 7])
+def test_band_lanczos_one_orbital_short(q, R):
+    """One start state and 1, 2, 3 or 7 basis vectors per part: T of size 1
+    (no reduction, no QR step), 2 (QR steps only) and larger, against the
+    oracle's run from the same start state: R, Lambda and G to 1e-10."""
+    from oracle import band
+    torch = _torch()
+    m = synth.random_model(508, 6, 3, 3)
+    orbs = [2]
+    print(f"band one orbital R={R}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=R)
+    Go, parts = band.green_band(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, ro["e0"], Z64,
+                                max_basis=R)
+    err = np.abs(g["G"].cpu().numpy() - Go).max()
+    print(f"  R {list(g['R'])}, max |dG| {err:.2e}")
+    assert err <= 1e-10
+    for k in range(2):
+        assert g["R"][k] == parts[k][0].shape[0] == R
+        assert np.abs(np.sort(g["lam"][k]) - np.sort(parts[k][0])).max() <= 1e-10
+
+
+def test_band_lanczos_one_orbital_stopping_rule(q):
+    """One start state with the paper's stopping rule (tested after every
+    basis vector, from T of size 1 on): the same R per part as the oracle and
+    the same lowest Ritz value (relative 1e-10)."""
+    from oracle import band
+    torch = _torch()
+    m = synth.random_model(508, 6, 3, 3)
+    orbs = [2]
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    g = q.green_band(m, b, psi, ro["e0"], orbs, Z64, max_basis=200, etol=1e-10)
+    _, parts = band.green_band(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, ro["e0"], Z64,
+                               max_basis=200, etol=1e-10)
+    print(f"band one orbital stop: R {list(g['R'])} (oracle {[x[0].shape[0] for x in parts]})")
+    for k in range(2):
+        assert g["R"][k] == parts[k][0].shape[0]
+        lg, lo = g["lam"][k].min(), parts[k][0].min()
+        assert abs(lg - lo) <= 1e-10 * max(1.0, abs(lo))
+
+
 def test_band_lanczos_fp32v_errors_reported(q):
     """FP32 vectors (FP64 sums and coefficients): against the FP64 run from
     the same start states, the lowest Ritz value of each part and the
