@@ -130,25 +130,79 @@ __global__ void __launch_bounds__(256) kbl_sub_band(T *__restrict__ base, int64_
     }
 }
 
-// x *= 1/nrm, and the normalisation coefficient into T or rho
-template <typename T>
-__global__ void __launch_bounds__(256) kbl_normalise(T *__restrict__ base, int64_t xo, int64_t dim,
-                                                     double nrm, int mode, int i, int k,
-                                                     double *__restrict__ Tm, int ldt,
-                                                     double *__restrict__ rho, int p) {
-    T *x = base + xo;
-    const double s = 1.0 / nrm;
-    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
-    for (int q = threadIdx.x; q < kChunk; q += 256) {
-        const int64_t e = b0 + q;
-        if (e < dim) x[e] = (T)(ldd(x + e) * s);
+// The coefficients of a new basis vector from the dots of its candidate x
+// (res[0] = <x, x>, res[q] = <x, y_q>): c_q = res[q] / nrm for the n other
+// candidates (into c, and into T or rho as `put` says), and nrm itself (mode
+// 0: T[i][k] = T[k][i]; mode 1: rho[i][k]).
+__global__ void kbl_coef(const double *__restrict__ res, int n, double nrm, Put put, int mode,
+                         int i, int k, double *__restrict__ Tm, int ldt, double *__restrict__ rho,
+                         int p, double *__restrict__ c) {
+    const int t = threadIdx.x;
+    if (t < n) {
+        const double v = res[t + 1] / nrm;
+        c[t] = v;
+        if (put.mode[t] == 0) {
+            Tm[(int64_t)put.i[t] * ldt + put.k[t]] = v;
+            Tm[(int64_t)put.k[t] * ldt + put.i[t]] = v;
+        } else {
+            rho[(int64_t)put.i[t] * p + put.k[t]] = v;
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (t == 0) {
         if (mode == 0) {
             Tm[(int64_t)i * ldt + k] = nrm;
             Tm[(int64_t)k * ldt + i] = nrm;
         } else {
             rho[(int64_t)i * p + k] = nrm;
+        }
+    }
+}
+
+// The new basis vector and the other candidates in one pass: v = x / nrm in
+// place (inv = 1 / nrm), then y_q -= c_q v for each other candidate, every
+// value rounded once to the storage type.  It also leaves the partial sums
+// of the next step's dots, from the stored values, in kbl_dots's layout and
+// order: <y_0, y_0> in row 0 and <y_0, y_q> in row q (ys lists the other
+// candidates in order, y_0 the next one to become a basis vector).
+template <typename T>
+__global__ void __launch_bounds__(256) kbl_orth(T *__restrict__ base, int64_t xo, VecList ys,
+                                                int64_t dim, int nchunks, double inv,
+                                                const double *__restrict__ c,
+                                                double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int n = ys.n;
+    T *x = base + xo;
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+    double acc[kBandMaxP];
+#pragma unroll
+    for (int q = 0; q < kBandMaxP; ++q) acc[q] = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t e = b0 + k;
+        if (e >= dim) break;
+        const T vt = (T)(ldd(x + e) * inv);
+        x[e] = vt;
+        if (n == 0) continue;
+        const double v = (double)vt;
+        T *y0 = base + ys.off[0];
+        const T a0 = (T)fma(-c[0], v, ldd(y0 + e));
+        y0[e] = a0;
+        const double a = (double)a0;
+        acc[0] = fma(a, a, acc[0]);
+#pragma unroll
+        for (int q = 1; q < kBandMaxP; ++q) {
+            if (q < n) {
+                T *yq = base + ys.off[q];
+                const T bt = (T)fma(-c[q], v, ldd(yq + e));
+                yq[e] = bt;
+                acc[q] = fma(a, (double)bt, acc[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kBandMaxP; ++q) {
+        if (q < n) {
+            const double t = block_sum(acc[q], sh);
+            if (threadIdx.x == 0) partial[(int64_t)q * nchunks + blockIdx.x] = t;
         }
     }
 }
@@ -466,6 +520,8 @@ struct BandPart {
     double *Tm = nullptr, *rho = nullptr, *lam = nullptr, *Q = nullptr;
     double *Tc = nullptr;        // copy of T for the convergence test (etol > 0)
     double *partial = nullptr, *res = nullptr, *scal = nullptr, *info = nullptr;
+    double *ahead = nullptr;     // partial dots of the next candidate, [kBandMaxP + 1][nchunks]
+    double *cq = nullptr;        // coefficients c_q of the candidates against a new basis vector
     int R = 0;
 };
 
@@ -510,6 +566,8 @@ static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_o
         P.lam = cv.take<double>(Rm);
         P.Q = cv.take<double>((size_t)p * Rm);
         P.partial = cv.take<double>((size_t)(kBandMaxP + 1) * P.nchunks);
+        P.ahead = cv.take<double>((size_t)(kBandMaxP + 1) * P.nchunks);
+        P.cq = cv.take<double>(kBandMaxP + 1);
         P.res = cv.take<double>(kBandMaxP + 1);
         P.scal = cv.take<double>(8);
         P.info = cv.take<double>(8);
@@ -542,22 +600,29 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
     int pc = p;
     double scale = 1.0;
     int j = 0;
-    Put none{};
-    none.n = 1;
-    none.mode[0] = 2;
     double host[2];
+    bool ahead = false;
     bool have_prev = false;
     double theta_prev = 0.0;
     while (j < Rm) {
         ++j;
         double nrm = 0.0;
         for (;;) {
-            // (1) norm of the next candidate, read back for the deflation test
-            VecList one{};
-            one.n = 1;
-            one.off[0] = off(cand[j]);
-            kbl_dots<T><<<dim3(nch, 1), 256, 0, s>>>(base, off(cand[j]), one, dim, nch, P.partial);
-            kbl_finish<<<1, 256, 0, s>>>(P.partial, nch, none, P.res, P.Tm, ldt, P.rho, p, P.scal);
+            // (1) the next candidate x = cand[j]: <x, x> (read back for the
+            // deflation test) and <x, y_q> for the other candidates y_q =
+            // cand[j + q], in rows 0..pc-1 of P.ahead.  The previous step's
+            // passes left them there unless a deflation changed the list.
+            if (!ahead) {
+                VecList ys{};
+                ys.n = pc;
+                for (int q = 0; q < pc; ++q) ys.off[q] = off(cand[j + q]);
+                kbl_dots<T><<<dim3(nch, pc), 256, 0, s>>>(base, off(cand[j]), ys, dim, nch,
+                                                          P.ahead);
+            }
+            Put raw{};
+            raw.n = pc;
+            for (int q = 0; q < pc; ++q) raw.mode[q] = 2;
+            kbl_finish<<<pc, 256, 0, s>>>(P.ahead, nch, raw, P.res, P.Tm, ldt, P.rho, p, P.scal);
             QCM_LAUNCH_CHECK();
             QCM_HIP(hipMemcpyAsync(host, P.res, sizeof(double), hipMemcpyDeviceToHost, s));
             QCM_HIP(hipMemcpyAsync(host + 1, P.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -565,6 +630,7 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
             scale = std::max(1.0, host[1]);
             nrm = sqrt(host[0] > 0.0 ? host[0] : 0.0);
             if (nrm > o->dtol * scale) break;
+            ahead = false;
             if (j - pc > 0) I.insert(j - pc);
             freeslots.push_back(cand[j]);
             --pc;
@@ -575,18 +641,13 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
             for (int k = j; k < j + pc; ++k) cand[k] = cand[k + 1];
             cand.erase(j + pc);
         }
-        // (2) normalise: v_j
+        // (2, 3) v_j = x / nrm and the other candidates against it,
+        // y_q -= (<x, y_q> / nrm) v_j, in one pass that also sums the dots of
+        // the next candidate with the others
         const int sj = cand[j];
         cand.erase(j);
         vslot[j] = sj;
-        if (j - pc > 0)
-            kbl_normalise<T><<<g1, 256, 0, s>>>(base, off(sj), dim, nrm, 0, j - 1, j - pc - 1,
-                                                P.Tm, ldt, P.rho, p);
-        else
-            kbl_normalise<T><<<g1, 256, 0, s>>>(base, off(sj), dim, nrm, 1, j - 1, j - pc + p - 1,
-                                                P.Tm, ldt, P.rho, p);
-        // (3) the other candidates against v_j
-        if (pc > 1) {
+        {
             VecList ys{};
             Put put{};
             ys.n = put.n = pc - 1;
@@ -603,10 +664,13 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
                     put.k[q] = k - pc + p - 1;
                 }
             }
-            kbl_dots<T><<<dim3(nch, pc - 1), 256, 0, s>>>(base, off(sj), ys, dim, nch, P.partial);
-            kbl_finish<<<pc - 1, 256, 0, s>>>(P.partial, nch, put, P.res, P.Tm, ldt, P.rho, p,
-                                              P.scal);
-            kbl_axpys<T><<<dim3(nch, pc - 1), 256, 0, s>>>(base, off(sj), ys, dim, P.res);
+            if (j - pc > 0)
+                kbl_coef<<<1, 64, 0, s>>>(P.res, pc - 1, nrm, put, 0, j - 1, j - pc - 1, P.Tm, ldt,
+                                          P.rho, p, P.cq);
+            else
+                kbl_coef<<<1, 64, 0, s>>>(P.res, pc - 1, nrm, put, 1, j - 1, j - pc + p - 1, P.Tm,
+                                          ldt, P.rho, p, P.cq);
+            kbl_orth<T><<<g1, 256, 0, s>>>(base, off(sj), ys, dim, nch, 1.0 / nrm, P.cq, P.ahead);
             QCM_LAUNCH_CHECK();
         }
         // (4) the new candidate w = H v_j
@@ -649,6 +713,18 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
             QCM_LAUNCH_CHECK();
         }
         cand[j + pc] = sw;
+        // the next candidate's dot with w (row pc - 1), or its norm when w is
+        // the next candidate itself
+        {
+            VecList one{};
+            one.n = 1;
+            one.off[0] = off(sw);
+            const int x_next = pc > 1 ? cand[j + 1] : sw;
+            kbl_dots<T><<<dim3(nch, 1), 256, 0, s>>>(base, off(x_next), one, dim, nch,
+                                                     P.ahead + (size_t)(pc - 1) * nch);
+            QCM_LAUNCH_CHECK();
+            ahead = true;
+        }
         // basis vectors older than the band and outside the look-back set are done
         for (auto it = vslot.begin(); it != vslot.end();) {
             if (it->first < j - p && !I.count(it->first)) {
