@@ -576,6 +576,22 @@ static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_o
     return QCM_OK;
 }
 
+// The stream, events and pinned result of the stopping tests, which run
+// beside the recurrence; released (after the side stream drains) on every
+// way out of band_run.
+struct SideTest {
+    hipStream_t s = nullptr;
+    hipEvent_t copied = nullptr, done = nullptr;
+    double *h_theta = nullptr;
+    ~SideTest() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (done) (void)hipEventDestroy(done);
+        if (copied) (void)hipEventDestroy(copied);
+        if (s) (void)hipStreamDestroy(s);
+        if (h_theta) (void)hipHostFree(h_theta);
+    }
+};
+
 template <typename T>
 static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int64_t d_src_up,
                     const SpinTables &src_up, int kind, const int32_t *ops, hipStream_t s) {
@@ -604,7 +620,54 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
     bool ahead = false;
     bool have_prev = false;
     double theta_prev = 0.0;
+    // The paper's stopping rule, once per block: the lowest eigenvalue of T_j
+    // (on a copy) against the one a block earlier.  Each test runs on a side
+    // stream while the recurrence goes on; when a test at j_t finds
+    // convergence the part ends at R = j_t, exactly as if it had stopped
+    // there: later steps only add rows and columns to T and rho, so their
+    // leading j_t block is final once step j_t is done.
+    SideTest side;
+    int pend_j = 0;   // basis size of the test in flight (0: none)
+    int stop_at = 0;  // basis size a finished test stopped the part at
+    bool near = false;
+    double prev_d = 0.0;  // the change of the lowest eigenvalue at the last test
+    if (o->etol > 0.0) {
+        QCM_HIP(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        QCM_HIP(hipEventCreateWithFlags(&side.copied, hipEventDisableTiming));
+        QCM_HIP(hipEventCreateWithFlags(&side.done, hipEventDisableTiming));
+        QCM_HIP(hipHostMalloc((void **)&side.h_theta, sizeof(double), hipHostMallocDefault));
+    }
+    // take the result of the test in flight, waiting for it or only if done
+    auto settle = [&](bool wait) -> int {
+        if (!pend_j) return QCM_OK;
+        if (wait) {
+            QCM_HIP(hipEventSynchronize(side.done));
+        } else {
+            const hipError_t q = hipEventQuery(side.done);
+            if (q == hipErrorNotReady) return QCM_OK;
+            QCM_HIP(q);
+        }
+        const double th = *side.h_theta;
+        if (have_prev && fabs(th - theta_prev) <= o->etol * std::max(1.0, fabs(th)))
+            stop_at = pend_j;
+        // when the change, shrinking at its last rate, would meet the
+        // tolerance at the next test, the steps wait for that test rather
+        // than run on speculatively
+        const double d = fabs(th - theta_prev);
+        near = have_prev && prev_d > 0.0 &&
+               d * (d / prev_d) <= o->etol * std::max(1.0, fabs(th));
+        if (have_prev) prev_d = d;
+        have_prev = true;
+        theta_prev = th;
+        pend_j = 0;
+        return QCM_OK;
+    };
     while (j < Rm) {
+        QCM_TRY(settle(near));
+        if (stop_at) {
+            P.R = stop_at;
+            return QCM_OK;
+        }
         ++j;
         double nrm = 0.0;
         for (;;) {
@@ -635,7 +698,8 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
             freeslots.push_back(cand[j]);
             --pc;
             if (pc == 0) {
-                P.R = j - 1;
+                QCM_TRY(settle(true));
+                P.R = stop_at ? stop_at : j - 1;
                 return QCM_OK;
             }
             for (int k = j; k < j + pc; ++k) cand[k] = cand[k + 1];
@@ -734,22 +798,25 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
                 ++it;
             }
         }
-        // the paper's stopping rule, once per block: the lowest eigenvalue of
-        // T_j (on a copy) against the one a block earlier
+        // the stopping test at this block boundary, after the one in flight
+        // (which holds the copy of T) has finished
         if (o->etol > 0.0 && j % p == 0) {
+            QCM_TRY(settle(true));
+            if (stop_at) break;
             QCM_HIP(hipMemcpy2DAsync(P.Tc, sizeof(double) * ldt, P.Tm, sizeof(double) * ldt,
                                      sizeof(double) * j, j, hipMemcpyDeviceToDevice, s));
-            kbl_lowest<<<1, kJacT, 0, s>>>(P.Tc, ldt, j, P.info);
+            QCM_HIP(hipEventRecord(side.copied, s));
+            QCM_HIP(hipStreamWaitEvent(side.s, side.copied, 0));
+            kbl_lowest<<<1, kJacT, 0, side.s>>>(P.Tc, ldt, j, P.info);
             QCM_LAUNCH_CHECK();
-            double th = 0.0;
-            QCM_HIP(hipMemcpyAsync(&th, P.info + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-            QCM_HIP(hipStreamSynchronize(s));
-            if (have_prev && fabs(th - theta_prev) <= o->etol * std::max(1.0, fabs(th))) break;
-            have_prev = true;
-            theta_prev = th;
+            QCM_HIP(hipMemcpyAsync(side.h_theta, P.info + 2, sizeof(double),
+                                   hipMemcpyDeviceToHost, side.s));
+            QCM_HIP(hipEventRecord(side.done, side.s));
+            pend_j = j;
         }
     }
-    P.R = j;
+    QCM_TRY(settle(true));
+    P.R = stop_at ? stop_at : j;
     return QCM_OK;
 }
 
