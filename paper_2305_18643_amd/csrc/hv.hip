@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include "qcm_internal.h"
+#include "lanczos_step.h"
 
 namespace qcm {
 
@@ -275,6 +276,48 @@ size_t hv_scratch_bytes(const HvOp &, int, int) { return 0; }
 
 template <typename T>
 static int hv_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipStream_t s) {
+    {
+        // rows that fit LDS with the packed up hops: the Lanczos step's product
+        // kernel, with no subtraction and no partial sums
+        const int prec = sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V;
+        int32_t rows = 0, nblk = 0;
+        row_shape(op.up.d, op.dn.d, prec, &rows, &nblk);
+        const size_t lds = fused_lds(op.up.d, rows, prec, op.md.nbytes, op.md.u_uniform,
+                                     2 * op.md.nbond);
+        if (op.hu.pk && lds <= kFusedLds) {
+            BGroup g;
+            memset(&g, 0, sizeof g);
+            g.d_up = op.up.d;
+            g.d_dn = op.dn.d;
+            g.dim = op.dim;
+            g.su = op.up.states;
+            g.sd = op.dn.states;
+            g.eu = op.hu.ediag;
+            g.ed = op.hd.ediag;
+            g.nhu = op.hu.nh;
+            g.nhd = op.hd.nh;
+            g.colu = op.hu.col;
+            g.cold = op.hd.col;
+            g.cfu = op.hu.coef;
+            g.cfd = op.hd.coef;
+            g.ulut = op.md.ulut;
+            g.pku = op.hu.pk;
+            g.ctab = op.md.ctab;
+            g.nctab = 2 * op.md.nbond;
+            g.u_uniform = op.md.u_uniform;
+            g.nbytes = op.md.nbytes;
+            g.rows = rows;
+            g.nblk = nblk;
+            g.nvec = nvec;
+            g.vp = v;   // not read: no subtraction
+            g.v = v;
+            g.w = w;
+            const OneSrc src{g};
+            ks_hv<T, OneSrc><<<(unsigned)((int64_t)nvec * nblk), 256, lds, s>>>(src);
+            QCM_LAUNCH_CHECK();
+            return QCM_OK;
+        }
+    }
     HvArgs a;
     a.d_up = op.up.d;
     a.d_dn = op.dn.d;
