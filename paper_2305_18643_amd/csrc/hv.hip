@@ -5,7 +5,10 @@
 //
 // A vector is the row-major d_dn x d_up matrix V[i_dn][i_up].  Then
 //   W = V K_up^T  (mixing inside a row)  +  K_dn V  (mixing whole rows)  +  D o V.
-// The kernel gives each workgroup one row i_dn: the row is staged in LDS,
+// Where the row tile fits LDS and the packed up hops exist, the product runs
+// in the Lanczos step's kernel (lanczos_step.h) with no subtraction and no
+// partial sums; otherwise (or for long rows, in the two-pass form) here.
+// The kernel below gives each workgroup one row i_dn: the row is staged in LDS,
 // the inside-row term gathers from LDS, the row-mixing term streams the
 // neighbour rows from global memory (coalesced along i_up), and the diagonal
 // is computed from the two strings.  All sums are FP64 in registers; the
