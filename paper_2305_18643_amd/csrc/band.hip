@@ -430,16 +430,32 @@ __global__ void __launch_bounds__(kJacT) kbl_eigh(double *__restrict__ A, int ld
         double x = dg[lo] - shift, z = of[lo];
         double dk = dg[lo], ek = of[lo];
         double wk = own ? wr[lo] : 0.0;
+        // the entries of row k + 1 are loaded one rotation ahead
+        double nd = dg[lo + 1], nek = lo + 1 < hi ? of[lo + 1] : 0.0;
+        double nw = own ? wr[lo + 1] : 0.0;
         for (int k = lo; k < hi; ++k) {
-            const double dk1 = dg[k + 1];
-            const double ek1 = k + 1 < hi ? of[k + 1] : 0.0;
-            const double wk1 = own ? wr[k + 1] : 0.0;
-            const double r = hypot(x, z);
-            double c = 1.0, s = 0.0;
-            if (r > 0.0) {
-                const double ir = 1.0 / r;
+            const double dk1 = nd, ek1 = nek, wk1 = nw;
+            if (k + 2 <= hi) {
+                nd = dg[k + 2];
+                nek = k + 2 < hi ? of[k + 2] : 0.0;
+                nw = own ? wr[k + 2] : 0.0;
+            }
+            // r = |(x, z)| and its reciprocal from one square root; the
+            // scaled form only where the squares could under- or overflow
+            const double r2 = fma(x, x, z * z);
+            double r, c = 1.0, s = 0.0;
+            if (r2 > 1e-280 && r2 < 1e280) {
+                const double ir = rsqrt(r2);
+                r = r2 * ir;
                 c = x * ir;
                 s = z * ir;
+            } else {
+                r = hypot(x, z);
+                if (r > 0.0) {
+                    const double ir = 1.0 / r;
+                    c = x * ir;
+                    s = z * ir;
+                }
             }
             if (k > lo) of[k - 1] = r;
             const double cs = c * s, c2 = c * c, s2 = s * s, tb = 2.0 * cs * ek;
