@@ -435,7 +435,9 @@ int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_
     Carver cv(d_ws);
     QCM_TRY(layout(cv, s));
 
-    // first pass: coefficients
+    // first pass: coefficients; the status starts empty (M = 0: no hint for
+    // the first test, as in the batched engine)
+    QCM_HIP(hipMemsetAsync(status, 0, sizeof(GsStatus), s));
     QCM_TRY(engine_reset(e, s));
     QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
     QCM_TRY(engine_normalize(e, s));

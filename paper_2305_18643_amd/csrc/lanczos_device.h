@@ -60,10 +60,17 @@ __device__ inline int sturm_below(int M, const double *__restrict__ a, const dou
 
 // k-th smallest eigenvalue by 256-way multisection: every thread tests one
 // point of the current bracket; 10 rounds narrow it by 257^10.  b2 = b^2.
+// hint (k = 0 only): the lowest eigenvalue of a leading block of T, which
+// can only lie above that of T; once a Sturm count confirms an eigenvalue
+// below it (plus 1e-12 relative) it becomes the upper end, and the first
+// round then spaces its points geometrically toward that end, where the
+// eigenvalue of a converging recurrence lies.  Any hint is safe: one that
+// the count does not confirm is ignored.
 __device__ inline double tridiag_kth(int M, const double *a, const double *b, const double *b2,
-                                     int k, double *sh_lo, double *sh_hi) {
+                                     int k, double *sh_lo, double *sh_hi, double hint = NAN) {
     const int t = threadIdx.x;
     __shared__ int cnts[256];
+    __shared__ int first, geo;
     if (t == 0) {
         double lo = a[0], hi = a[0];
         for (int i = 0; i < M; ++i) {
@@ -74,14 +81,27 @@ __device__ inline double tridiag_kth(int M, const double *a, const double *b, co
         double pad = 1e-12 * fmax(1.0, fmax(fabs(lo), fabs(hi)));
         *sh_lo = lo - pad;
         *sh_hi = hi + pad;
+        geo = 0;
+        if (k == 0 && isfinite(hint)) {
+            const double up = hint + 1e-12 * fmax(1.0, fabs(hint));
+            if (up > *sh_lo && up < *sh_hi && sturm_below(M, a, b2, up) > 0) {
+                *sh_hi = up;
+                geo = 1;
+            }
+        }
     }
     __syncthreads();
-    __shared__ int first;
     for (int round = 0; round < 10; ++round) {
         const double lo = *sh_lo, hi = *sh_hi;
         // stop once the bracket is at the resolution of its end points
         if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)))) break;
-        double x = lo + (hi - lo) * (double)(t + 1) / 257.0;
+        const bool g = round == 0 && geo;
+        // point j of the round: uniform, or hi - (hi - lo) 2^(-53 (j + 1) / 256)
+        auto point = [&](int j) -> double {
+            return g ? hi - (hi - lo) * exp2(-53.0 * (double)(j + 1) / 256.0)
+                     : lo + (hi - lo) * (double)(j + 1) / 257.0;
+        };
+        const double x = point(t);
         cnts[t] = sturm_below(M, a, b2, x);
         if (t == 0) first = 256;
         __syncthreads();
@@ -91,8 +111,8 @@ __device__ inline double tridiag_kth(int M, const double *a, const double *b, co
         __syncthreads();
         if (t == 0) {
             const int j = first;
-            double nlo = j == 0 ? lo : lo + (hi - lo) * (double)j / 257.0;
-            double nhi = j == 256 ? hi : lo + (hi - lo) * (double)(j + 1) / 257.0;
+            const double nlo = j == 0 ? lo : point(j - 1);
+            const double nhi = j == 256 ? hi : point(j);
             *sh_lo = nlo;
             *sh_hi = nhi;
         }
@@ -216,7 +236,10 @@ __device__ inline void tridiag_status_block(const double *__restrict__ alpha,
         for (int i = threadIdx.x; i < M; i += blockDim.x) b2[i] = beta[i] * beta[i];
     }
     __syncthreads();
-    double th0 = tridiag_kth(M, a, b, b2, 0, &lo, &hi);
+    // the previous test's theta_0 (of T_{M'}, M' <= M) as the hint
+    const double hint = (status->M >= 1 && status->M <= M) ? status->theta0 : NAN;
+    __syncthreads();
+    double th0 = tridiag_kth(M, a, b, b2, 0, &lo, &hi, hint);
     double th1 = (want1 && M > 1) ? tridiag_kth(M, a, b, b2, 1, &lo, &hi) : NAN;
     if (threadIdx.x == 0) {
         const int S = in_lds ? kTriLds : M;
