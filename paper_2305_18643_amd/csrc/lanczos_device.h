@@ -38,9 +38,13 @@ __device__ __forceinline__ void st(T *p, double x) {
 // i.e. the negative pivots q_i = p_i / p_{i-1} of the LDL^T of T_M - x, counted
 // without a division.  The pair (p_i, p_{i-1}) is rescaled by a power of two
 // whenever p_i leaves [2^-256, 2^256] (exact), and a vanishing p_i becomes
-// -1e-300 p_{i-1} (a pivot of -1e-300).  b2[i] = b[i]^2.
-__device__ inline int sturm_below(int M, const double *__restrict__ a, const double *__restrict__ b2,
-                           double x) {
+// -2^-700 p_{i-1} (a pivot of -2^-700, so an eigenvalue at x counts as below
+// it).  |p_{i-1}| lies in [2^-256, 2^256] there, so the replacement is a
+// normal number and the rescale that follows brings the pair back into range
+// (a replacement that underflowed to -0 would lose this and every later sign
+// change).  b2[i] = b[i]^2.  Callable on the host too (for tests).
+__host__ __device__ inline int sturm_below(int M, const double *__restrict__ a,
+                                           const double *__restrict__ b2, double x) {
     // branch-free body, so that the loads of later steps can go out early
     int cnt = 0;
     double pm = 1.0, pmm = 0.0;
@@ -48,7 +52,7 @@ __device__ inline int sturm_below(int M, const double *__restrict__ a, const dou
     for (int i = 0; i < M; ++i) {
         const double bi = i > 0 ? b2[i - 1] : 0.0;
         double p = fma(-bi, pmm, (a[i] - x) * pm);
-        p = p == 0.0 ? -1e-300 * pm : p;
+        p = p == 0.0 ? -0x1p-700 * pm : p;
         cnt += (p < 0.0) != (pm < 0.0);
         const int e = ilogb(p);
         const int k = (e > 256 || e < -256) ? -e : 0;
