@@ -39,8 +39,9 @@ def band_lanczos(matvec, B: np.ndarray, max_basis: int, dtol_rel: float = 1e-10,
     one block of p basis vectors (tested when R is a multiple of p), the
     paper's rule against orthogonality leaks.
     full_reorth (a test device, not the paper's recurrence) also removes
-    from each new candidate its components along every earlier basis vector
-    without recording them in T, so that an exhausted space deflates
+    from each new candidate, and again from each candidate before its
+    deflation test, its components along every earlier basis vector (two
+    passes) without recording them in T, so that an exhausted space deflates
     exactly."""
     n, p = B.shape
     vhat = {k + 1: np.array(B[:, k], dtype=np.float64) for k in range(p)}  # candidates
@@ -56,6 +57,13 @@ def band_lanczos(matvec, B: np.ndarray, max_basis: int, dtol_rel: float = 1e-10,
         j += 1
         # (1) deflation test of the next candidate
         while True:
+            if full_reorth:
+                # the candidate is also cleared of every earlier basis vector
+                # (twice, so that what is left of a dependent candidate is at
+                # rounding level and deflates)
+                for _ in range(2):
+                    for k in sorted(V):
+                        vhat[j] = vhat[j] - float(np.dot(V[k], vhat[j])) * V[k]
             nrm = float(np.sqrt(np.dot(vhat[j], vhat[j])))
             if nrm > dtol_rel * scale:
                 break
@@ -99,8 +107,9 @@ def band_lanczos(matvec, B: np.ndarray, max_basis: int, dtol_rel: float = 1e-10,
         for k in I:
             t[(j, k)] = t[(k, j)]
         if full_reorth:
-            for k in sorted(V):
-                w = w - float(np.dot(V[k], w)) * V[k]
+            for _ in range(2):
+                for k in sorted(V):
+                    w = w - float(np.dot(V[k], w)) * V[k]
         vhat[j + pc] = w
         if not full_reorth:
             # basis vectors older than the band and outside I are not needed again

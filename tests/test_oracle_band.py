@@ -45,8 +45,9 @@ def _qqt(parts, orbs):
 
 @pytest.mark.parametrize("m,orbs", [(synth.plaquette_2x2(), [0, 1, 2, 3]),
                                     (synth.random_model(501, 6, 3, 2), [0, 2, 5]),
-                                    (synth.impurity_model(np.random.default_rng(3), 2), [0, 1, 2, 3])],
-                         ids=["2x2", "rand6", "imp6"])
+                                    (synth.impurity_model(np.random.default_rng(3), 2), [0, 1, 2, 3]),
+                                    (synth.random_model(42, 5, 2, 3), [0, 1, 2, 3, 4])],
+                         ids=["2x2", "rand6", "imp6", "rand5"])
 def test_band_exhausted_equals_dense_lehmann(m, orbs):
     e0, psi = _gs(m)
     G, parts = band.green_band(m.t, m.U, m.nup, m.ndn, psi, orbs, e0, Z, max_basis=2000,
