@@ -177,7 +177,18 @@ typedef struct qcm_gs_result {
     int32_t n_iter;       /* M, number of Lanczos steps */
     int32_t converged;    /* residual test met (or breakdown) */
     int32_t breakdown;    /* Krylov space exhausted */
-    int32_t pad;
+    int32_t degenerate_suspect;  /* 1 when theta1 - e0 < 1e-8 max(1, |e0|): the
+                             ground state may be degenerate, so the returned
+                             vector is one state of a manifold and G built on it
+                             is not unique (the paper hands such cases to other
+                             methods, subsection "The Lanczos algorithm for the
+                             ground state").  Single-vector Lanczos cannot tell
+                             a true second eigenvalue from a copy of e0 made by
+                             loss of orthogonality (which appears only after e0
+                             has converged, e.g. with long fixed_steps runs), nor
+                             see a degenerate partner before rounding feeds it
+                             in: the flag asks for a closer look (a dense check
+                             or a second start vector), it does not decide. */
 } qcm_gs_result;
 
 /*
@@ -296,6 +307,21 @@ int qcm_green_band(const qcm_model *m, const qcm_basis *gs, const double *d_gs, 
                    const qcm_band_opts *o, int32_t *h_R, double *h_lambda, double *h_Q,
                    int32_t n_z, const double *h_z, double *d_G, void *d_ws, size_t ws_bytes,
                    size_t *ws_needed, void *stream);
+
+/*
+ * qcm_lehmann_form — the Lehmann representation of eq. (spectral1) from the
+ * output of qcm_green_band: the poles measured from the ground-state energy,
+ *   electron r < R_e:  w_r = Lambda_e[r] - e0,   Q[:, r]       = Q_e[:, r],
+ *   hole     r < R_h:  w_{R_e + r} = e0 - Lambda_h[r], Q[:, R_e + r] = Q_h[:, r],
+ * so that G_ij(z) = sum_r Q_ir Q_jr / (z - w_r).
+ *   n_orb, max_basis: as passed to qcm_green_band; h_R, h_lambda, h_Q: its
+ *   host outputs ([2], [2][max_basis], [2][n_orb][max_basis]).
+ *   h_poles: host [h_R[0] + h_R[1]]; h_Qout: host [n_orb][h_R[0] + h_R[1]].
+ * Host arithmetic only (no device work).  Errors: QCM_EARG (NULL pointer,
+ * R outside [0, max_basis]).
+ */
+int qcm_lehmann_form(int32_t n_orb, int32_t max_basis, double e0, const int32_t *h_R,
+                     const double *h_lambda, const double *h_Q, double *h_poles, double *h_Qout);
 
 /* An inter-cluster hopping term for CPT: amplitude t between site i of the
  * cluster at the origin and site j of the cluster at shift[0] E1 +
@@ -669,7 +695,7 @@ typedef struct qcm_job_result {
     int32_t status;          /* QCM_OK */
     int64_t bytes;           /* pool bytes the job held */
     int32_t rounds;          /* rounds from admission to completion */
-    int32_t pad;
+    int32_t degenerate_suspect;  /* as in qcm_gs_result */
 } qcm_job_result;
 
 typedef struct qcm_engine_stats {

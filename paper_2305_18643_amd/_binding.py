@@ -55,7 +55,7 @@ class GsResult(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("residual_est", ctypes.c_double),
                 ("true_residual", ctypes.c_double), ("theta1", ctypes.c_double),
                 ("n_iter", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("breakdown", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("breakdown", ctypes.c_int32), ("degenerate_suspect", ctypes.c_int32)]
 
 
 class GreenOpts(ctypes.Structure):
@@ -113,7 +113,8 @@ class JobResult(ctypes.Structure):
                 ("residual_est", ctypes.c_double), ("true_residual", ctypes.c_double),
                 ("n_iter", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("breakdown", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("bytes", ctypes.c_int64), ("rounds", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("bytes", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("degenerate_suspect", ctypes.c_int32)]
 
 
 class EngineStats(ctypes.Structure):
@@ -131,7 +132,8 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_engine_info", "qcm_batch_solve", "qcm_hv_plan_create", "qcm_hv_plan_apply",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
            "qcm_cdmft_fit", "qcm_vca_omega", "qcm_vca_omega_quad", "qcm_sym_sector_build", "qcm_sym_csr_count",
-           "qcm_sym_csr_fill", "qcm_sym_csr_pack", "qcm_sym_hv", "qcm_sym_lanczos_gs"]
+           "qcm_sym_csr_fill", "qcm_sym_csr_pack", "qcm_sym_hv", "qcm_sym_lanczos_gs",
+           "qcm_lehmann_form"]
 
 _lib = None
 
@@ -174,6 +176,9 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_green_band.restype = ctypes.c_int
     lib.qcm_green_band.argtypes = [P(Model), P(Basis), vp, ctypes.c_double, P(BandOpts), _c_i32,
                                    _c_d, _c_d, ctypes.c_int32, _c_d, vp, vp, sz, _c_sz, vp]
+    lib.qcm_lehmann_form.restype = ctypes.c_int
+    lib.qcm_lehmann_form.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _c_i32,
+                                     _c_d, _c_d, _c_d, _c_d]
     lib.qcm_hv_plan_create.restype = ctypes.c_int
     lib.qcm_hv_plan_create.argtypes = [P(Model), P(Basis), ctypes.c_int32, vp, sz, _c_sz, vp, P(vp)]
     lib.qcm_hv_plan_apply.restype = ctypes.c_int
@@ -421,7 +426,8 @@ def lanczos_gs(model, basis: SectorBasis, *, max_iter=600, fixed_steps=0, want_v
     M = res.n_iter
     return dict(e0=res.e0, residual_est=res.residual_est, true_residual=res.true_residual,
                 theta1=res.theta1, n_iter=M, converged=bool(res.converged),
-                breakdown=bool(res.breakdown), alpha=alpha[:M], beta=beta[:M], psi=psi)
+                breakdown=bool(res.breakdown), degenerate_suspect=bool(res.degenerate_suspect),
+                alpha=alpha[:M], beta=beta[:M], psi=psi)
 
 
 def green_cf(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_steps=200, prec="fp64",
@@ -494,8 +500,15 @@ def green_band(model, basis: SectorBasis, psi, e0: float, orbs, z, *, max_basis=
                               Q.ctypes.data_as(_c_d), nz, zz.ctypes.data_as(_c_d),
                               ctypes.c_void_p(G.data_ptr()), _ptr(ws), ws.numel(),
                               ctypes.byref(need), _stream(torch, stream)))
+    Rt = int(R[0]) + int(R[1])
+    poles = np.zeros(max(Rt, 1))
+    Qcat = np.zeros((n, max(Rt, 1)))
+    _check(lib.qcm_lehmann_form(n, max_basis, float(e0), R.ctypes.data_as(_c_i32),
+                                lam.ctypes.data_as(_c_d), Q.ctypes.data_as(_c_d),
+                                poles.ctypes.data_as(_c_d), Qcat.ctypes.data_as(_c_d)))
     return dict(G=G[:nz], R=R, lam=[lam[k, :R[k]].copy() for k in range(2)],
-                Q=[Q[k, :, :R[k]].copy() for k in range(2)])
+                Q=[Q[k, :, :R[k]].copy() for k in range(2)],
+                poles=poles[:Rt].copy(), Q_lehmann=np.ascontiguousarray(Qcat[:, :Rt]))
 
 
 def cpt_gk(Gc, R, E, bonds, ks, z=None, stream=None):
@@ -720,7 +733,8 @@ class JobSpec:
     def result(self, r: JobResult, n_z: int) -> dict:
         return dict(tag=self.tag, e0=r.e0, theta1=r.theta1, residual_est=r.residual_est,
                     true_residual=r.true_residual, n_iter=r.n_iter, converged=bool(r.converged),
-                    breakdown=bool(r.breakdown), bytes=r.bytes, rounds=r.rounds,
+                    breakdown=bool(r.breakdown), degenerate_suspect=bool(r.degenerate_suspect),
+                    bytes=r.bytes, rounds=r.rounds,
                     G=self.G[:n_z] if self.orbs.shape[0] else None, coef=self.coef, len=self.len,
                     psi=self.psi)
 
@@ -970,4 +984,5 @@ def sym_lanczos_gs(H: SymHamiltonian, *, max_iter=600, fixed_steps=0, want_vecto
     M = res.n_iter
     return dict(e0=res.e0, residual_est=res.residual_est, true_residual=res.true_residual,
                 theta1=res.theta1, n_iter=M, converged=bool(res.converged),
-                breakdown=bool(res.breakdown), alpha=alpha[:M], beta=beta[:M], psi=psi)
+                breakdown=bool(res.breakdown), degenerate_suspect=bool(res.degenerate_suspect),
+                alpha=alpha[:M], beta=beta[:M], psi=psi)

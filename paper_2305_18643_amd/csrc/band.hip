@@ -840,6 +840,29 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
 
 using namespace qcm;
 
+extern "C" int qcm_lehmann_form(int32_t n_orb, int32_t max_basis, double e0, const int32_t *h_R,
+                                const double *h_lambda, const double *h_Q, double *h_poles,
+                                double *h_Qout) {
+    if (!h_R || !h_lambda || !h_Q || !h_poles || !h_Qout)
+        return fail(QCM_EARG, "qcm_lehmann_form: NULL pointer");
+    if (n_orb < 1 || max_basis < 1) return fail(QCM_EARG, "qcm_lehmann_form: n_orb, max_basis < 1");
+    for (int k = 0; k < 2; ++k)
+        if (h_R[k] < 0 || h_R[k] > max_basis)
+            return fail(QCM_EARG, "qcm_lehmann_form: R[%d] = %d outside [0, %d]", k, h_R[k],
+                        max_basis);
+    const int Re = h_R[0], Rh = h_R[1], R = Re + Rh;
+    // electron poles Lambda_e - E0 first, then hole poles E0 - Lambda_h
+    for (int r = 0; r < Re; ++r) h_poles[r] = h_lambda[r] - e0;
+    for (int r = 0; r < Rh; ++r) h_poles[Re + r] = e0 - h_lambda[max_basis + r];
+    for (int i = 0; i < n_orb; ++i) {
+        for (int r = 0; r < Re; ++r) h_Qout[(size_t)i * R + r] = h_Q[(size_t)i * max_basis + r];
+        for (int r = 0; r < Rh; ++r)
+            h_Qout[(size_t)i * R + Re + r] =
+                h_Q[((size_t)n_orb + i) * max_basis + r];
+    }
+    return QCM_OK;
+}
+
 extern "C" void qcm_band_default_opts(qcm_band_opts *o) {
     if (!o) return;
     memset(o, 0, sizeof *o);

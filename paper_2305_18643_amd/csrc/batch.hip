@@ -472,6 +472,7 @@ static int complete(qcm_engine *E, Job &j) {
     r.status = QCM_OK;
     r.bytes = (int64_t)j.bytes;
     r.rounds = (int32_t)(E->rounds - j.round0);
+    r.degenerate_suspect = degenerate_suspect(j.fin_gs.theta0, j.fin_gs.theta1);
     E->finished.push_back(r);
     pool_free(E, j.off, j.bytes);
     return QCM_OK;

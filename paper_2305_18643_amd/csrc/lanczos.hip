@@ -486,6 +486,7 @@ int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_
     r.n_iter = M;
     r.converged = conv;
     r.breakdown = brk;
+    r.degenerate_suspect = degenerate_suspect(hs.theta0, hs.theta1);
     r.true_residual = -1.0;
 
     // the coefficients of the first pass go out before the second pass reruns

@@ -64,6 +64,14 @@ struct Carver {
 
 inline size_t ceil_div(size_t a, size_t b) { return (a + b - 1) / b; }
 
+// The ground state may be degenerate: the second Ritz value lies within
+// 1e-8 max(1, |theta_0|) of the first (theta_1 is NaN for a 1x1 T).
+inline int degenerate_suspect(double theta0, double theta1) {
+    return (theta1 == theta1 && theta1 - theta0 < 1e-8 * (fabs(theta0) > 1.0 ? fabs(theta0) : 1.0))
+               ? 1
+               : 0;
+}
+
 // ---------------------------------------------------------------- sector
 struct SpinTables {
     int32_t L, N, l_lo, l_hi;

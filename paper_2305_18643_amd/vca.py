@@ -26,8 +26,7 @@ def reference_lehmann(prob, *, max_basis=1000):
     gs = B.lanczos_gs(model, basis)
     g = B.green_band(model, basis, gs["psi"], gs["e0"], list(range(L)), np.array([1j]),
                      max_basis=max_basis)
-    poles = np.concatenate([g["lam"][0] - gs["e0"], gs["e0"] - g["lam"][1]])
-    return gs["e0"], poles, np.concatenate(g["Q"], axis=1)
+    return gs["e0"], g["poles"], g["Q_lehmann"]
 
 
 def omega(prob, ks, *, max_basis=1000, method="poles", rtol=1e-12):

@@ -282,3 +282,42 @@ def test_vca_quad_argument_checks(lib):
     assert call(mi=4) == b.QCM_EARG
     assert call(R_=0) == b.QCM_ERANGE
     assert call(nk=0) == b.QCM_EARG
+
+
+def test_lehmann_form_assembles_poles_and_residues(lib):
+    # host arithmetic only: the band output of the oracle (full
+    # reorthogonalisation, exhausted Krylov space) turned into (poles, Q) by
+    # the library gives G(z) = sum_r Q_ir Q_jr / (z - w_r) equal to the exact
+    # Lehmann sum of dense diagonalisation
+    from paper_2305_18643_amd import _binding as b
+    import synth
+    from oracle import band, dense
+    m = synth.random_model(42, 5, 2, 3)
+    e0, psi, _ = dense.ground_state(m.t, m.U, 2, 3)
+    orbs = [0, 1, 2, 3, 4]
+    z = synth.omega_grid()[::8]
+    mb = 2000
+    _, parts = band.green_band(m.t, m.U, 2, 3, psi, orbs, e0, z, max_basis=mb, full_reorth=True)
+    p = len(orbs)
+    R = np.array([parts[0][0].shape[0], parts[1][0].shape[0]], dtype=np.int32)
+    lam = np.zeros((2, mb))
+    Q = np.zeros((2, p, mb))
+    for k in range(2):
+        lam[k, :R[k]] = parts[k][0]
+        Q[k, :, :R[k]] = parts[k][1]
+    Rt = int(R.sum())
+    poles = np.zeros(Rt)
+    Qo = np.zeros((p, Rt))
+    rc = lib.qcm_lehmann_form(p, mb, e0, R.ctypes.data_as(b._c_i32), lam.ctypes.data_as(b._c_d),
+                              Q.ctypes.data_as(b._c_d), poles.ctypes.data_as(b._c_d),
+                              Qo.ctypes.data_as(b._c_d))
+    assert rc == b.QCM_OK
+    G = np.einsum("ir,jr,zr->zij", Qo, Qo, 1.0 / (z[:, None] - poles[None, :]))
+    Gd = dense.lehmann_green(m.t, m.U, 2, 3, orbs, z)
+    assert np.max(np.abs(G - Gd)) < 1e-10
+    # the anticommutator: Q Q^T = 1
+    assert np.max(np.abs(Qo @ Qo.T - np.eye(p))) < 1e-10
+    bad = np.array([mb + 1, 0], dtype=np.int32)
+    assert lib.qcm_lehmann_form(p, mb, e0, bad.ctypes.data_as(b._c_i32), lam.ctypes.data_as(b._c_d),
+                                Q.ctypes.data_as(b._c_d), poles.ctypes.data_as(b._c_d),
+                                Qo.ctypes.data_as(b._c_d)) == b.QCM_EARG

@@ -188,6 +188,29 @@ def test_fixed_steps_and_breakdown(q):
     assert abs(r["e0"] + 12.0) < 1e-12
 
 
+def test_degenerate_suspect_flag(q):
+    # near-degenerate: two identical dimers (t = -1) coupled by 1e-10, one up
+    # electron: the lowest two one-body levels are -1 -+ 5e-11, which the
+    # exhausted Krylov space resolves, so theta_1 - theta_0 ~ 1e-10 < 1e-8
+    from oracle import dense
+    t = np.zeros((4, 4))
+    t[0, 1] = t[1, 0] = t[2, 3] = t[3, 2] = -1.0
+    t[1, 2] = t[2, 1] = 1e-10
+    U = np.full(4, 4.0)
+    w = dense.ground_state(t, U, 1, 0)[2]
+    assert w[1] - w[0] < 1e-8
+    b = q.sector_basis(4, 1, 0)
+    r = q.lanczos_gs((t, U), b)
+    assert r["degenerate_suspect"], (r["e0"], r["theta1"])
+    assert abs(r["e0"] - w[0]) < 1e-12
+    # a non-degenerate ground state (the half-filled plaquette, gap > 0.1)
+    m = synth.plaquette_2x2()
+    wd = dense.ground_state(m.t, m.U, m.nup, m.ndn)[2]
+    assert wd[1] - wd[0] > 0.1
+    r2 = q.lanczos_gs(m, q.sector_basis(m.L, m.nup, m.ndn))
+    assert r2["converged"] and not r2["degenerate_suspect"], r2["theta1"] - r2["e0"]
+
+
 # ---------------------------------------------------------------- Green function and CPT
 
 Z64 = synth.omega_grid()
