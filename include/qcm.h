@@ -131,6 +131,28 @@ int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, const void *d_v
            void *d_ws, size_t ws_bytes, size_t *ws_needed, void *stream);
 
 /*
+ * qcm_hv_noalloc — the product of qcm_hv (same kernels, same result bit for
+ * bit) for callers that cannot allocate device memory or pass a workspace
+ * (tight serving loops, hosts that forbid hipMalloc).  It is not meant for
+ * stream capture: the model is copied from host memory on every call, and on
+ * sectors with long rows the set-up waits for the stream once.  The hopping
+ * tables go to a fixed device-resident array of
+ * 32 MiB per GPU that the library holds until the process ends (the first
+ * call on a device looks up its address there); the call allocates nothing.
+ * Sectors whose tables need more (qcm_hv's size query above 32 MiB; the
+ * 16-orbital (8, 8) sector needs about 18 MB) are rejected with
+ * QCM_EWORKSPACE before anything is enqueued.
+ *   m, b, prec, d_v, d_w, stream: as in qcm_hv.
+ * Every call on one GPU rewrites that GPU's array: calls that overlap on one
+ * GPU (other streams, other host threads) race and give undefined results;
+ * serialise them.  Nothing in the array needs clearing between calls.
+ * Errors: QCM_EARG, QCM_EWORKSPACE, QCM_EHIP.  Asynchronous apart from that
+ * wait.
+ */
+int qcm_hv_noalloc(const qcm_model *m, const qcm_basis *b, int32_t prec, const void *d_v,
+                   void *d_w, void *stream);
+
+/*
  * Plans: the tables of qcm_hv built once and applied many times.
  * qcm_hv_plan_create builds the model- and sector-dependent tables into d_ws
  * (size query with d_ws == NULL, as everywhere) and returns a host handle;

@@ -133,7 +133,7 @@ EXPORTS = ["qcm_last_error", "qcm_version", "qcm_sector_basis", "qcm_hv",
            "qcm_hv_plan_destroy", "qcm_band_default_opts", "qcm_green_band", "qcm_cdmft_g0inv",
            "qcm_cdmft_fit", "qcm_vca_omega", "qcm_vca_omega_quad", "qcm_sym_sector_build", "qcm_sym_csr_count",
            "qcm_sym_csr_fill", "qcm_sym_csr_pack", "qcm_sym_hv", "qcm_sym_lanczos_gs",
-           "qcm_lehmann_form"]
+           "qcm_lehmann_form", "qcm_hv_noalloc"]
 
 _lib = None
 
@@ -176,6 +176,9 @@ def load_library(path: str = LIB_PATH):
     lib.qcm_green_band.restype = ctypes.c_int
     lib.qcm_green_band.argtypes = [P(Model), P(Basis), vp, ctypes.c_double, P(BandOpts), _c_i32,
                                    _c_d, _c_d, ctypes.c_int32, _c_d, vp, vp, sz, _c_sz, vp]
+    lib.qcm_hv_noalloc.restype = ctypes.c_int
+    lib.qcm_hv_noalloc.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Basis), ctypes.c_int32, vp,
+                                   vp, vp]
     lib.qcm_lehmann_form.restype = ctypes.c_int
     lib.qcm_lehmann_form.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _c_i32,
                                      _c_d, _c_d, _c_d, _c_d]
@@ -350,6 +353,21 @@ def hv(model, basis: SectorBasis, v, w=None, stream=None, ws=None):
         ws = _workspace(torch, need.value, v.device)
     _check(lib.qcm_hv(ctypes.byref(m.c), ctypes.byref(basis.c), prec, _ptr(v), _ptr(w), _ptr(ws),
                       ws.numel(), ctypes.byref(need), _stream(torch, stream)))
+    return w
+
+
+def hv_noalloc(model, basis: SectorBasis, v, w, stream=None):
+    """w = H v through qcm_hv_noalloc (tables in the library's static device
+    array; nothing allocated).  v, w: device float64 or float32 tensors."""
+    torch = _torch()
+    lib = load_library()
+    m = as_model(model)
+    prec = QCM_FP64 if v.dtype == torch.float64 else QCM_FP32V
+    for x in (v, w):
+        if x.dtype != v.dtype or x.numel() != basis.dim or not x.is_contiguous():
+            raise ValueError("v, w must be contiguous tensors of one dtype and length dim")
+    _check(lib.qcm_hv_noalloc(ctypes.byref(m.c), ctypes.byref(basis.c), prec, _ptr(v), _ptr(w),
+                              _stream(torch, stream)))
     return w
 
 

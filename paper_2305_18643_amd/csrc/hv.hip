@@ -15,6 +15,8 @@
 // output is rounded once to the storage type.
 #include <string.h>
 
+#include <mutex>
+
 #include "qcm_internal.h"
 #include "lanczos_step.h"
 
@@ -425,6 +427,71 @@ extern "C" int qcm_hv(const qcm_model *m, const qcm_basis *b, int32_t prec, cons
     if (pv < pw + vb && pw < pv + vb) return fail(QCM_EARG, "qcm_hv: v and w overlap");
     hipStream_t s = as_stream(stream);
     Carver cv(d_ws);
+    HvOp op;
+    QCM_TRY(hv_setup(m, b, cv, &op, s));
+    return hv_launch(op, prec, d_v, d_w, 1, s);
+}
+
+// ---------------------------------------------------------------- allocation-free product
+
+namespace qcm {
+
+// The tables of the allocation-free product live in this device array, one
+// copy per GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: it uses the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// The device address of `scratch` on the current device, looked up on the
+// first call there.
+static int static_scratch(void **out) {
+    int dev = -1;
+    QCM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QCM_EARG, "qcm_hv_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        QCM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(QCM_EHIP, "qcm_hv_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QCM_OK;
+}
+
+}  // namespace qcm
+
+extern "C" int qcm_hv_noalloc(const qcm_model *m, const qcm_basis *b, int32_t prec,
+                              const void *d_v, void *d_w, void *stream) {
+    QCM_TRY(validate_model(m));
+    QCM_TRY(check_basis(b, m->L));
+    if (prec != QCM_FP64 && prec != QCM_FP32V)
+        return fail(QCM_EARG, "qcm_hv_noalloc: bad prec %d", prec);
+    size_t need = 0;
+    QCM_TRY(hv_setup_bytes(m, b, &need));
+    if (need > kStaticScratchBytes)
+        return fail(QCM_EWORKSPACE,
+                    "qcm_hv_noalloc: the sector's tables need %zu bytes, more than the %zu-byte "
+                    "static scratch (use qcm_hv with a workspace)",
+                    need, kStaticScratchBytes);
+    if (!d_v || !d_w) return fail(QCM_EARG, "qcm_hv_noalloc: NULL vector");
+    size_t vb = (prec == QCM_FP64 ? 8 : 4) * (size_t)b->dim;
+    const char *pv = (const char *)d_v, *pw = (const char *)d_w;
+    if (pv < pw + vb && pw < pv + vb) return fail(QCM_EARG, "qcm_hv_noalloc: v and w overlap");
+    void *ws = nullptr;
+    QCM_TRY(static_scratch(&ws));
+    hipStream_t s = as_stream(stream);
+    // every table the product reads is rewritten here, so nothing carried
+    // over from an earlier call needs clearing
+    Carver cv(ws);
     HvOp op;
     QCM_TRY(hv_setup(m, b, cv, &op, s));
     return hv_launch(op, prec, d_v, d_w, 1, s);
