@@ -91,6 +91,8 @@ def _load():
         lib.ora_cf_chain.restype = ctypes.c_int
         lib.ora_cf_chain.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, ctypes.c_int, _d,
                                      ctypes.c_int, ctypes.c_double, _d, _d, _d, ctypes.c_int]
+        lib.ora_cf_chain_full.restype = ctypes.c_int
+        lib.ora_cf_chain_full.argtypes = lib.ora_cf_chain.argtypes
         _lib = lib
     return _lib
 
@@ -273,22 +275,27 @@ def apply_op(L: int, nup: int, ndn: int, psi: np.ndarray, kind: int, mu: int,
 
 
 def cf_chain(t, U, nup: int, ndn: int, phi: np.ndarray, max_steps: int, btol: float = 1e-13,
-             nthreads: int | None = None):
+             nthreads: int | None = None, full_reorth: bool = False):
     """Lanczos chain from phi (not normalised) in sector (nup, ndn).
-    Returns (b0sq, a[len], b2[len-1])."""
+    Returns (b0sq, a[len], b2[len-1]).  full_reorth: the test device that
+    removes from every new vector its components along all earlier chain
+    vectors (twice), not entered in T."""
     L, t, U = _model_arrays(t, U)
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     a = np.zeros(max_steps)
     b2 = np.zeros(max_steps)
     b0 = np.zeros(1)
-    n = _load().ora_cf_chain(L, _p(t, _d), _p(U, _d), nup, ndn, _p(phi, _d), max_steps, btol,
-                             _p(b0, _d), _p(a, _d), _p(b2, _d), nthreads or default_threads())
+    lib = _load()
+    fn = lib.ora_cf_chain_full if full_reorth else lib.ora_cf_chain
+    n = fn(L, _p(t, _d), _p(U, _d), nup, ndn, _p(phi, _d), max_steps, btol,
+           _p(b0, _d), _p(a, _d), _p(b2, _d), nthreads or default_threads())
     assert n >= 0
     return float(b0[0]), a[:n].copy(), b2[:max(n - 1, 0)].copy()
 
 
 def green_cf(t, U, nup: int, ndn: int, psi: np.ndarray, orbs, max_steps: int = 200,
-             btol: float = 1e-13, nthreads: int | None = None) -> dict:
+             btol: float = 1e-13, nthreads: int | None = None,
+             full_reorth: bool = False) -> dict:
     """All continued fractions for the up-spin Green function restricted to
     the orbitals ``orbs``: for each pair (i <= j) of positions in ``orbs`` an
     electron chain from (c_mu + c_nu)+ psi and a hole chain from
@@ -305,5 +312,6 @@ def green_cf(t, U, nup: int, ndn: int, psi: np.ndarray, orbs, max_steps: int = 2
                     out[(i, j, part)] = (0.0, np.zeros(0), np.zeros(0))
                     continue
                 phi = apply_op(L, nup, ndn, psi, part, mu, nu)
-                out[(i, j, part)] = cf_chain(t, U, nup2, ndn, phi, max_steps, btol, nthreads)
+                out[(i, j, part)] = cf_chain(t, U, nup2, ndn, phi, max_steps, btol, nthreads,
+                                             full_reorth)
     return out

@@ -616,3 +616,74 @@ int ora_cf_chain(int L, const double *t, const double *U, int nup, int ndn,
     sector_free(&s);
     return M;
 }
+
+/* The same chain with full reorthogonalisation (a test device, not the
+ * paper's recurrence, which tolerates the loss of orthogonality): after
+ * w = H v_n - beta_{n-1} v_{n-1} - alpha_n v_n, the components of w along
+ * every earlier chain vector v_0..v_n are removed twice (classical
+ * Gram-Schmidt: all coefficients <v_k, w> first, then one subtraction per
+ * element), and those corrections are not entered in T.  The chain then is
+ * the Lanczos recurrence of exact arithmetic up to rounding, so its
+ * coefficients and its truncated G do not depend on the rounding history.
+ * Stores all chain vectors ((max_steps + 1) dim doubles). */
+int ora_cf_chain_full(int L, const double *t, const double *U, int nup, int ndn,
+                      const double *phi, int max_steps, double btol, double *b0sq,
+                      double *a, double *b2, int nthreads)
+{
+    sector_t s;
+    if (sector_init(&s, L, nup, ndn)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const int64_t dim = s.dup * s.ddn;
+    double nn = dot(dim, phi, phi);
+    *b0sq = nn;
+    if (nn == 0.0 || max_steps < 1) { sector_free(&s); return 0; }
+    double *V = malloc(sizeof(double) * dim * (size_t)(max_steps + 1));
+    double *w = malloc(sizeof(double) * dim);
+    double *c = malloc(sizeof(double) * (max_steps + 1));
+    double *beta = malloc(sizeof(double) * max_steps);
+    if (!V || !w || !c || !beta) {
+        free(V); free(w); free(c); free(beta);
+        sector_free(&s);
+        return -2;
+    }
+    double nrm = sqrt(nn);
+    for (int64_t i = 0; i < dim; i++) V[i] = phi[i] / nrm;
+    double amax = 0.0;
+    int M = 0;
+    for (int n = 0; n < max_steps; n++) {
+        const double *v = V + (size_t)n * dim;
+        const double *vp = n > 0 ? V + (size_t)(n - 1) * dim : NULL;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < dim; i++) w[i] = hv_row(&s, t, U, v, i);
+        double bprev = (n == 0) ? 0.0 : beta[n - 1];
+        if (vp) for (int64_t i = 0; i < dim; i++) w[i] -= bprev * vp[i];
+        double al = dot(dim, v, w);
+        for (int64_t i = 0; i < dim; i++) w[i] -= al * v[i];
+        for (int pass = 0; pass < 2; pass++) {
+#pragma omp parallel for schedule(dynamic)
+            for (int k = 0; k <= n; k++) c[k] = dot(dim, V + (size_t)k * dim, w);
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < dim; i++) {
+                double x = w[i];
+                for (int k = 0; k <= n; k++) x -= c[k] * V[(size_t)k * dim + i];
+                w[i] = x;
+            }
+        }
+        double b = sqrt(dot(dim, w, w));
+        a[n] = al;
+        beta[n] = b;
+        if (fabs(al) > amax) amax = fabs(al);
+        M = n + 1;
+        if (b < btol * (amax > 0 ? amax : 1.0)) break;
+        if (n + 1 < max_steps) {
+            double *vn = V + (size_t)(n + 1) * dim;
+            for (int64_t i = 0; i < dim; i++) vn[i] = w[i] / b;
+        }
+    }
+    for (int n = 0; n + 1 < M; n++) b2[n] = beta[n] * beta[n];
+    free(V); free(w); free(c); free(beta);
+    sector_free(&s);
+    return M;
+}
