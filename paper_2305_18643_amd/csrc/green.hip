@@ -12,7 +12,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "lanczos_device.h"
+#include "lanczos_step.h"
 
 namespace qcm {
 
@@ -180,6 +183,188 @@ int green_eval(const double *coef, const int32_t *len, int n, int maxs, int nz, 
     return QCM_OK;
 }
 
+// ---------------------------------------------------------------- full reorthogonalisation
+// A test device (the paper's recurrence tolerates the loss of orthogonality):
+// every chain keeps all its vectors, hist[k][c][dim] (k = floor, c = chain),
+// and after w = H v_n - beta' v_{n-1} - alpha_n v_n the components of w along
+// v_0..v_n are removed twice by classical Gram-Schmidt (all coefficients
+// <v_k, w> from fixed-order two-level sums, then one subtraction per element
+// summed in floor order, rounded once); they are not entered in T.  Then
+// beta_n = |w| and v_{n+1} = w / beta_n.
+
+constexpr int kFrPer = kChunk / 256;   // elements of a chunk per thread
+constexpr size_t kFrHistBytes = (size_t)16 << 30;   // history of one group of chains
+
+// w = w - alpha_n v, rounded once (grid: chunks x chains)
+template <typename T>
+__global__ void __launch_bounds__(256) k_fr_alpha(T *__restrict__ w, const T *__restrict__ v,
+                                                  int64_t dim, ChainState cs, int n) {
+    const int64_t c = blockIdx.y, base = (int64_t)blockIdx.x * kChunk;
+    const double a = cs.alpha[c * cs.maxs + n];
+    T *wc = w + c * dim;
+    const T *vc = v + c * dim;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = base + k;
+        if (i < dim) wc[i] = (T)fma(-a, (double)vc[i], (double)wc[i]);
+    }
+}
+
+// partial <v_k, w> of one chunk for k = 0..nk-1: part[(c * kmax + k) * nchunks + chunk]
+template <typename T>
+__global__ void __launch_bounds__(256) k_fr_dots(const T *__restrict__ hist, const T *__restrict__ w,
+                                                 int64_t dim, int nvec, int nk, int kmax,
+                                                 int nchunks, double *__restrict__ part) {
+    __shared__ double sh[256];
+    const int64_t c = blockIdx.y, ch = blockIdx.x, base = ch * kChunk;
+    double x[kFrPer];
+#pragma unroll
+    for (int j = 0; j < kFrPer; ++j) {
+        const int64_t i = base + threadIdx.x + 256 * j;
+        x[j] = i < dim ? (double)w[c * dim + i] : 0.0;
+    }
+    for (int k = 0; k < nk; ++k) {
+        const T *h = hist + ((int64_t)k * nvec + c) * dim;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kFrPer; ++j) {
+            const int64_t i = base + threadIdx.x + 256 * j;
+            if (i < dim) acc = fma((double)h[i], x[j], acc);
+        }
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) part[((int64_t)c * kmax + k) * nchunks + ch] = t;
+    }
+}
+
+// coef[c * kmax + k] = sum over the chunks of the partials (fixed order)
+__global__ void __launch_bounds__(256) k_fr_coef(const double *__restrict__ part, int kmax,
+                                                 int nchunks, double *__restrict__ coef) {
+    __shared__ double sh[256];
+    const int64_t k = blockIdx.x, c = blockIdx.y;
+    const double s = block_sum(strided_sum(part + (c * kmax + k) * nchunks, nchunks), sh);
+    if (threadIdx.x == 0) coef[c * kmax + k] = s;
+}
+
+// w = w - sum_k coef_k v_k (floors in order, FP64, rounded once)
+template <typename T>
+__global__ void __launch_bounds__(256) k_fr_sub(const T *__restrict__ hist, T *__restrict__ w,
+                                                int64_t dim, int nvec, int nk, int kmax,
+                                                const double *__restrict__ coef) {
+    const int64_t c = blockIdx.y, base = (int64_t)blockIdx.x * kChunk;
+    double x[kFrPer];
+#pragma unroll
+    for (int j = 0; j < kFrPer; ++j) {
+        const int64_t i = base + threadIdx.x + 256 * j;
+        x[j] = i < dim ? (double)w[c * dim + i] : 0.0;
+    }
+    for (int k = 0; k < nk; ++k) {
+        const double ck = coef[c * kmax + k];
+        const T *h = hist + ((int64_t)k * nvec + c) * dim;
+#pragma unroll
+        for (int j = 0; j < kFrPer; ++j) {
+            const int64_t i = base + threadIdx.x + 256 * j;
+            if (i < dim) x[j] = fma(-ck, (double)h[i], x[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kFrPer; ++j) {
+        const int64_t i = base + threadIdx.x + 256 * j;
+        if (i < dim) w[c * dim + i] = (T)x[j];
+    }
+}
+
+// partial |w|^2 of one chunk into pn[c * 3 * nchunks + chunk]
+template <typename T>
+__global__ void __launch_bounds__(256) k_fr_norm(const T *__restrict__ w, int64_t dim, int nchunks,
+                                                 double *__restrict__ pn) {
+    __shared__ double sh[256];
+    const int64_t c = blockIdx.y, ch = blockIdx.x, base = ch * kChunk;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = base + k;
+        if (i < dim) {
+            const double x = (double)w[c * dim + i];
+            acc = fma(x, x, acc);
+        }
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) pn[c * 3 * nchunks + ch] = t;
+}
+
+// v_{n+1} = w / beta_n (zero once the chain has stopped)
+template <typename T>
+__global__ void __launch_bounds__(256) k_fr_store(const T *__restrict__ w, T *__restrict__ out,
+                                                  int64_t dim, ChainState cs) {
+    const int64_t c = blockIdx.y, base = (int64_t)blockIdx.x * kChunk;
+    const double s = cs.inv[c];
+    for (int k = threadIdx.x; k < kChunk; k += 256) {
+        const int64_t i = base + k;
+        if (i < dim) out[c * dim + i] = (T)((double)w[c * dim + i] * s);
+    }
+}
+
+// Chains of a group that fit the history cap at once.
+int fr_group_size(int npairs, int maxs, int64_t dim, int prec) {
+    const size_t per = (size_t)(maxs + 1) * (size_t)dim * (prec == QCM_FP64 ? 8 : 4);
+    int64_t g = per > 0 ? (int64_t)(kFrHistBytes / per) : npairs;
+    if (g < 1) g = 1;
+    if (g > npairs) g = npairs;
+    return (int)g;
+}
+
+struct FrBufs {
+    void *hist;
+    double *part, *coef;
+};
+
+int fr_carve(Carver &cv, int prec, int ng, int maxs, int64_t dim, FrBufs *b) {
+    const size_t s = prec == QCM_FP64 ? 8 : 4;
+    const int64_t nch = (int64_t)ceil_div(dim, kChunk);
+    b->hist = cv.take<char>((size_t)(maxs + 1) * ng * dim * s);
+    b->part = cv.take<double>((size_t)ng * (maxs + 1) * (nch > 0 ? nch : 1));
+    b->coef = cv.take<double>((size_t)ng * (maxs + 1));
+    return QCM_OK;
+}
+
+// One step n of the group: w = H v_n - beta' v_{n-1}, alpha_n, the two
+// Gram-Schmidt passes, beta_n, v_{n+1} into hist[n + 1].
+template <typename T>
+int fr_step_t(Engine &e, const FrBufs &b, int n, hipStream_t s) {
+    const int64_t dim = e.dim;
+    const int nvec = e.nvec, kmax = e.maxs + 1, nch = e.nchunks;
+    T *hist = (T *)b.hist;
+    T *w = (T *)e.vbuf[2];
+    T *v = hist + (int64_t)n * nvec * dim;
+    T *vp = n > 0 ? hist + (int64_t)(n - 1) * nvec * dim : v;
+    BGroup g = engine_group(e, n);
+    g.v = v;
+    g.vp = vp;
+    g.w = w;
+    g.na = e.nchunks;
+    g.reorth = 0;
+    const OneSrc src{g};
+    const dim3 gc((unsigned)nch, (unsigned)nvec);
+    QCM_TRY(hv_launch(e.op, e.prec, v, w, nvec, s));
+    ks_sub_prev<T, OneSrc><<<(unsigned)(nvec * nch), 256, 0, s>>>(src);
+    ks_finish<OneSrc><<<nvec, 256, 0, s>>>(src, 0);
+    k_fr_alpha<T><<<gc, 256, 0, s>>>(w, v, dim, e.cs, n);
+    for (int pass = 0; pass < 2; ++pass) {
+        k_fr_dots<T><<<gc, 256, 0, s>>>(hist, w, dim, nvec, n + 1, kmax, nch, b.part);
+        k_fr_coef<<<dim3((unsigned)(n + 1), (unsigned)nvec), 256, 0, s>>>(b.part, kmax, nch, b.coef);
+        k_fr_sub<T><<<gc, 256, 0, s>>>(hist, w, dim, nvec, n + 1, kmax, b.coef);
+    }
+    k_fr_norm<T><<<gc, 256, 0, s>>>(w, dim, nch, e.pn);
+    ks_finish<OneSrc><<<nvec, 256, 0, s>>>(src, 1);
+    if (n + 1 < e.maxs)
+        k_fr_store<T><<<gc, 256, 0, s>>>(w, hist + (int64_t)(n + 1) * nvec * dim, dim, e.cs);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int fr_step(Engine &e, const FrBufs &b, int n, hipStream_t s) {
+    if (e.prec == QCM_FP64) return fr_step_t<double>(e, b, n, s);
+    return fr_step_t<float>(e, b, n, s);
+}
+
 }  // namespace qcm
 
 using namespace qcm;
@@ -210,8 +395,8 @@ static int green_common(const qcm_model *m, const qcm_basis *gs, int n, int stri
 
 static int green_part(const qcm_model *m, const qcm_basis *gs, const qcm_green_opts *o, int nup2,
                       const GreenCommon &c, Carver &cv, hipStream_t s, SpinTables *up2,
-                      HvOp *op, Engine *e) {
-    const int npairs = o->n_orb * (o->n_orb + 1) / 2;
+                      HvOp *op, Engine *e, FrBufs *fr) {
+    int npairs = o->n_orb * (o->n_orb + 1) / 2;
     QCM_TRY(build_spin_tables(m->L, nup2, cv, up2, s));
     op->md = c.md;
     op->up = *up2;
@@ -221,6 +406,11 @@ static int green_part(const qcm_model *m, const qcm_basis *gs, const qcm_green_o
     QCM_TRY(build_hop_tables(c.md, *up2, cv, &op->hu, s, count_bonds(m)));
     op->split = 0;
     if (split_applies(m, nup2, up2->d, op->dn.d)) QCM_TRY(split_prepare(m, *op, cv, s));
+    if (o->reorth == 2) {
+        // chains in groups whose history fits the cap
+        npairs = fr_group_size(npairs, o->max_steps, op->dim, o->prec);
+        QCM_TRY(fr_carve(cv, o->prec, npairs, o->max_steps, op->dim, fr));
+    }
     QCM_TRY(engine_init(*e, *op, o->prec, npairs, o->max_steps, o->btol, o->reorth, cv));
     return QCM_OK;
 }
@@ -239,7 +429,8 @@ static int green_bytes(const qcm_model *m, const qcm_basis *gs, const qcm_green_
         SpinTables up2;
         HvOp op;
         Engine e;
-        QCM_TRY(green_part(m, gs, o, nup2, c, p, nullptr, &up2, &op, &e));
+        FrBufs fr;
+        QCM_TRY(green_part(m, gs, o, nup2, c, p, nullptr, &up2, &op, &e, &fr));
         if (p.off > end) end = p.off;
     }
     *need = end + 256;
@@ -265,6 +456,7 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
     if (o->max_steps < 1) return fail(QCM_EARG, "qcm_green_cf: max_steps < 1");
     if (o->prec != QCM_FP64 && o->prec != QCM_FP32V)
         return fail(QCM_EARG, "qcm_green_cf: bad prec");
+    if (o->reorth < 0 || o->reorth > 2) return fail(QCM_EARG, "qcm_green_cf: reorth must be 0, 1 or 2");
     if (n_z < 0 || (n_z > 0 && (!h_z || (!d_G && d_ws))))
         return fail(QCM_EARG, "qcm_green_cf: bad frequency arguments");
     size_t need = 0;
@@ -317,7 +509,37 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         SpinTables up2;
         HvOp op;
         Engine e;
-        QCM_TRY(green_part(m, gs, o, nup2, c, cv, s, &up2, &op, &e));
+        FrBufs fr{};
+        QCM_TRY(green_part(m, gs, o, nup2, c, cv, s, &up2, &op, &e, &fr));
+        if (o->reorth == 2) {
+            // groups of e.nvec chains, each with its full history
+            for (int g0 = 0; g0 < npairs; g0 += e.nvec) {
+                const int ng = std::min(e.nvec, npairs - g0);
+                Engine eg = e;
+                eg.nvec = ng;
+                eg.cs.maxs = maxs;
+                QCM_TRY(engine_reset(eg, s));
+                QCM_TRY(apply_ops_raw(eg.prec, d_gs, gs->d_up, upg, up2, eg.dim, part,
+                                      ops_d + 2 * g0, ng, fr.hist, eg.nchunks, eg.partial, s));
+                eg.vbuf[eg.iv] = fr.hist;
+                QCM_TRY(engine_normalize_from_partials(eg, s));
+                std::vector<int32_t> done(ng);
+                for (int step = 0; step < maxs; ++step) {
+                    QCM_TRY(fr_step(eg, fr, step, s));
+                    if ((step + 1) % 32 == 0 && step + 1 < maxs) {
+                        QCM_HIP(hipMemcpyAsync(done.data(), eg.cs.done, sizeof(int32_t) * ng,
+                                               hipMemcpyDeviceToHost, s));
+                        QCM_HIP(hipStreamSynchronize(s));
+                        bool all = true;
+                        for (int k = 0; k < ng; ++k) all = all && done[k];
+                        if (all) break;
+                    }
+                }
+                QCM_TRY(green_store(&eg, ng, part, coef + (size_t)g0 * 2 * stride, lenv + 2 * g0,
+                                    stride, s));
+            }
+            continue;
+        }
         QCM_TRY(engine_reset(e, s));
         QCM_TRY(apply_ops_launch(e, d_gs, gs->d_up, upg, up2, part, ops_d, s));
         QCM_TRY(engine_normalize_from_partials(e, s));

@@ -6,10 +6,11 @@
 //   pass A (inside rows, K_up, and the diagonal):  W = V K_up^T + D o V
 //     Persistent workgroups stage one whole row in LDS and gather the
 //     neighbour values from it.  The hops of an up string are the same for
-//     every row: they come from a packed slot-major table read through the
-//     caches (1.2 MB for the 4x4 sector, resident in each XCD's L2), with the
+//     every row: they come from a table of 64-string tiles read through the
+//     caches (1.6 MB for the 4x4 sector, resident in each XCD's L2), with the
 //     LDS byte offset of the neighbour, its coefficient index and its sign in
-//     one 32-bit word.
+//     one 32-bit word; a wave takes one tile at a time with a wave-uniform
+//     hop count.
 //   pass B (row mixing, K_dn):  W += K_dn V
 //     The columns are cut into slabs; all rows of one slab are produced by the
 //     workgroups of one XCD, so most neighbour segments a slab needs (about
@@ -27,65 +28,75 @@
 
 namespace qcm {
 
-// Largest row length of the two-pass path: an LDS byte offset col * 8 must
-// fit the 17 bits the packed in-row entry gives it.
+// Largest row length of the two-pass path: an LDS byte offset col * 8 (and
+// the zero slot's 8 d_up) must fit the 17 bits the in-row entry gives it.
 constexpr int64_t kSplitMaxUp = 16384;
 constexpr int64_t kSplitMinUp = 4096;
 
 // ---------------------------------------------------------------- kernels
 
-// Packed in-row entry of hop s of up string i, from the hopping list's packed
-// form (column | coefficient index << 16):
+// In-row entry of a hop, from the hopping list's packed form (column |
+// coefficient index << 16):
 //   bits 0..16  LDS byte offset of the neighbour in an FP64 row (col * 8)
 //   bits 17..30 index of +-t_ab in the model's coefficient table
 //   bit  31     sign of the coefficient (the index's parity)
-__global__ void k_pack_inrow(int64_t n, const uint32_t *__restrict__ pk,
-                             uint32_t *__restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const uint32_t p = pk[e], col = p & 0xffffu, idx = p >> 16;
-    out[e] = (col << 3) | (idx << 17) | ((idx & 1u) << 31);
+// A padding entry holds the offset 8 d_up (the zero slot after the row) and
+// index 0.  Block = tile of 64 up strings, thread = lane.
+__global__ void k_pack_tiles(int64_t d, const int32_t *__restrict__ nh,
+                             const uint32_t *__restrict__ pk, const int32_t *__restrict__ tnt,
+                             const int32_t *__restrict__ toff, uint32_t *__restrict__ out) {
+    const int tt = blockIdx.x, lane = threadIdx.x;
+    const int64_t i = (int64_t)tt * 64 + lane;
+    const int n = i < d ? nh[i] : 0;
+    const uint32_t pad = (uint32_t)(8 * d);
+    for (int s = 0; s < tnt[tt]; ++s) {
+        uint32_t e = pad;
+        if (s < n) {
+            const uint32_t p = pk[(int64_t)s * d + i], col = p & 0xffffu, idx = p >> 16;
+            e = (col << 3) | (idx << 17) | ((idx & 1u) << 31);
+        }
+        out[toff[tt] + s * 64 + lane] = e;
+    }
 }
 
 // Pass A: one row of V in LDS at a time (persistent grid, one 1024-thread
-// workgroup per CU, the next row prefetched in registers), one thread per up
-// string.  The row sits at LDS address 0, so the masked entry is the gather
-// address (halved for FP32 rows).  When every bond has the same t (UT), a
-// coefficient is +-t: the entry's sign bit flips the sign of the neighbour
-// value and the coefficient table is not read.  W = V K_up^T + D o V, written
-// once.
+// workgroup per CU, the next row prefetched in registers).  A wave takes one
+// tile of 64 up strings at a time: the tile's hop count is wave-uniform and
+// its entries are tile-major, so every lane runs the same hop loop with no
+// masking and the entry loads are one contiguous 256-byte load per slot from
+// a wave-uniform base; slots past a lane's own hops read the zero slot.  Eight
+// entries are loaded, then eight neighbours gathered from LDS, then summed.
+// The row sits at LDS address 0, so the masked entry is the gather address
+// (halved for FP32 rows).  When every bond has the same t (UT), a coefficient
+// is +-t: the entry's sign bit flips the sign of the neighbour value and the
+// coefficient table is not read.  W = V K_up^T + D o V, written once; the
+// per-element sum is the diagonal term, then the hops in list order.
+constexpr int kTileChunk = 8;
 template <typename T, int KS, bool UT>
-__global__ void __launch_bounds__(1024) k_hv_inrow_pk(
+__global__ void __launch_bounds__(1024) k_hv_inrow_tile(
     const int64_t d_up, const int64_t d_dn, const uint32_t *__restrict__ su,
-    const double *__restrict__ eu, const int32_t *__restrict__ nhu,
-    const uint32_t *__restrict__ pin, const double *__restrict__ ctab_g, const int nctab,
-    const uint32_t *__restrict__ sd, const double *__restrict__ ed,
-    const double *__restrict__ ulut_g, const int nbytes, const double u_uniform, const double tu,
-    const T *__restrict__ v, T *__restrict__ w) {
+    const double *__restrict__ eu, const int ntile, const int32_t *__restrict__ tnt,
+    const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent,
+    const double *__restrict__ ctab_g, const int nctab, const uint32_t *__restrict__ sd,
+    const double *__restrict__ ed, const double *__restrict__ ulut_g, const int nbytes,
+    const double u_uniform, const double tu, const T *__restrict__ v, T *__restrict__ w) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int NT = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = NT >> 6;
     const int dup = (int)d_up;
     T *row = reinterpret_cast<T *>(smem);
-    const size_t row_bytes = ((size_t)sizeof(T) * dup + 15) & ~(size_t)15;
-    double *ct = reinterpret_cast<double *>(smem + row_bytes);
+    // zero slot: 64 bytes right after the row (a padding entry's offset 8 d_up,
+    // halved for FP32 rows, points there)
+    const size_t zero_at = sizeof(T) * (size_t)dup;
+    const size_t tab_at = (zero_at + 64 + 15) & ~(size_t)15;
+    double *ct = reinterpret_cast<double *>(smem + tab_at);
     double *ulut = ct + ((nctab + 1) & ~1);
+    if (tid < 16) reinterpret_cast<uint32_t *>(smem + zero_at)[tid] = 0u;
     const int nlut = u_uniform >= 0.0 ? 0 : nbytes * 256;
     for (int k = tid; k < nlut; k += NT) ulut[k] = ulut_g[k];
     if (!UT)
         for (int k = tid; k < nctab; k += NT) ct[k] = ctab_g[k];
     typedef __attribute__((address_space(3))) const T lds_t;
-    auto term = [&](uint32_t p, double acc) -> double {
-        // the row starts at LDS address 0: the masked entry is the address
-        const uint32_t off = sizeof(T) == 8 ? (p & 0x1ffffu) : ((p & 0x1ffffu) >> 1);
-        const double x = (double)*(lds_t *)(size_t)off;
-        if constexpr (UT) {
-            const double xs = __hiloint2double(__double2hiint(x) ^ (int)(p & 0x80000000u),
-                                               __double2loint(x));
-            return fma(tu, xs, acc);
-        } else {
-            return fma(ct[(p >> 17) & 0x3fffu], x, acc);
-        }
-    };
     const int64_t vb = (int64_t)blockIdx.y * d_up * d_dn;
     const T *vv = v + vb;
     T *ww = w + vb;
@@ -119,34 +130,45 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_pk(
         const uint32_t bd = sd[r];
         const double edn = ed[r];
         T *wrow = ww + r * d_up;
-        for (int iu = tid; iu < dup; iu += NT) {
-            const uint32_t dbl = su[iu] & bd;
-            double diag = eu[iu] + edn;
-            if (u_uniform >= 0.0) {
-                diag += u_uniform * (double)__popc(dbl);
-            } else {
-                for (int byte = 0; byte < nbytes; ++byte)
-                    diag += ulut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
+        for (int tt = wave; tt < ntile; tt += nwave) {
+            const int iu = tt * 64 + lane;
+            const int nt = __builtin_amdgcn_readfirstlane(tnt[tt]);
+            const uint32_t *eb = ent + __builtin_amdgcn_readfirstlane(toff[tt]) + lane;
+            const bool in = iu < dup;
+            double acc = 0.0;
+            if (in) {
+                const uint32_t dbl = su[iu] & bd;
+                double diag = eu[iu] + edn;
+                if (u_uniform >= 0.0) {
+                    diag += u_uniform * (double)__popc(dbl);
+                } else {
+                    for (int byte = 0; byte < nbytes; ++byte)
+                        diag += ulut[byte * 256 + ((dbl >> (8 * byte)) & 255u)];
+                }
+                acc = diag * (double)row[iu];
             }
-            double acc = diag * (double)row[iu];
-            const int nh = nhu[iu];
-            // table loads as a wave-uniform slot base plus the lane's byte offset
-            const uint32_t ob = (uint32_t)iu * 4u;
-            auto at = [&](const uint32_t *base) {
-                return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(base) + ob);
-            };
-            const uint32_t *slot = pin;
-            int s = 0;
-            for (; s + 4 <= nh; s += 4, slot += 4 * d_up) {
-                const uint32_t p0 = at(slot), p1 = at(slot + d_up);
-                const uint32_t p2 = at(slot + 2 * d_up), p3 = at(slot + 3 * d_up);
-                acc = term(p0, acc);
-                acc = term(p1, acc);
-                acc = term(p2, acc);
-                acc = term(p3, acc);
+            for (int s = 0; s < nt; s += kTileChunk) {
+                uint32_t p[kTileChunk];
+#pragma unroll
+                for (int u = 0; u < kTileChunk; ++u) p[u] = eb[(s + u) * 64];
+                double x[kTileChunk];
+#pragma unroll
+                for (int u = 0; u < kTileChunk; ++u) {
+                    const uint32_t off = sizeof(T) == 8 ? (p[u] & 0x1ffffu) : ((p[u] & 0x1ffffu) >> 1);
+                    x[u] = (double)*(lds_t *)(size_t)off;
+                }
+#pragma unroll
+                for (int u = 0; u < kTileChunk; ++u) {
+                    if constexpr (UT) {
+                        const double xs = __hiloint2double(
+                            __double2hiint(x[u]) ^ (int)(p[u] & 0x80000000u), __double2loint(x[u]));
+                        acc = fma(tu, xs, acc);
+                    } else {
+                        acc = fma(ct[(p[u] >> 17) & 0x3fffu], x[u], acc);
+                    }
+                }
             }
-            for (; s < nh; ++s, slot += d_up) acc = term(at(slot), acc);
-            __builtin_nontemporal_store((T)acc, wrow + iu);
+            if (in) __builtin_nontemporal_store((T)acc, wrow + iu);
         }
     }
 }
@@ -308,7 +330,8 @@ int build_row_offsets(HopTables &ht, int64_t d_up, Carver &cv, hipStream_t s) {
 
 static size_t inrow_lds_bytes(const HvOp &op, int prec) {
     const size_t es = prec == QCM_FP64 ? 8 : 4;
-    const size_t row = (es * (size_t)op.up.d + 15) & ~(size_t)15;
+    // the row, the 64-byte zero slot, then the coefficient and U tables
+    const size_t row = (es * (size_t)op.up.d + 64 + 15) & ~(size_t)15;
     const size_t nct = (size_t)((2 * op.md.nbond + 1) & ~1);
     const size_t lut = op.md.u_uniform >= 0.0 ? 0 : 256 * (size_t)op.md.nbytes;
     return row + 8 * (nct + lut);
@@ -328,15 +351,15 @@ static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipS
 #define QCM_PK(KS_)                                                                            \
     if (ks <= KS_) {                                                                           \
         if (op.md.t_is_uniform)                                                                \
-            k_hv_inrow_pk<T, KS_, true><<<gp, 1024, lds, s>>>(                                 \
-                d_up, d_dn, op.up.states, op.hu.ediag, op.hu.nh, op.inrow_pk, op.md.ctab, nctab, \
-                op.dn.states, op.hd.ediag, op.md.ulut, op.md.nbytes, op.md.u_uniform,          \
-                op.md.t_uniform, (const T *)v, (T *)w);                                        \
+            k_hv_inrow_tile<T, KS_, true><<<gp, 1024, lds, s>>>(                               \
+                d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off,      \
+                op.tile_ent, op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut,         \
+                op.md.nbytes, op.md.u_uniform, op.md.t_uniform, (const T *)v, (T *)w);        \
         else                                                                                   \
-            k_hv_inrow_pk<T, KS_, false><<<gp, 1024, lds, s>>>(                                \
-                d_up, d_dn, op.up.states, op.hu.ediag, op.hu.nh, op.inrow_pk, op.md.ctab, nctab, \
-                op.dn.states, op.hd.ediag, op.md.ulut, op.md.nbytes, op.md.u_uniform,          \
-                op.md.t_uniform, (const T *)v, (T *)w);                                        \
+            k_hv_inrow_tile<T, KS_, false><<<gp, 1024, lds, s>>>(                              \
+                d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off,      \
+                op.tile_ent, op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut,         \
+                op.md.nbytes, op.md.u_uniform, op.md.t_uniform, (const T *)v, (T *)w);        \
     } else
     QCM_PK(4) QCM_PK(8) QCM_PK(12) QCM_PK(16) { return fail(QCM_EARG, "in-row pass: row too long"); }
 #undef QCM_PK
@@ -388,10 +411,11 @@ int64_t split_pa_count(const HvOp &op) {
 bool split_applies(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn) {
     (void)n_up;
     if (d_up < kSplitMinUp || d_up > kSplitMaxUp || d_dn < 1) return false;
-    // the FP64 row, the coefficient table and the U lookup table in LDS
+    // the FP64 row, its zero slot, the coefficient table and the U lookup
+    // table in LDS
     const size_t nct = (size_t)((2 * count_bonds(m) + 1) & ~1);
     const size_t lut = 256 * (size_t)((m->L + 7) / 8);
-    return 8 * (size_t)d_up + 16 + 8 * (nct + lut) <= 160 * 1024;
+    return 8 * (size_t)d_up + 64 + 16 + 8 * (nct + lut) <= 160 * 1024;
 }
 
 int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
@@ -399,8 +423,15 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
     // null pointers and must take the same path as the real one
     if (op.hu.rowmajor || op.up.d > kSplitMaxUp)
         return fail(QCM_EARG, "two-pass product: no packed up hops for this sector");
-    const size_t n = (size_t)op.hu.width * op.up.d;
-    op.inrow_pk = cv.take<uint32_t>(n);
+    // the padding entry's offset 8 d_up must fit the entry's 17 offset bits
+    if (8 * op.up.d >= ((int64_t)1 << 17))
+        return fail(QCM_EARG, "two-pass product: row of %lld strings too long", (long long)op.up.d);
+    const int64_t du = op.up.d;
+    op.ntile = (int32_t)((du + 63) / 64);
+    const int wr = (op.hu.width + kTileChunk - 1) / kTileChunk * kTileChunk;
+    op.tile_ent = cv.take<uint32_t>((size_t)op.ntile * wr * 64);
+    op.tile_nt = cv.take<int32_t>(op.ntile);
+    op.tile_off = cv.take<int32_t>(op.ntile);
     QCM_TRY(build_hop_tables(op.md, op.dn, cv, &op.hd_rm, s, count_bonds(m), 1));
     QCM_TRY(build_row_offsets(op.hd_rm, op.up.d, cv, s));
     // rows grouped by the popcount of the high half of the down string, so
@@ -424,8 +455,26 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
         QCM_HIP(hipStreamSynchronize(s));   // ord is pageable and about to go
     }
     if (cv.base) {
-        k_pack_inrow<<<ceil_div((int64_t)n, 256), 256, 0, s>>>((int64_t)n, op.hu.pk, op.inrow_pk);
+        // each tile's slot count from the hop counts (read back once)
+        std::vector<int32_t> nh(du), tnt(op.ntile), toff(op.ntile);
+        QCM_HIP(hipMemcpyAsync(nh.data(), op.hu.nh, sizeof(int32_t) * du, hipMemcpyDeviceToHost, s));
+        QCM_HIP(hipStreamSynchronize(s));
+        int32_t o = 0;
+        for (int tt = 0; tt < op.ntile; ++tt) {
+            int mx = 0;
+            for (int l = 0; l < 64 && tt * 64 + l < du; ++l) mx = std::max(mx, nh[tt * 64 + l]);
+            tnt[tt] = (mx + kTileChunk - 1) / kTileChunk * kTileChunk;
+            toff[tt] = o;
+            o += tnt[tt] * 64;
+        }
+        QCM_HIP(hipMemcpyAsync(op.tile_nt, tnt.data(), sizeof(int32_t) * op.ntile,
+                               hipMemcpyHostToDevice, s));
+        QCM_HIP(hipMemcpyAsync(op.tile_off, toff.data(), sizeof(int32_t) * op.ntile,
+                               hipMemcpyHostToDevice, s));
+        k_pack_tiles<<<op.ntile, 64, 0, s>>>(du, op.hu.nh, op.hu.pk, op.tile_nt, op.tile_off,
+                                              op.tile_ent);
         QCM_LAUNCH_CHECK();
+        QCM_HIP(hipStreamSynchronize(s));   // tnt and toff are pageable and about to go
     }
     op.split = 1;
     return QCM_OK;

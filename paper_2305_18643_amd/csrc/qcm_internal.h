@@ -153,7 +153,13 @@ struct HvOp {
     int64_t dim;
     // two-pass path for long rows (see hv_split.hip); used when split != 0
     int split = 0;
-    uint32_t *inrow_pk = nullptr; // up hops packed for the in-row pass (LDS offset | index | sign)
+    // in-row pass by 64-column tiles: the packed up hops (LDS offset | coefficient
+    // index | sign) of tile t at tile_ent[tile_off[t] + s * 64 + lane], s <
+    // tile_nt[t] (the tile's largest hop count rounded up to 8, padded with
+    // entries that read a zero slot)
+    uint32_t *tile_ent = nullptr;
+    int32_t *tile_nt = nullptr, *tile_off = nullptr;
+    int32_t ntile = 0;
     HopTables hd_rm;              // down hops, row-major, with neighbour offsets
     int32_t *row_order = nullptr; // rows of V in the order the row-mixing pass takes them
     // a symmetry-adapted sector's stored matrix; used (FP64 only) when csr.rowptr != nullptr

@@ -245,6 +245,57 @@ def test_green_function(q, m, steps):
             p += 1
 
 
+# Full reorthogonalisation (reorth = 2, a test device): truncated chains are
+# the recurrence of exact arithmetic, so from the same start vectors the
+# coefficients agree floor by floor and G agrees far below 1e-4, also before
+# the Krylov space is exhausted.  Exhausted chains give the dense Lehmann sum.
+# FP32 vectors: the storage rounding (relative 6e-8 per stored vector) is
+# amplified by the truncated continued fraction (1.5e-4 measured on the
+# 30-floor case); the error is printed and bounded at 2e-3.
+@pytest.mark.parametrize("m,steps,exhaust", [(synth.random_model(43, 6, 3, 3), 30, False),
+                                             (synth.random_model(301, 6, 3, 2), 40, False),
+                                             (synth.random_model(42, 5, 2, 3), 120, True)],
+                         ids=["rand6_30", "rand6b_40", "rand5_exhausted"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32v"])
+def test_green_full_reorth(q, m, steps, exhaust, prec):
+    torch = _torch()
+    print(f"green full reorth {m.name} {steps} {prec}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True, nthreads=1)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    orbs = list(range(m.L))
+    g = q.green_cf(m, b, psi, ro["e0"], orbs, Z64, max_steps=steps, reorth=2, prec=prec)
+    ch = oracle.green_cf(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, max_steps=steps,
+                         full_reorth=True, nthreads=1)
+    Go = cf.green_matrix(ch, len(orbs), Z64, ro["e0"])
+    G = g["G"].cpu().numpy()
+    err = np.abs(G - Go).max()
+    print(f"  max |dG| = {err:.2e}")
+    if exhaust:
+        from oracle import dense
+        Gd = dense.lehmann_green(m.t, m.U, m.nup, m.ndn, orbs, Z64, psi=ro["psi"], e0=ro["e0"])
+        print(f"  max |dG| vs Lehmann = {np.abs(G - Gd).max():.2e}")
+        assert np.abs(G - Gd).max() <= (1e-9 if prec == "fp64" else 2e-3)
+    assert err <= (1e-9 if prec == "fp64" else 2e-3)
+    M = g["coef"].shape[2] // 2
+    p = 0
+    worst = 0.0
+    for i in range(len(orbs)):
+        for j in range(i, len(orbs)):
+            for part in (0, 1):
+                b0, a, b2 = ch[(i, j, part)]
+                co = g["coef"][p, part]
+                assert g["len"][p, part] == len(a)
+                assert abs(co[0] - b0) < (1e-12 if prec == "fp64" else 1e-6)
+                # late floors are sensitive once Ritz values converge (G is
+                # not): the first floors one by one
+                k = min(len(a), 12 if prec == "fp64" else 4)
+                worst = max(worst, np.abs(co[1:1 + k] - a[:k]).max() / max(1.0, np.abs(a).max()))
+            p += 1
+    print(f"  first floors: max |da| / max |a| = {worst:.2e}")
+    assert worst <= (1e-9 if prec == "fp64" else 1e-5)
+
+
 def test_cpt_2x2(q):
     torch = _torch()
     m = synth.plaquette_2x2()
@@ -260,7 +311,11 @@ def test_cpt_2x2(q):
 
 def test_hv_plan_matches_hv(q):
     torch = _torch()
-    for m in (synth.cluster_3x4(), synth.random_model(102, 11, 3, 6)):
+    # short rows (fused product kernel and the one-row-per-block kernel) and
+    # long rows (the two-pass path, uniform and per-bond t)
+    for m in (synth.cluster_3x4(), synth.random_model(102, 11, 3, 6),
+              synth.rect_cluster(4, 4, U=8.0, mu=4.0, nup=8, ndn=1, name="4x4r"),
+              synth.rect_cluster(5, 3, tp=0.3, U=5.0, mu=2.5, nup=7, ndn=2, name="5x3r")):
         b = q.sector_basis(m.L, m.nup, m.ndn)
         for dt, prec in ((torch.float64, "fp64"), (torch.float32, "fp32v")):
             v = (torch.rand(2 * b.dim, dtype=torch.float64, device="cuda") * 2 - 1).to(dt)
