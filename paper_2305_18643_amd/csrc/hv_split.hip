@@ -220,7 +220,9 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t p = blockIdx.x;
     const int64_t lg = (p & 7) * per + (p >> 3);  // XCD p % 8 takes a contiguous range
     if (lg >= total) {
-        if (SP && threadIdx.x == 0) sp.pa[(int64_t)blockIdx.y * gridDim.x + p] = 0.0;
+        if (SP && threadIdx.x == 0)
+            for (int k = 0; k < (sp.reorth ? 5 : 3); ++k)
+                sp.pa[k * sp.pstride + (int64_t)blockIdx.y * gridDim.x + p] = 0.0;
         return;
     }
     const int64_t slab = lg / nrb, rb = lg - slab * nrb;
@@ -233,14 +235,22 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
     T *ww = w + vb;
     const T *vpp = SP ? (const T *)sp.vp + vb : nullptr;
     const double bprev = (SP && sp.n > 0) ? sp.beta[(int64_t)blockIdx.y * sp.maxs + sp.n - 1] : 0.0;
-    double part = 0.0;
+    double p_vw = 0.0, p_ww = 0.0, p_vv = 0.0, p_pw = 0.0, p_pv = 0.0;
     // the element as a separate pass would leave it: product rounded once,
-    // then w - beta' vp rounded once; and its share of <v, w>
+    // then w - beta' vp rounded once; and its shares of the step's dots
     auto fin = [&](double a, int64_t i) -> T {
         T t = (T)a;
         if (SP) {
-            if (sp.n > 0) t = (T)fma(-bprev, (double)vpp[i], (double)t);
-            part = fma((double)vv[i], (double)t, part);
+            const double pv = sp.n > 0 ? (double)vpp[i] : 0.0;
+            if (sp.n > 0) t = (T)fma(-bprev, pv, (double)t);
+            const double vi = (double)vv[i], wi = (double)t;
+            p_vw = fma(vi, wi, p_vw);
+            p_ww = fma(wi, wi, p_ww);
+            p_vv = fma(vi, vi, p_vv);
+            if (sp.reorth) {
+                p_pw = fma(pv, wi, p_pw);
+                p_pv = fma(pv, vi, p_pv);
+            }
         }
         return t;
     };
@@ -311,8 +321,23 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
         }
     }
     if (SP) {
-        const double t = block_sum(part, sh);
-        if (threadIdx.x == 0) sp.pa[(int64_t)blockIdx.y * gridDim.x + p] = t;
+        double *o = sp.pa + (int64_t)blockIdx.y * gridDim.x + p;
+        const double t0 = block_sum(p_vw, sh);
+        const double t1 = block_sum(p_ww, sh);
+        const double t2 = block_sum(p_vv, sh);
+        if (threadIdx.x == 0) {
+            o[0] = t0;
+            o[sp.pstride] = t1;
+            o[2 * sp.pstride] = t2;
+        }
+        if (sp.reorth) {
+            const double t3 = block_sum(p_pw, sh);
+            const double t4 = block_sum(p_pv, sh);
+            if (threadIdx.x == 0) {
+                o[3 * sp.pstride] = t3;
+                o[4 * sp.pstride] = t4;
+            }
+        }
     }
 }
 

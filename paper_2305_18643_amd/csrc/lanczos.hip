@@ -190,7 +190,8 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.partial = cv.take<double>((size_t)nvec * e.nchunks);
     int64_t npa = e.nblk > e.nchunks ? e.nblk : e.nchunks;
     if (e.na > npa) npa = e.na;
-    e.pa = cv.take<double>((size_t)nvec * npa);
+    // the two-pass product keeps five partial arrays (alpha and the norm dots)
+    e.pa = cv.take<double>((size_t)nvec * npa * (op.split ? 5 : 1));
     e.pn = cv.take<double>((size_t)nvec * 3 * e.nchunks);
     e.cs.maxs = maxs;
     e.cs.btol = btol;
@@ -260,6 +261,7 @@ BGroup engine_group(const Engine &e, int n) {
     g.v = e.vbuf[e.iv];
     g.w = e.vbuf[e.iw];
     g.pa = e.pa;
+    g.pstride = (int64_t)e.nvec * e.na;
     g.pn = e.pn;
     g.psi = nullptr;
     g.svec = nullptr;
@@ -283,14 +285,21 @@ static int step_t(Engine &e, int n, hipStream_t s) {
         sp.maxs = e.cs.maxs;
         sp.n = n;
         sp.pa = e.pa;
+        sp.pstride = (int64_t)e.nvec * e.na;
+        sp.reorth = e.reorth;
         QCM_TRY(hv_split_launch_sub(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, sp, s));
+        // alpha, then beta from the product's dots: no norm pass
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 2);
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
         ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);
     }
-    ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
-    ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src);
-    ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 1);
+    if (!e.op.split) {
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
+        ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src);
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 1);
+    }
     ks_update<T, OneSrc><<<nk, 256, 0, s>>>(src);
     QCM_LAUNCH_CHECK();
     // rotate: v_{n-1} <- v_n, v_n <- the new vector, next w <- old v_{n-1}

@@ -8,7 +8,9 @@
 //           product runs first and a chunked pass subtracts and sums);
 //   finish  alpha_n = <v, w>;
 //   pass 2  x = w - alpha_n v (not stored): partial sums of |x|^2 and, with
-//           local reorthogonalisation, of <v, x> and <vp, x>;
+//           local reorthogonalisation, of <v, x> and <vp, x> (after the
+//           two-pass product these come from dots its last pass already
+//           summed, and this pass is skipped);
 //   finish  c1 = <v, x>, c2 = <vp, x>; alpha_n += c1;
 //           beta_n^2 = |x|^2 - c1^2 - c2^2 (the norm of x - c1 v - c2 vp for
 //           unit v, vp orthogonal to each other, up to terms of order c^2 eps);
@@ -46,6 +48,7 @@ struct BGroup {
     int32_t nblk;      // product blocks per vector
     int32_t nvec, nchunks;
     int32_t na;        // alpha partials per vector (nblk when fused, else nchunks)
+    int64_t pstride;   // two-pass product: stride between its five partial arrays
     int32_t n;         // step index
     int32_t reorth;
     const void *vp, *v;
@@ -385,8 +388,28 @@ __device__ __forceinline__ double strided_sum(const double *__restrict__ p, int6
     return acc;
 }
 
+// beta_n from |x|^2 and the reorthogonalisation terms c1 = <v, x>,
+// c2 = <vp, x> of x = w - alpha_n v, and the chain's bookkeeping
+__device__ __forceinline__ void finish_beta(const ChainState &cs, int c, int n, int reorth,
+                                            double s0, double s1, double s2) {
+    if (reorth) cs.alpha[(int64_t)c * cs.maxs + n] += s1;
+    cs.corr[c] = s1;
+    cs.corr2[c] = s2;
+    const double bb = s0 - s1 * s1 - s2 * s2;
+    const double b = sqrt(bb > 0.0 ? bb : 0.0);
+    cs.beta[(int64_t)c * cs.maxs + n] = b;
+    if (!cs.done[c]) {
+        const double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
+        if (!(b >= cs.btol * am)) cs.done[c] = 1;
+        cs.len[c] = n + 1;
+    }
+    cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
+}
+
 // per-chain sums of the partials and the recurrence bookkeeping
-// mode 0: alpha_n; mode 1: reorthogonalisation terms, beta_n, breakdown.
+// mode 0: alpha_n; mode 1: reorthogonalisation terms, beta_n, breakdown, from
+// the norm pass; mode 2: the same from the dots of the two-pass product
+// (pa: <v,w>, <w,w>, and with reorthogonalisation <v,v>, <vp,w>, <vp,v>).
 template <class Src>
 __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
     __shared__ double sh[256];
@@ -407,6 +430,24 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         }
         return;
     }
+    if (mode == 2) {
+        const double *p = q.pa + (int64_t)c * q.na;
+        const double ww = block_sum(strided_sum(p + q.pstride, q.na), sh);
+        const double vv = block_sum(strided_sum(p + 2 * q.pstride, q.na), sh);
+        double pw = 0.0, pv = 0.0;
+        if (q.reorth) {
+            pw = block_sum(strided_sum(p + 3 * q.pstride, q.na), sh);
+            pv = block_sum(strided_sum(p + 4 * q.pstride, q.na), sh);
+        }
+        if (threadIdx.x != 0) return;
+        const double a = cs.apre[c];   // <v, w>
+        // x = w - a v: |x|^2, <v, x>, <vp, x> from the dots
+        const double s0 = fma(a * a, vv, fma(-2.0 * a, a, ww));
+        const double s1 = q.reorth ? fma(-a, vv, a) : 0.0;
+        const double s2 = q.reorth ? fma(-a, pv, pw) : 0.0;
+        finish_beta(cs, c, n, q.reorth, s0, s1, s2);
+        return;
+    }
     const double *p = q.pn + (int64_t)c * 3 * q.nchunks;
     const double s0 = block_sum(strided_sum(p, q.nchunks), sh);
     double s1 = 0.0, s2 = 0.0;
@@ -415,18 +456,7 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         s2 = block_sum(strided_sum(p + 2 * q.nchunks, q.nchunks), sh);
     }
     if (threadIdx.x != 0) return;
-    if (q.reorth) cs.alpha[(int64_t)c * cs.maxs + n] += s1;
-    cs.corr[c] = s1;
-    cs.corr2[c] = s2;
-    const double bb = s0 - s1 * s1 - s2 * s2;
-    const double b = sqrt(bb > 0.0 ? bb : 0.0);
-    cs.beta[(int64_t)c * cs.maxs + n] = b;
-    if (!cs.done[c]) {
-        const double am = cs.amax[c] > 0.0 ? cs.amax[c] : 1.0;
-        if (!(b >= cs.btol * am)) cs.done[c] = 1;
-        cs.len[c] = n + 1;
-    }
-    cs.inv[c] = cs.done[c] ? 0.0 : 1.0 / b;
+    finish_beta(cs, c, n, q.reorth, s0, s1, s2);
 }
 
 // pass 3: w = (w - alpha v - c1 v - c2 vp) / beta_n; psi += svec[n] v (replay)

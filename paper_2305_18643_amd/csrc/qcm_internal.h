@@ -175,13 +175,22 @@ bool split_applies(const qcm_model *m, int n_up, int64_t d_up, int64_t d_dn);
 int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s);
 // The first pass of a Lanczos step fused into the two-pass product's row-mixing
 // pass: w = H v - beta' vp (beta' = beta[c * maxs + n - 1] of chain c; none
-// when n = 0) and the partial <v, w> of every row-mixing workgroup in
-// pa[c * split_pa_count(op) + workgroup].
+// when n = 0) and, per row-mixing workgroup g (G = split_pa_count(op) of them
+// per chain), the partial sums
+//   pa[k * pstride + c * G + g] = <v, w>, <w, w>, <v, v> for k = 0, 1, 2,
+// and with reorth also <vp, w>, <vp, v> at k = 3, 4; pstride = nvec * G.
+// With them the step needs no separate norm pass: for x = w - alpha v,
+// |x|^2 = <w,w> - 2 alpha <v,w> + alpha^2 <v,v>, <v, x> = <v,w> - alpha <v,v>,
+// <vp, x> = <vp,w> - alpha <vp,v>.  <v, v> is measured, not taken as 1: the
+// rounding of the normalisation would otherwise enter beta uncorrected and
+// grow from step to step.
 struct SubPrev {
     const void *vp = nullptr;
     const double *beta = nullptr;
     int maxs = 0, n = 0;
     double *pa = nullptr;
+    int64_t pstride = 0;
+    int reorth = 0;
 };
 int64_t split_pa_count(const HvOp &op);
 int hv_split_launch_sub(const HvOp &op, int prec, const void *v, void *w, int nvec,
