@@ -318,10 +318,11 @@ void qcm_band_default_opts(qcm_band_opts *o);
  *   n_z, h_z, d_G: as in qcm_green_cf (device complex128 [n_z][n_orb][n_orb]).
  * Workspace: 3 n_orb + 3 vectors per part plus one max_basis^2 FP64 matrix
  * (two with etol > 0).
- * With etol > 0 the stopping tests run on a stream the call creates (default
- * priority, waiting on `stream` through events) and destroys before it
- * returns, plus 8 bytes of pinned host memory; the result is the same as
- * with the tests in order on `stream`.
+ * With etol > 0 the stopping tests run on a side stream (default priority,
+ * waiting on `stream` through events) with 8 bytes of pinned host memory; the
+ * library creates one such set per device the first time it is needed (one
+ * more per concurrent caller) and reuses it for the life of the process.  The
+ * result is the same as with the tests in order on `stream`.
  * Errors: QCM_EARG (also when the QR steps run out, which takes a non-finite
  * T), QCM_EWORKSPACE, QCM_EHIP.  Synchronises the stream.
  */

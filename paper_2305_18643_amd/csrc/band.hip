@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <set>
 #include <vector>
 
@@ -592,19 +593,69 @@ static int band_layout(const qcm_model *m, const qcm_basis *gs, const qcm_band_o
     return QCM_OK;
 }
 
-// The stream, events and pinned result of the stopping tests, which run
-// beside the recurrence; released (after the side stream drains) on every
-// way out of band_run.
+// The stream (default priority), events and pinned result of the stopping
+// tests, which run beside the recurrence.  They are created once and kept in
+// a process-wide pool for the life of the process: a call leases a free set
+// of its device (creating one only when none is free, so concurrent calls from
+// other host threads get sets of their own) and returns it, after its side
+// stream has drained, on every way out of band_run.  Later calls therefore
+// create and destroy nothing (stream and pinned-memory teardown can wait for
+// the whole device).
+struct SideRes {
+    int dev = -1;
+    hipStream_t s = nullptr;
+    hipEvent_t copied = nullptr, done = nullptr;
+    double *h_theta = nullptr;
+};
+static std::mutex g_side_mu;
+static std::vector<SideRes *> g_side_free;
+
 struct SideTest {
     hipStream_t s = nullptr;
     hipEvent_t copied = nullptr, done = nullptr;
     double *h_theta = nullptr;
+    SideRes *r = nullptr;
+    int lease() {
+        int dev = -1;
+        QCM_HIP(hipGetDevice(&dev));
+        {
+            std::lock_guard<std::mutex> lock(g_side_mu);
+            for (size_t k = 0; k < g_side_free.size(); ++k)
+                if (g_side_free[k]->dev == dev) {
+                    r = g_side_free[k];
+                    g_side_free.erase(g_side_free.begin() + k);
+                    break;
+                }
+        }
+        if (!r) {
+            SideRes *n = new SideRes();
+            n->dev = dev;
+            hipError_t e = hipStreamCreateWithFlags(&n->s, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&n->copied, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&n->done, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void **)&n->h_theta, sizeof(double), hipHostMallocDefault);
+            if (e != hipSuccess) {
+                if (n->h_theta) (void)hipHostFree(n->h_theta);
+                if (n->done) (void)hipEventDestroy(n->done);
+                if (n->copied) (void)hipEventDestroy(n->copied);
+                if (n->s) (void)hipStreamDestroy(n->s);
+                delete n;
+                return fail(QCM_EHIP, "band Lanczos side stream: %s", hipGetErrorString(e));
+            }
+            r = n;
+        }
+        s = r->s;
+        copied = r->copied;
+        done = r->done;
+        h_theta = r->h_theta;
+        return QCM_OK;
+    }
     ~SideTest() {
-        if (s) (void)hipStreamSynchronize(s);
-        if (done) (void)hipEventDestroy(done);
-        if (copied) (void)hipEventDestroy(copied);
-        if (s) (void)hipStreamDestroy(s);
-        if (h_theta) (void)hipHostFree(h_theta);
+        if (!r) return;
+        (void)hipStreamSynchronize(r->s);
+        std::lock_guard<std::mutex> lock(g_side_mu);
+        g_side_free.push_back(r);
     }
 };
 
@@ -647,12 +698,7 @@ static int band_run(const qcm_band_opts *o, BandPart &P, const double *d_gs, int
     int stop_at = 0;  // basis size a finished test stopped the part at
     bool near = false;
     double prev_d = 0.0;  // the change of the lowest eigenvalue at the last test
-    if (o->etol > 0.0) {
-        QCM_HIP(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
-        QCM_HIP(hipEventCreateWithFlags(&side.copied, hipEventDisableTiming));
-        QCM_HIP(hipEventCreateWithFlags(&side.done, hipEventDisableTiming));
-        QCM_HIP(hipHostMalloc((void **)&side.h_theta, sizeof(double), hipHostMallocDefault));
-    }
+    if (o->etol > 0.0) QCM_TRY(side.lease());
     // take the result of the test in flight, waiting for it or only if done
     auto settle = [&](bool wait) -> int {
         if (!pend_j) return QCM_OK;
