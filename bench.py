@@ -180,7 +180,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.U),
-                     "kernel": "H.v (k_hv_inrow_pk + k_hv_down_acc)",
+                     "kernel": "H.v (k_hv_inrow_tile + k_hv_down_acc)",
                      "bytes_per_launch": bytes_alg,
                      "copy_kernel_GBps": round(copy_gbs, 1),
                      "frac_of_copy_kernel": round(gbs / copy_gbs, 4)},
@@ -290,13 +290,19 @@ def engine_opts_for(prec):
     return dict(prec="fp32v", reorth=1)
 
 
+K_FLOORS = 12
+
+
 def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
     """Per-result errors of GPU solves against the CPU FP64 oracle (plain
     recurrence, the same start vector): relative |dE0|, max |dG| over the 4x4
     block on the grid, max |d b0^2| of the 20 chains, the degeneracy flag and
     whether every chain of the oracle ended by exhausting its Krylov space
     (only then is the 100-floor G independent of rounding; truncated chains
-    without reorthogonalisation differ run to run, in either precision)."""
+    without reorthogonalisation differ run to run, in either precision).
+    Also the well-posed part of every chain: its first K = 12 floors (a_n and
+    b_n^2 relative to max(1, |a|)) and the G those floors give on the grid,
+    which rounding does not move before orthogonality is lost."""
     import oracle
     from oracle import cf
     recs = []
@@ -310,13 +316,33 @@ def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
         Go = cf.green_matrix(ch, 4, z, ro["e0"])
         exhausted = all(len(a) < gf_steps for (_, a, _) in ch.values())
         rec = {"job": int(i), "orbitals": m.L, "dim": int(d), "oracle_chains_exhausted": exhausted}
+        keys = [(a, b, part) for a in range(4) for b in range(a, 4) for part in (0, 1)]
         for prec, res in results_by_prec.items():
             r = res[i]
             b0 = [r["coef"][p, part, 0] for p in range(10) for part in (0, 1)]
-            b0o = [ch[(a, b, part)][0] for a in range(4) for b in range(a, 4) for part in (0, 1)]
+            b0o = [ch[k][0] for k in keys]
+            # the first K floors of each chain, on both sides
+            chk, chko, dcoef = {}, {}, 0.0
+            for n, k in enumerate(keys):
+                p, part = n // 2, n % 2
+                bo, ao, b2o = ch[k]
+                K = min(K_FLOORS, int(r["len"][p, part]), len(ao))
+                ag = r["coef"][p, part, 1:1 + K]
+                b2g = r["coef"][p, part, 1 + gf_steps:gf_steps + K]
+                sc = max(1.0, float(np.abs(ao[:K]).max())) if K else 1.0
+                if K:
+                    dcoef = max(dcoef, float(np.abs(ag - ao[:K]).max()) / sc)
+                if K > 1:
+                    dcoef = max(dcoef, float(np.abs(b2g - b2o[:K - 1]).max()) / sc)
+                chk[k] = (r["coef"][p, part, 0], ag, b2g)
+                chko[k] = (bo, ao[:K], b2o[:K - 1])
+            GK = cf.green_matrix(chk, 4, z, r["e0"])
+            GKo = cf.green_matrix(chko, 4, z, ro["e0"])
             rec[prec] = {"rel_dE0": abs(r["e0"] - ro["e0"]) / abs(ro["e0"]),
                          "max_dG": float(np.abs(r["G"] - Go).max()),
                          "max_db0sq": float(np.max(np.abs(np.array(b0) - np.array(b0o)))),
+                         "max_rel_dcoef_12floors": dcoef,
+                         "max_dG_12floors": float(np.abs(GK - GKo).max()),
                          "degenerate_suspect": bool(r["degenerate_suspect"])}
         recs.append(rec)
     summ = {}
@@ -331,6 +357,8 @@ def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
                 "max_dG": max(r[prec]["max_dG"] for r in sel),
                 "median_dG": float(np.median([r[prec]["max_dG"] for r in sel])),
                 "max_db0sq": max(r[prec]["max_db0sq"] for r in sel),
+                "max_rel_dcoef_12floors": max(r[prec]["max_rel_dcoef_12floors"] for r in sel),
+                "max_dG_12floors": max(r[prec]["max_dG_12floors"] for r in sel),
                 "degenerate_suspect_jobs": sum(r[prec]["degenerate_suspect"] for r in sel)}
     return summ, recs
 

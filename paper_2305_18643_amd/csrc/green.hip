@@ -543,6 +543,7 @@ extern "C" int qcm_green_cf(const qcm_model *m, const qcm_basis *gs, const doubl
         QCM_TRY(engine_reset(e, s));
         QCM_TRY(apply_ops_launch(e, d_gs, gs->d_up, upg, up2, part, ops_d, s));
         QCM_TRY(engine_normalize_from_partials(e, s));
+        e.lazy = 1;   // only the coefficients are kept
         std::vector<int32_t> done(npairs);
         for (int step = 0; step < maxs; ++step) {
             QCM_TRY(engine_step(e, step, s));

@@ -71,17 +71,49 @@ __global__ void k_pack_tiles(int64_t d, const int32_t *__restrict__ nh,
 // is +-t: the entry's sign bit flips the sign of the neighbour value and the
 // coefficient table is not read.  W = V K_up^T + D o V, written once; the
 // per-element sum is the diagonal term, then the hops in list order.
+// LZ > 0 (a Lanczos step after a deferred update, LazyUpd): v holds w_n; the
+// prefetch of the next row also loads v_n (and v_{n-1} for LZ = 2, with
+// reorthogonalisation); when the row is staged, v_{n+1} is formed, put in LDS
+// and stored back over w_n.
 constexpr int kTileChunk = 8;
-template <typename T, int KS, bool UT>
-__global__ void __launch_bounds__(1024) k_hv_inrow_tile(
+constexpr int kInrowThreads = 1024;
+
+// Rows are loaded and stored through a buffer descriptor over the row: one
+// lane offset register and a scalar offset per slot (the slot's offsets need
+// no registers of their own), and the hardware's range check returns 0 for
+// loads past the row and drops stores past it.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *row, int64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(row), (short)0,
+                                             (int)(n * (int64_t)sizeof(T)), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T row_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 2));
+}
+template <typename T>
+__device__ __forceinline__ void row_store(T x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, voff, soff, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, voff, soff, 2);
+}
+
+template <typename T, int KS, bool UT, int LZ>
+__global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     const int64_t d_up, const int64_t d_dn, const uint32_t *__restrict__ su,
     const double *__restrict__ eu, const int ntile, const int32_t *__restrict__ tnt,
     const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent,
     const double *__restrict__ ctab_g, const int nctab, const uint32_t *__restrict__ sd,
     const double *__restrict__ ed, const double *__restrict__ ulut_g, const int nbytes,
-    const double u_uniform, const double tu, const T *__restrict__ v, T *__restrict__ w) {
+    const double u_uniform, const double tu, T *__restrict__ v, T *w, const LazyUpd lz) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int NT = blockDim.x, tid = threadIdx.x;
+    constexpr int NT = kInrowThreads;   // the launch's block size
+    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = NT >> 6;
     const int dup = (int)d_up;
     T *row = reinterpret_cast<T *>(smem);
@@ -98,20 +130,61 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_tile(
         for (int k = tid; k < nctab; k += NT) ct[k] = ctab_g[k];
     typedef __attribute__((address_space(3))) const T lds_t;
     const int64_t vb = (int64_t)blockIdx.y * d_up * d_dn;
-    const T *vv = v + vb;
+    T *vv = v + vb;
     T *ww = w + vb;
-    T xr[KS];
-    int64_t r = blockIdx.x;
-    {
-        const T *src = vv + r * d_up;
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            const int idx = tid + k * NT;
-            xr[k] = (r < d_dn && idx < dup) ? __builtin_nontemporal_load(src + idx) : T(0);
+    // the deferred update's operands (LZ > 0)
+    const T *vo = LZ ? (const T *)lz.vold + vb : nullptr;
+    const T *vpo = LZ == 2 ? (const T *)lz.vpold + vb : nullptr;
+    double la = 0.0, lc1 = 0.0, lc2 = 0.0, linv = 0.0;
+    if (LZ) {
+        la = lz.apre[blockIdx.y];
+        linv = lz.inv[blockIdx.y];
+        if (LZ == 2) {
+            lc1 = lz.corr[blockIdx.y];
+            lc2 = lz.corr2[blockIdx.y];
         }
     }
+    // slot k of a row is element tid + k NT, at byte offset voff + k sstep
+    const int voff = tid * (int)sizeof(T);
+    constexpr int sstep = NT * (int)sizeof(T);
+    T xr[KS];
+    T yr[LZ ? KS : 1];
+    T zr[LZ == 2 ? KS : 1];
+    auto fetch = [&](int64_t rr) {
+        const int64_t o = rr * d_up;
+        const __amdgpu_buffer_rsrc_t rv = row_rsrc(vv + o, d_up);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) xr[k] = row_load<T>(rv, voff, k * sstep);
+        if (LZ) {
+            const __amdgpu_buffer_rsrc_t ro = row_rsrc(vo + o, d_up);
+#pragma unroll
+            for (int k = 0; k < KS; ++k) yr[k] = row_load<T>(ro, voff, k * sstep);
+        }
+        if (LZ == 2) {
+            const __amdgpu_buffer_rsrc_t rp = row_rsrc(vpo + o, d_up);
+#pragma unroll
+            for (int k = 0; k < KS; ++k) zr[k] = row_load<T>(rp, voff, k * sstep);
+        }
+    };
+    int64_t r = blockIdx.x;
+    if (r < d_dn) fetch(r);
     for (; r < d_dn; r += gridDim.x) {
         __syncthreads();
+        if (LZ) {
+            // v_{n+1} as the update pass forms it, stored over w_n
+            const __amdgpu_buffer_rsrc_t rs = row_rsrc(vv + r * d_up, d_up);
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                const double vi = (double)yr[k];
+                double x = fma(-la, vi, (double)xr[k]);
+                if (LZ == 2) {
+                    x = fma(-lc1, vi, x);
+                    x = fma(-lc2, (double)zr[k], x);
+                }
+                xr[k] = (T)(x * linv);
+                row_store<T>(xr[k], rs, voff, k * sstep);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int idx = tid + k * NT;
@@ -119,14 +192,7 @@ __global__ void __launch_bounds__(1024) k_hv_inrow_tile(
         }
         __syncthreads();
         const int64_t rn = r + gridDim.x;
-        if (rn < d_dn) {
-            const T *src = vv + rn * d_up;
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                const int idx = tid + k * NT;
-                if (idx < dup) xr[k] = __builtin_nontemporal_load(src + idx);
-            }
-        }
+        if (rn < d_dn) fetch(rn);
         const uint32_t bd = sd[r];
         const double edn = ed[r];
         T *wrow = ww + r * d_up;
@@ -363,31 +429,44 @@ static size_t inrow_lds_bytes(const HvOp &op, int prec) {
 }
 
 template <typename T>
-static int split_launch_t(const HvOp &op, const void *v, void *w, int nvec, hipStream_t s,
-                          const SubPrev *sp) {
+static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_t s,
+                          const SubPrev *sp, const LazyUpd *lzp) {
     const int64_t d_up = op.up.d, d_dn = op.dn.d;
     const HopTables &hd_rm = op.hd_rm;
     const size_t lds = inrow_lds_bytes(op, sizeof(T) == 8 ? QCM_FP64 : QCM_FP32V);
     if (lds > 160 * 1024) return fail(QCM_EARG, "in-row pass: the row does not fit LDS");
     const int ks = (int)((d_up + 1023) / 1024);
     const int nctab = 2 * op.md.nbond;
-    // pass A: in-row term and diagonal, writes W
+    // pass A: in-row term and diagonal, writes W (and first forms v from a
+    // deferred update)
     dim3 gp((unsigned)std::min<int64_t>(d_dn, 256), (unsigned)nvec);
+    const LazyUpd lz = lzp ? *lzp : LazyUpd{};
+    const int lzm = lzp ? (lz.reorth ? 2 : 1) : 0;
+#define QCM_PK_L(KS_, UT_, LZ_)                                                                \
+    k_hv_inrow_tile<T, KS_, UT_, LZ_><<<gp, 1024, lds, s>>>(                                   \
+        d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off, op.tile_ent, \
+        op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut, op.md.nbytes,                \
+        op.md.u_uniform, op.md.t_uniform, (T *)v, (T *)w, lz)
+#define QCM_PK_U(KS_, UT_)                                                                     \
+    do {                                                                                       \
+        if (lzm == 0)                                                                          \
+            QCM_PK_L(KS_, UT_, 0);                                                             \
+        else if (lzm == 1)                                                                     \
+            QCM_PK_L(KS_, UT_, 1);                                                             \
+        else                                                                                   \
+            QCM_PK_L(KS_, UT_, 2);                                                             \
+    } while (0)
 #define QCM_PK(KS_)                                                                            \
     if (ks <= KS_) {                                                                           \
         if (op.md.t_is_uniform)                                                                \
-            k_hv_inrow_tile<T, KS_, true><<<gp, 1024, lds, s>>>(                               \
-                d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off,      \
-                op.tile_ent, op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut,         \
-                op.md.nbytes, op.md.u_uniform, op.md.t_uniform, (const T *)v, (T *)w);        \
+            QCM_PK_U(KS_, true);                                                               \
         else                                                                                   \
-            k_hv_inrow_tile<T, KS_, false><<<gp, 1024, lds, s>>>(                              \
-                d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off,      \
-                op.tile_ent, op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut,         \
-                op.md.nbytes, op.md.u_uniform, op.md.t_uniform, (const T *)v, (T *)w);        \
+            QCM_PK_U(KS_, false);                                                              \
     } else
     QCM_PK(4) QCM_PK(8) QCM_PK(12) QCM_PK(16) { return fail(QCM_EARG, "in-row pass: row too long"); }
 #undef QCM_PK
+#undef QCM_PK_U
+#undef QCM_PK_L
     QCM_LAUNCH_CHECK();
     // pass B: row mixing, accumulates into W
     const int R = 16;
@@ -505,15 +584,17 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
     return QCM_OK;
 }
 
+// v is only read here (the plain product writes W alone)
 int hv_split_launch(const HvOp &op, int prec, const void *v, void *w, int nvec, hipStream_t s) {
-    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s, nullptr);
-    return split_launch_t<float>(op, v, w, nvec, s, nullptr);
+    void *vm = const_cast<void *>(v);
+    if (prec == QCM_FP64) return split_launch_t<double>(op, vm, w, nvec, s, nullptr, nullptr);
+    return split_launch_t<float>(op, vm, w, nvec, s, nullptr, nullptr);
 }
 
-int hv_split_launch_sub(const HvOp &op, int prec, const void *v, void *w, int nvec,
-                        const SubPrev &sp, hipStream_t s) {
-    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s, &sp);
-    return split_launch_t<float>(op, v, w, nvec, s, &sp);
+int hv_split_launch_sub(const HvOp &op, int prec, void *v, void *w, int nvec, const SubPrev &sp,
+                        const LazyUpd *lz, hipStream_t s) {
+    if (prec == QCM_FP64) return split_launch_t<double>(op, v, w, nvec, s, &sp, lz);
+    return split_launch_t<float>(op, v, w, nvec, s, &sp, lz);
 }
 
 }  // namespace qcm

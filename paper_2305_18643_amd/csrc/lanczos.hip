@@ -211,6 +211,8 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.ivp = 0;
     e.iv = 1;
     e.iw = 2;
+    e.lazy = 0;
+    e.pending = 0;
     return QCM_OK;
 }
 
@@ -223,6 +225,7 @@ int engine_reset(Engine &e, hipStream_t s) {
     e.ivp = 0;
     e.iv = 1;
     e.iw = 2;
+    e.pending = 0;
     QCM_HIP(hipMemsetAsync(e.vbuf[e.ivp], 0, sz, s));
     return QCM_OK;
 }
@@ -278,7 +281,8 @@ static int step_t(Engine &e, int n, hipStream_t s) {
                                      e.op.md.u_uniform, 2 * e.op.md.nbond);
         ks_hv<T, OneSrc><<<(unsigned)e.nvec * e.nblk, 256, lds, s>>>(src);
     } else if (e.op.split) {
-        // the first pass (w -= beta' vp, partial <v, w>) inside the row-mixing pass
+        // the first pass (w -= beta' vp, partial <v, w>) inside the row-mixing
+        // pass; a deferred update of the previous step inside the in-row pass
         SubPrev sp;
         sp.vp = e.vbuf[e.ivp];
         sp.beta = e.cs.beta;
@@ -287,10 +291,22 @@ static int step_t(Engine &e, int n, hipStream_t s) {
         sp.pa = e.pa;
         sp.pstride = (int64_t)e.nvec * e.na;
         sp.reorth = e.reorth;
-        QCM_TRY(hv_split_launch_sub(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, sp, s));
+        LazyUpd lz;
+        if (e.pending) {
+            // after the rotation: v_n is in ivp, v_{n-1} in iw (where W goes)
+            lz.vold = e.vbuf[e.ivp];
+            lz.vpold = e.vbuf[e.iw];
+            lz.apre = e.cs.apre;
+            lz.corr = e.cs.corr;
+            lz.corr2 = e.cs.corr2;
+            lz.inv = e.cs.inv;
+            lz.reorth = e.reorth;
+        }
+        QCM_TRY(hv_split_launch_sub(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, sp,
+                                    e.pending ? &lz : nullptr, s));
+        e.pending = 0;
         // alpha, then beta from the product's dots: no norm pass
-        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
-        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 2);
+        ks_finish_dots<OneSrc><<<e.nvec, 1024, 0, s>>>(src);
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
         ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);
@@ -300,7 +316,10 @@ static int step_t(Engine &e, int n, hipStream_t s) {
         ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src);
         ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 1);
     }
-    ks_update<T, OneSrc><<<nk, 256, 0, s>>>(src);
+    if (e.op.split && e.lazy)
+        e.pending = 1;   // the next step's in-row pass forms v_{n+1}
+    else
+        ks_update<T, OneSrc><<<nk, 256, 0, s>>>(src);
     QCM_LAUNCH_CHECK();
     // rotate: v_{n-1} <- v_n, v_n <- the new vector, next w <- old v_{n-1}
     int t = e.ivp;
@@ -315,9 +334,31 @@ int engine_step(Engine &e, int n, hipStream_t s) {
     return step_t<float>(e, n, s);
 }
 
+// The deferred update as its own pass (the update pass of the step before the
+// rotation: w was its w, v its v, vp its vp).
+template <typename T>
+static int settle_t(Engine &e, hipStream_t s) {
+    BGroup g = engine_group(e, 0);
+    g.vp = e.vbuf[e.iw];
+    g.v = e.vbuf[e.ivp];
+    g.w = e.vbuf[e.iv];
+    const OneSrc src{g};
+    ks_update<T, OneSrc><<<(unsigned)e.nvec * e.nchunks, 256, 0, s>>>(src);
+    QCM_LAUNCH_CHECK();
+    return QCM_OK;
+}
+
+int engine_settle(Engine &e, hipStream_t s) {
+    if (!e.pending) return QCM_OK;
+    e.pending = 0;
+    if (e.prec == QCM_FP64) return settle_t<double>(e, s);
+    return settle_t<float>(e, s);
+}
+
 // Normalise the current vectors v (chain start vectors), storing b0sq.
 template <typename T>
 static int normalize_t(Engine &e, hipStream_t s) {
+    e.pending = 0;
     T *v = (T *)e.vbuf[e.iv];
     const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
     k_dot_partial<T, T><<<g, 256, 0, s>>>(v, v, e.dim, e.nchunks, e.partial);
@@ -333,6 +374,7 @@ int engine_normalize(Engine &e, hipStream_t s) {
 }
 
 int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s) {
+    e.pending = 0;
     void *v = e.vbuf[e.iv];
     size_t sz = (e.prec == QCM_FP64 ? 8 : 4) * (size_t)e.dim;
     if (v0) {
@@ -347,6 +389,7 @@ int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s) {
 }
 
 int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t s) {
+    QCM_TRY(engine_settle(e, s));
     const unsigned g = (unsigned)e.nchunks;
     if (e.prec == QCM_FP64)
         k_accum<double><<<g, 256, 0, s>>>(psi, (const double *)e.vbuf[e.iv], e.dim, coef, n);
@@ -450,6 +493,8 @@ int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_
     QCM_TRY(engine_reset(e, s));
     QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
     QCM_TRY(engine_normalize(e, s));
+    // the first pass needs the coefficients only: updates may be deferred
+    e.lazy = 1;
     GsStatus hs{};
     int M = 0, conv = 0, brk = 0;
     int32_t done = 0;
@@ -507,6 +552,7 @@ int gs_run(const char *fn, const GsSetup &setup, int64_t dim, const qcm_lanczos_
         // second pass: identical recurrence, psi = sum_n s_n v_n
         double *psi = (double *)d_gs;
         QCM_HIP(hipMemsetAsync(psi, 0, sizeof(double) * dim, s));
+        e.lazy = 0;
         QCM_TRY(engine_reset(e, s));
         QCM_TRY(engine_seed(e, o->seed, o->d_v0, s));
         QCM_TRY(engine_normalize(e, s));
@@ -546,6 +592,7 @@ namespace qcm {
 
 // Normalise the start vectors from norm partials already in e.partial.
 int engine_normalize_from_partials(Engine &e, hipStream_t s) {
+    e.pending = 0;
     const dim3 g((unsigned)e.nchunks, (unsigned)e.nvec);
     k_finish<<<e.nvec, 256, 0, s>>>(e.partial, e.nchunks, 5, e.cs, 0, nullptr);
     if (e.prec == QCM_FP64)

@@ -41,6 +41,11 @@ struct Engine {
     double *pn;        // [nvec][3][nchunks]: norm partials of a step
     int32_t na, rows, nblk;
     int32_t fused;     // product fused with the first pass (rows fit LDS)
+    // Deferred update (two-pass product only): with lazy set, a step leaves
+    // the unnormalised w_n in the buffer of v_{n+1} (pending) and the next
+    // step's in-row pass forms v_{n+1} while it stages the rows; whatever
+    // reads the vectors in between calls engine_settle first.
+    int32_t lazy, pending;
     double *scratch;
     ChainState cs;
 };
@@ -52,6 +57,7 @@ int engine_reset(Engine &e, hipStream_t s);
 int engine_seed(Engine &e, uint64_t seed, const void *v0, hipStream_t s);
 int engine_normalize(Engine &e, hipStream_t s);
 int engine_step(Engine &e, int n, hipStream_t s);
+int engine_settle(Engine &e, hipStream_t s);
 int engine_accum(Engine &e, double *psi, const double *coef, int n, hipStream_t s);
 int engine_normalize_from_partials(Engine &e, hipStream_t s);
 int psi_finalize(Engine &e, double *psi, hipStream_t s);

@@ -16,6 +16,9 @@
 //           unit v, vp orthogonal to each other, up to terms of order c^2 eps);
 //   pass 3  v_{n+1} = (x - c1 v - c2 vp) / beta_n, rounded once to the storage
 //           type (optionally also psi += s_n v_n for the ground-state replay).
+// After the two-pass product the two finishes are one launch (ks_finish_dots),
+// and pass 3 may be deferred into the next step's in-row pass, which forms
+// v_{n+1} element by element with the same operations when it stages a row.
 // Every sum is a fixed-order two-level reduction (per block or per chunk of
 // kChunk elements, then per chain), so results depend only on the inputs and
 // the sector shape, not on the launch or on other groups sharing it.
@@ -456,6 +459,66 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         s2 = block_sum(strided_sum(p + 2 * q.nchunks, q.nchunks), sh);
     }
     if (threadIdx.x != 0) return;
+    finish_beta(cs, c, n, q.reorth, s0, s1, s2);
+}
+
+// ks_finish modes 0 and 2 in one block of 1024 threads per chain, for the
+// two-pass product: its three (with reorthogonalisation five) partial arrays
+// are summed together, eight loads per array in flight per thread, each
+// thread's share in index order, then a fixed tree; thread 0 then records
+// alpha_n and beta_n as the two modes do.
+template <class Src>
+__global__ void __launch_bounds__(1024) ks_finish_dots(Src src) {
+    constexpr int NT = 1024, U = 8;
+    __shared__ double sh[5][NT];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.x, &local);
+    const int c = (int)local;
+    const ChainState &cs = q.cs;
+    const int n = q.n;
+    const int na = q.reorth ? 5 : 3;
+    const double *p = q.pa + (int64_t)c * q.na;
+    const int t = threadIdx.x;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t k = t;
+    for (; k + (U - 1) * NT < q.na; k += U * NT) {
+        double x[5][U];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+            if (a < na)
+#pragma unroll
+                for (int u = 0; u < U; ++u) x[a][u] = p[a * q.pstride + k + u * NT];
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+            if (a < na)
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[a] += x[a][u];
+    }
+    for (; k < q.na; k += NT)
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+            if (a < na) acc[a] += p[a * q.pstride + k];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) sh[a][t] = acc[a];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int a = 0; a < 5; ++a) sh[a][t] += sh[a][t + s];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double vw = sh[0][0], ww = sh[1][0], vv = sh[2][0];
+    const double pw = q.reorth ? sh[3][0] : 0.0, pv = q.reorth ? sh[4][0] : 0.0;
+    // mode 0: alpha_n = <v, w>
+    cs.alpha[(int64_t)c * cs.maxs + n] = vw;
+    cs.apre[c] = vw;
+    if (fabs(vw) > cs.amax[c]) cs.amax[c] = fabs(vw);
+    // mode 2: x = w - a v: |x|^2, <v, x>, <vp, x> from the dots
+    const double a = vw;
+    const double s0 = fma(a * a, vv, fma(-2.0 * a, a, ww));
+    const double s1 = q.reorth ? fma(-a, vv, a) : 0.0;
+    const double s2 = q.reorth ? fma(-a, pv, pw) : 0.0;
     finish_beta(cs, c, n, q.reorth, s0, s1, s2);
 }
 

@@ -192,9 +192,23 @@ struct SubPrev {
     int64_t pstride = 0;
     int reorth = 0;
 };
+// A Lanczos step whose previous update was deferred: the vector buffer v
+// holds the unnormalised w_n of the previous step; the in-row pass forms
+// v_{n+1} = (w_n - (a + c1) v_n - c2 v_{n-1}) * inv element by element, in
+// the order and roundings of the separate update pass (x = w - a v, then
+// - c1 v, - c2 v_{n-1} with reorthogonalisation, times inv, rounded once),
+// stores it over w_n and uses it as the row.  Per chain: a = apre, c1 = corr,
+// c2 = corr2, inv (0 for a stopped chain).  vpold is the buffer the product
+// writes W into (read before the row's W is written).
+struct LazyUpd {
+    const void *vold = nullptr;    // v_n
+    const void *vpold = nullptr;   // v_{n-1} (read with reorthogonalisation only)
+    const double *apre = nullptr, *corr = nullptr, *corr2 = nullptr, *inv = nullptr;
+    int reorth = 0;
+};
 int64_t split_pa_count(const HvOp &op);
-int hv_split_launch_sub(const HvOp &op, int prec, const void *v, void *w, int nvec,
-                        const SubPrev &sp, hipStream_t s);
+int hv_split_launch_sub(const HvOp &op, int prec, void *v, void *w, int nvec, const SubPrev &sp,
+                        const LazyUpd *lz, hipStream_t s);
 int check_basis(const qcm_basis *b, int L);
 
 // ---------------------------------------------------------------- misc
