@@ -721,7 +721,8 @@ def serving_section(args, torch, q, synth, np):
         arr = serving.poisson_arrivals(lam, n, seed=2305 + k)
         specs = [q.JobSpec((m.t, m.U), m.nup, m.ndn, orbs=range(4), tag=i)
                  for i, m in enumerate(reqs)]
-        rep = serving.serve(eng, specs, arr)
+        rep = serving.serve(eng, specs, arr, progress=lambda c: print(
+            f"  serving x{mult}: {c} of {n} done", file=sys.stderr, flush=True))
         base = serving.fifo_one_at_a_time(svc, arr)
         if k == 0 and not args.no_cpu:
             # per-result accuracy of the served (FP32V) solves against the CPU
@@ -752,6 +753,9 @@ def serving_section(args, torch, q, synth, np):
         print(f"serving x{mult}: p99 {serving.nearest_rank(lat, 99):.3f} s", file=sys.stderr,
               flush=True)
     out["peak_pool_GB"] = round(eng.info()["peak_in_use"] / 1e9, 3)
+    free, total = torch.cuda.mem_get_info()
+    out["device_memory_in_use_GB"] = round((total - free) / 1e9, 3)
+    out["device_memory_GB"] = round(total / 1e9, 3)
     eng.close()
     return out
 

@@ -488,7 +488,10 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
                 d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
                 (T *)w, R, nrb, total, per, op.row_order, none);                             \
     } while (0)
-    if (cw == 2 && sizeof(T) == 8)
+    // FP64 keeps four rows in flight for the product alone; the Lanczos form
+    // (its epilogue needs more registers) is faster with two, which leave
+    // room for five waves per SIMD instead of three
+    if (cw == 2 && sizeof(T) == 8 && !sp)
         QCM_DACC(4, 2);
     else if (cw == 2)
         QCM_DACC(2, 2);

@@ -14,6 +14,8 @@
 
 #include <string.h>
 
+#include <algorithm>
+
 #include "lanczos_step.h"
 
 namespace qcm {
@@ -157,7 +159,7 @@ size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs) {
     row_shape(d_up, d_dn, prec, &rows, &nblk);
     cv.take<double>((size_t)nvec * nch);
     cv.take<double>((size_t)nvec * (nblk > nch ? nblk : nch));
-    cv.take<double>((size_t)nvec * 3 * nch);
+    cv.take<double>((size_t)nvec * std::max<size_t>(3 * (size_t)nch, 5 * kDotBlocks));
     cv.take<double>((size_t)nvec * maxs * 2);
     cv.take<double>((size_t)nvec * 7);
     cv.take<int32_t>((size_t)nvec * 2);
@@ -192,7 +194,8 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     if (e.na > npa) npa = e.na;
     // the two-pass product keeps five partial arrays (alpha and the norm dots)
     e.pa = cv.take<double>((size_t)nvec * npa * (op.split ? 5 : 1));
-    e.pn = cv.take<double>((size_t)nvec * 3 * e.nchunks);
+    // norm partials, or the two-pass step's per-range dot sums
+    e.pn = cv.take<double>((size_t)nvec * std::max<size_t>(3 * (size_t)e.nchunks, 5 * kDotBlocks));
     e.cs.maxs = maxs;
     e.cs.btol = btol;
     e.cs.alpha = cv.take<double>((size_t)nvec * maxs);
@@ -306,7 +309,8 @@ static int step_t(Engine &e, int n, hipStream_t s) {
                                     e.pending ? &lz : nullptr, s));
         e.pending = 0;
         // alpha, then beta from the product's dots: no norm pass
-        ks_finish_dots<OneSrc><<<e.nvec, 1024, 0, s>>>(src);
+        ks_dots_stage<OneSrc><<<dim3(kDotBlocks, (unsigned)e.nvec), 256, 0, s>>>(src);
+        ks_finish_dots<OneSrc><<<e.nvec, kDotBlocks, 0, s>>>(src);
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
         ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);

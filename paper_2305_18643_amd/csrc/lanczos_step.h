@@ -16,9 +16,10 @@
 //           unit v, vp orthogonal to each other, up to terms of order c^2 eps);
 //   pass 3  v_{n+1} = (x - c1 v - c2 vp) / beta_n, rounded once to the storage
 //           type (optionally also psi += s_n v_n for the ground-state replay).
-// After the two-pass product the two finishes are one launch (ks_finish_dots),
-// and pass 3 may be deferred into the next step's in-row pass, which forms
-// v_{n+1} element by element with the same operations when it stages a row.
+// After the two-pass product the two finishes are ks_dots_stage and
+// ks_finish_dots, and pass 3 may be deferred into the next step's in-row
+// pass, which forms v_{n+1} element by element with the same operations when
+// it stages a row.
 // Every sum is a fixed-order two-level reduction (per block or per chunk of
 // kChunk elements, then per chain), so results depend only on the inputs and
 // the sector shape, not on the launch or on other groups sharing it.
@@ -462,46 +463,59 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
     finish_beta(cs, c, n, q.reorth, s0, s1, s2);
 }
 
-// ks_finish modes 0 and 2 in one block of 1024 threads per chain, for the
-// two-pass product: its three (with reorthogonalisation five) partial arrays
-// are summed together, eight loads per array in flight per thread, each
-// thread's share in index order, then a fixed tree; thread 0 then records
-// alpha_n and beta_n as the two modes do.
+// The two-pass product's partial arrays (three, five with
+// reorthogonalisation, of q.na values per chain) are summed in two launches:
+// ks_dots_stage sums contiguous ranges, one per workgroup of kDotBlocks, into
+// q.pn ([chain][array][kDotBlocks]); ks_finish_dots sums those in order and
+// records alpha_n and beta_n as ks_finish modes 0 and 2 do.  Each thread's
+// share is summed in index order and each block's by a fixed tree.
+constexpr int kDotBlocks = 64;
+
 template <class Src>
-__global__ void __launch_bounds__(1024) ks_finish_dots(Src src) {
-    constexpr int NT = 1024, U = 8;
-    __shared__ double sh[5][NT];
+__global__ void __launch_bounds__(256) ks_dots_stage(Src src) {
+    constexpr int U = 8;
+    __shared__ double sh[256];
+    int64_t local;
+    const BGroup &q = src.at(blockIdx.y, &local);
+    const int c = (int)local;
+    const int na = q.reorth ? 5 : 3;
+    const int64_t len = (q.na + kDotBlocks - 1) / kDotBlocks;
+    const int64_t k0 = (int64_t)blockIdx.x * len;
+    const int64_t k1 = min((int64_t)q.na, k0 + len);
+    const double *p = q.pa + (int64_t)c * q.na;
+    double *o = q.pn + ((int64_t)c * 5) * kDotBlocks + blockIdx.x;
+    for (int a = 0; a < na; ++a) {
+        const double *pa = p + a * q.pstride;
+        double acc = 0.0;
+        int64_t k = k0 + threadIdx.x;
+        for (; k + (U - 1) * 256 < k1; k += U * 256) {
+            double x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = pa[k + u * 256];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += x[u];
+        }
+        for (; k < k1; k += 256) acc += pa[k];
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) o[a * kDotBlocks] = t;
+    }
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kDotBlocks) ks_finish_dots(Src src) {
+    __shared__ double sh[5][kDotBlocks];
     int64_t local;
     const BGroup &q = src.at(blockIdx.x, &local);
     const int c = (int)local;
     const ChainState &cs = q.cs;
     const int n = q.n;
     const int na = q.reorth ? 5 : 3;
-    const double *p = q.pa + (int64_t)c * q.na;
     const int t = threadIdx.x;
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    int64_t k = t;
-    for (; k + (U - 1) * NT < q.na; k += U * NT) {
-        double x[5][U];
+    const double *p = q.pn + ((int64_t)c * 5) * kDotBlocks;
 #pragma unroll
-        for (int a = 0; a < 5; ++a)
-            if (a < na)
-#pragma unroll
-                for (int u = 0; u < U; ++u) x[a][u] = p[a * q.pstride + k + u * NT];
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-            if (a < na)
-#pragma unroll
-                for (int u = 0; u < U; ++u) acc[a] += x[a][u];
-    }
-    for (; k < q.na; k += NT)
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-            if (a < na) acc[a] += p[a * q.pstride + k];
-#pragma unroll
-    for (int a = 0; a < 5; ++a) sh[a][t] = acc[a];
+    for (int a = 0; a < 5; ++a) sh[a][t] = a < na ? p[a * kDotBlocks + t] : 0.0;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = kDotBlocks / 2; s > 0; s >>= 1) {
         if (t < s)
 #pragma unroll
             for (int a = 0; a < 5; ++a) sh[a][t] += sh[a][t + s];

