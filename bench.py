@@ -290,7 +290,25 @@ def engine_opts_for(prec):
     return dict(prec="fp32v", reorth=1)
 
 
-K_FLOORS = 12
+MOMENT_FLOORS = 5
+
+
+def _moments(b0sq, a, b2, kmax, np):
+    """mu_k = b0^2 (T^k)_00, k = 0..kmax, T the tridiagonal matrix of the
+    floors given (exact for k <= 2 len(a) - 1)."""
+    K = len(a)
+    T = np.diag(np.asarray(a, dtype=float))
+    if K > 1:
+        off = np.sqrt(np.maximum(np.asarray(b2, dtype=float), 0.0))
+        T += np.diag(off, 1) + np.diag(off, -1)
+    e = np.zeros(K)
+    e[0] = 1.0
+    out = []
+    x = e.copy()
+    for _ in range(kmax + 1):
+        out.append(b0sq * x[0])
+        x = T @ x
+    return np.array(out)
 
 
 def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
@@ -300,9 +318,14 @@ def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
     whether every chain of the oracle ended by exhausting its Krylov space
     (only then is the 100-floor G independent of rounding; truncated chains
     without reorthogonalisation differ run to run, in either precision).
-    Also the well-posed part of every chain: its first K = 12 floors (a_n and
-    b_n^2 relative to max(1, |a|)) and the G those floors give on the grid,
-    which rounding does not move before orthogonality is lost."""
+    Also the well-conditioned part of every chain: the spectral moments
+    mu_k = <phi| H^k |phi> = b0^2 (T^k)_00, k <= 8, which its first five floors
+    fix exactly (T their tridiagonal matrix), relative to b0^2 S^k with S the
+    largest |a_n| or b_n of those floors.  The coefficients themselves are
+    not: where a chain starts in a cluster of close eigenvalues they amplify a
+    start-vector change about tenfold per floor (FP32 storage, 1e-7, moves a_4
+    by 2e-4 on a 7-orbital request; the FP64 chains agree with the oracle to
+    1e-9 through floor 11 on the 3x4 cluster)."""
     import oracle
     from oracle import cf
     recs = []
@@ -321,28 +344,24 @@ def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
             r = res[i]
             b0 = [r["coef"][p, part, 0] for p in range(10) for part in (0, 1)]
             b0o = [ch[k][0] for k in keys]
-            # the first K floors of each chain, on both sides
-            chk, chko, dcoef = {}, {}, 0.0
+            # spectral moments from the first floors of each chain, both sides
+            dmom = 0.0
             for n, k in enumerate(keys):
                 p, part = n // 2, n % 2
                 bo, ao, b2o = ch[k]
-                K = min(K_FLOORS, int(r["len"][p, part]), len(ao))
-                ag = r["coef"][p, part, 1:1 + K]
-                b2g = r["coef"][p, part, 1 + gf_steps:gf_steps + K]
-                sc = max(1.0, float(np.abs(ao[:K]).max())) if K else 1.0
-                if K:
-                    dcoef = max(dcoef, float(np.abs(ag - ao[:K]).max()) / sc)
-                if K > 1:
-                    dcoef = max(dcoef, float(np.abs(b2g - b2o[:K - 1]).max()) / sc)
-                chk[k] = (r["coef"][p, part, 0], ag, b2g)
-                chko[k] = (bo, ao[:K], b2o[:K - 1])
-            GK = cf.green_matrix(chk, 4, z, r["e0"])
-            GKo = cf.green_matrix(chko, 4, z, ro["e0"])
+                K = min(MOMENT_FLOORS, int(r["len"][p, part]), len(ao))
+                if K == 0 or bo == 0.0:
+                    continue
+                mg = _moments(r["coef"][p, part, 0], r["coef"][p, part, 1:1 + K],
+                              r["coef"][p, part, 1 + gf_steps:gf_steps + K], 2 * K - 2, np)
+                mo = _moments(bo, ao[:K], b2o[:K - 1], 2 * K - 2, np)
+                S = max(1.0, float(np.abs(ao[:K]).max()), float(np.sqrt(np.max(b2o[:K - 1]))) if K > 1 else 0.0)
+                scale = bo * S ** np.arange(mo.shape[0])
+                dmom = max(dmom, float(np.max(np.abs(mg - mo) / scale)))
             rec[prec] = {"rel_dE0": abs(r["e0"] - ro["e0"]) / abs(ro["e0"]),
                          "max_dG": float(np.abs(r["G"] - Go).max()),
                          "max_db0sq": float(np.max(np.abs(np.array(b0) - np.array(b0o)))),
-                         "max_rel_dcoef_12floors": dcoef,
-                         "max_dG_12floors": float(np.abs(GK - GKo).max()),
+                         "max_rel_dmoment": dmom,
                          "degenerate_suspect": bool(r["degenerate_suspect"])}
         recs.append(rec)
     summ = {}
@@ -357,8 +376,7 @@ def oracle_accuracy(models, results_by_prec, idx, z, np, gf_steps=100):
                 "max_dG": max(r[prec]["max_dG"] for r in sel),
                 "median_dG": float(np.median([r[prec]["max_dG"] for r in sel])),
                 "max_db0sq": max(r[prec]["max_db0sq"] for r in sel),
-                "max_rel_dcoef_12floors": max(r[prec]["max_rel_dcoef_12floors"] for r in sel),
-                "max_dG_12floors": max(r[prec]["max_dG_12floors"] for r in sel),
+                "max_rel_dmoment_k8": max(r[prec]["max_rel_dmoment"] for r in sel),
                 "degenerate_suspect_jobs": sum(r[prec]["degenerate_suspect"] for r in sel)}
     return summ, recs
 
@@ -753,6 +771,7 @@ def serving_section(args, torch, q, synth, np):
         print(f"serving x{mult}: p99 {serving.nearest_rank(lat, 99):.3f} s", file=sys.stderr,
               flush=True)
     out["peak_pool_GB"] = round(eng.info()["peak_in_use"] / 1e9, 3)
+    torch.cuda.empty_cache()   # blocks cached by earlier sections are not the engine's
     free, total = torch.cuda.mem_get_info()
     out["device_memory_in_use_GB"] = round((total - free) / 1e9, 3)
     out["device_memory_GB"] = round(total / 1e9, 3)

@@ -241,9 +241,9 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
 
 // Pass B: W += K_dn V on column slabs, hopping lists row-contiguous and
 // wave-uniform (scalar loads), RI rows of a wave with 8 neighbour segments
-// each in flight (FP64 with two columns per lane: RI = 4, 2.5 % faster than 2
-// on the 4x4 sector, while 1, 6 or 8 rows, or 32-row slabs, were slower;
-// FP32 vectors keep RI = 2, four rows slowed them from 2.95 to 4.06 ms).  When
+// each in flight (RI: chosen at the launch below; for the FP64 product four
+// rows were 2.5 % faster than two on the 4x4 sector, while 1, 6 or 8 rows, or
+// 32-row slabs, were slower).  When
 // d_up is even a lane takes two adjacent columns (one 2-element load per
 // neighbour), which halves the load instructions.  Within a slab the rows are
 // taken in row_order: grouped by the popcount of the high half of the down
@@ -463,7 +463,11 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
         else                                                                                   \
             QCM_PK_U(KS_, false);                                                              \
     } else
-    QCM_PK(4) QCM_PK(8) QCM_PK(12) QCM_PK(16) { return fail(QCM_EARG, "in-row pass: row too long"); }
+    // one instantiation per slot count, so that no slot past the row is
+    // carried through the hop loop (4x4 H.v 2.70 -> 2.67 ms with 13 slots
+    // instead of 16)
+    QCM_PK(4) QCM_PK(5) QCM_PK(6) QCM_PK(7) QCM_PK(8) QCM_PK(9) QCM_PK(10) QCM_PK(11) QCM_PK(12)
+    QCM_PK(13) QCM_PK(14) QCM_PK(15) QCM_PK(16) { return fail(QCM_EARG, "in-row pass: row too long"); }
 #undef QCM_PK
 #undef QCM_PK_U
 #undef QCM_PK_L
@@ -488,13 +492,17 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
                 d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
                 (T *)w, R, nrb, total, per, op.row_order, none);                             \
     } while (0)
-    // FP64 keeps four rows in flight for the product alone; the Lanczos form
-    // (its epilogue needs more registers) is faster with two, which leave
-    // room for five waves per SIMD instead of three
+    // Rows in flight per wave, measured on the 4x4 sector: FP64 keeps four
+    // for the product alone; its Lanczos form (the epilogue needs more
+    // registers) is faster with two, which leave room for five waves per SIMD
+    // instead of three; FP32 vectors are fastest with one (product 2.80 ->
+    // 2.55 ms, step 3.97 -> 3.28 ms against two).
     if (cw == 2 && sizeof(T) == 8 && !sp)
         QCM_DACC(4, 2);
-    else if (cw == 2)
+    else if (cw == 2 && sizeof(T) == 8)
         QCM_DACC(2, 2);
+    else if (cw == 2)
+        QCM_DACC(1, 2);
     else
         QCM_DACC(2, 1);
 #undef QCM_DACC
