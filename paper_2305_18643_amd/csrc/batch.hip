@@ -449,9 +449,11 @@ static int launch_round(qcm_engine *E, int ng, int na, int nc, size_t lds, const
     if (ng > 0) {
         const unsigned nh = (unsigned)hvb[ng], nk = (unsigned)chb[ng], nn = (unsigned)cnb[ng];
         ks_hv<T, TabSrc><<<nh, 256, lds, s>>>(hv);
-        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 0);
-        ks_norm<T, TabSrc><<<nk, 256, 0, s>>>(ch);
-        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 1);
+        // alpha and beta from the product's dots; the direct norm pass only
+        // for chains whose beta the dots cannot resolve
+        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 3);
+        ks_norm<T, TabSrc><<<nk, 256, 0, s>>>(ch, 1);
+        ks_finish<TabSrc><<<nn, 256, 0, s>>>(cn, 4);
         ks_update<T, TabSrc><<<nk, 256, 0, s>>>(ch);
     }
     if (nc > 0) kb_control<<<nc, 256, 0, s>>>(C, E->d_stat);

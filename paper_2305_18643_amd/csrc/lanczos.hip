@@ -148,24 +148,6 @@ __global__ void __launch_bounds__(256) k_tridiag_status(const double *__restrict
 
 // ---------------------------------------------------------------- engine
 
-size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs) {
-    Carver cv(nullptr);
-    const size_t s = prec == QCM_FP64 ? 8 : 4;
-    const int64_t dim = d_up * d_dn;
-    cv.take<char>(3 * s * (size_t)nvec * dim + 64);
-    int64_t nch = (int64_t)ceil_div(dim, kChunk);
-    if (nch < 1) nch = 1;
-    int32_t rows, nblk;
-    row_shape(d_up, d_dn, prec, &rows, &nblk);
-    cv.take<double>((size_t)nvec * nch);
-    cv.take<double>((size_t)nvec * (nblk > nch ? nblk : nch));
-    cv.take<double>((size_t)nvec * std::max<size_t>(3 * (size_t)nch, 5 * kDotBlocks));
-    cv.take<double>((size_t)nvec * maxs * 2);
-    cv.take<double>((size_t)nvec * 7);
-    cv.take<int32_t>((size_t)nvec * 2);
-    return cv.off + 256;
-}
-
 int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double btol, int reorth,
                 Carver &cv) {
     e.op = op;
@@ -192,8 +174,9 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.partial = cv.take<double>((size_t)nvec * e.nchunks);
     int64_t npa = e.nblk > e.nchunks ? e.nblk : e.nchunks;
     if (e.na > npa) npa = e.na;
-    // the two-pass product keeps five partial arrays (alpha and the norm dots)
-    e.pa = cv.take<double>((size_t)nvec * npa * (op.split ? 5 : 1));
+    // five partial arrays (alpha and the norm dots of the fused or two-pass
+    // product)
+    e.pa = cv.take<double>((size_t)nvec * npa * 5);
     // norm partials, or the two-pass step's per-range dot sums
     e.pn = cv.take<double>((size_t)nvec * std::max<size_t>(3 * (size_t)e.nchunks, 5 * kDotBlocks));
     e.cs.maxs = maxs;
@@ -208,9 +191,10 @@ int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double 
     e.cs.b0sq = sc + 4 * nvec;
     e.scratch = sc + 5 * nvec;
     e.cs.apre = sc + 6 * nvec;
-    int32_t *ic = cv.take<int32_t>((size_t)nvec * 2);
+    int32_t *ic = cv.take<int32_t>((size_t)nvec * 3);
     e.cs.len = ic;
     e.cs.done = ic + nvec;
+    e.cs.renorm = ic + 2 * nvec;
     e.ivp = 0;
     e.iv = 1;
     e.iw = 2;
@@ -223,7 +207,7 @@ int engine_reset(Engine &e, hipStream_t s) {
     QCM_HIP(hipMemsetAsync(e.cs.alpha, 0, sizeof(double) * e.nvec * e.maxs, s));
     QCM_HIP(hipMemsetAsync(e.cs.beta, 0, sizeof(double) * e.nvec * e.maxs, s));
     QCM_HIP(hipMemsetAsync(e.cs.amax, 0, sizeof(double) * e.nvec * 7, s));
-    QCM_HIP(hipMemsetAsync(e.cs.len, 0, sizeof(int32_t) * e.nvec * 2, s));
+    QCM_HIP(hipMemsetAsync(e.cs.len, 0, sizeof(int32_t) * e.nvec * 3, s));
     size_t sz = (e.prec == QCM_FP64 ? 8 : 4) * (size_t)e.nvec * e.dim;
     e.ivp = 0;
     e.iv = 1;
@@ -311,13 +295,22 @@ static int step_t(Engine &e, int n, hipStream_t s) {
         // alpha, then beta from the product's dots: no norm pass
         ks_dots_stage<OneSrc><<<dim3(kDotBlocks, (unsigned)e.nvec), 256, 0, s>>>(src);
         ks_finish_dots<OneSrc><<<e.nvec, kDotBlocks, 0, s>>>(src);
+        // chains whose beta the dots cannot resolve take the direct norm
+        ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src, 1);
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 4);
     } else {
         QCM_TRY(hv_launch(e.op, e.prec, e.vbuf[e.iv], e.vbuf[e.iw], e.nvec, s));
         ks_sub_prev<T, OneSrc><<<nk, 256, 0, s>>>(src);
     }
-    if (!e.op.split) {
+    if (e.fused) {
+        // alpha and beta from the fused product's dots; the direct norm pass
+        // only for chains whose beta the dots cannot resolve
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 3);
+        ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src, 1);
+        ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 4);
+    } else if (!e.op.split) {
         ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 0);
-        ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src);
+        ks_norm<T, OneSrc><<<nk, 256, 0, s>>>(src, 0);
         ks_finish<OneSrc><<<e.nvec, 256, 0, s>>>(src, 1);
     }
     if (e.op.split && e.lazy)

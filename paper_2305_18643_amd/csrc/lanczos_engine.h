@@ -23,6 +23,7 @@ struct ChainState {
     double *b0sq;   // <phi|phi> of the start vector
     int32_t *len;   // number of steps recorded
     int32_t *done;  // chain stopped (breakdown or empty start)
+    int32_t *renorm;  // this step's beta needs the direct norm pass (see ks_finish)
 };
 
 struct GsStatus {
@@ -50,7 +51,6 @@ struct Engine {
     ChainState cs;
 };
 
-size_t engine_bytes(int prec, int nvec, int64_t d_up, int64_t d_dn, int maxs);
 int engine_init(Engine &e, const HvOp &op, int prec, int nvec, int maxs, double btol, int reorth,
                 Carver &cv);
 int engine_reset(Engine &e, hipStream_t s);

@@ -4,8 +4,10 @@
 // A group is nvec chains in one sector (vectors [nvec][dim], consecutive).
 // With v = v_n, vp = v_{n-1}, beta' = beta_{n-1}:
 //   pass 1  w = H v - beta' vp, stored; partial sums of <v, w>
-//           (fused into the product when rows of V fit in LDS; otherwise the
-//           product runs first and a chunked pass subtracts and sums);
+//           (fused into the product when rows of V fit in LDS, with the dots
+//           <w, w>, <v, v> (<vp, w>, <vp, v>) that then replace pass 2;
+//           otherwise the product runs first and a chunked pass subtracts and
+//           sums);
 //   finish  alpha_n = <v, w>;
 //   pass 2  x = w - alpha_n v (not stored): partial sums of |x|^2 and, with
 //           local reorthogonalisation, of <v, x> and <vp, x> (after the
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
     __syncthreads();
     const uint32_t du = (uint32_t)d_up;
-    double pa = 0.0;
+    double pa = 0.0, pww = 0.0, pvv = 0.0, ppw = 0.0, ppv = 0.0;
     // one element: diagonal, in-row hops through the packed entries, row-mixing
     // hops from global memory, -beta vp, rounded once
     // diagonal and in-row part of one element: returns the partial sum and v_i
@@ -187,12 +189,21 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
         }
         return acc;
     };
-    // -beta vp, round once, store, and the <v, w> partial
+    // -beta vp, round once, store, and the partials <v, w>, <w, w>, <v, v>
+    // (with reorthogonalisation also <vp, w>, <vp, v>)
     auto finish = [&](int64_t i, double acc, double vi) {
-        if (sub) acc = fma(-b, ldd(vp + i), acc);
+        const double pv = sub ? ldd(vp + i) : 0.0;
+        if (sub) acc = fma(-b, pv, acc);
         const T wt = (T)acc;
         w[i] = wt;
-        pa = fma(vi, (double)wt, pa);
+        const double wd = (double)wt;
+        pa = fma(vi, wd, pa);
+        pww = fma(wd, wd, pww);
+        pvv = fma(vi, vi, pvv);
+        if (q.reorth) {
+            ppw = fma(pv, wd, ppw);
+            ppv = fma(pv, vi, ppv);
+        }
     };
     // one element: diagonal, in-row hops through the packed entries, row-mixing
     // hops from global memory, -beta vp, rounded once
@@ -283,8 +294,23 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
         }
     }
     if (q.pa) {
-        const double t = block_sum(pa, sh);
-        if (threadIdx.x == 0) q.pa[vec * q.na + rb] = t;
+        double *o = q.pa + vec * q.na + rb;
+        const double t0 = block_sum(pa, sh);
+        const double t1 = block_sum(pww, sh);
+        const double t2 = block_sum(pvv, sh);
+        if (threadIdx.x == 0) {
+            o[0] = t0;
+            o[q.pstride] = t1;
+            o[2 * q.pstride] = t2;
+        }
+        if (q.reorth) {
+            const double t3 = block_sum(ppw, sh);
+            const double t4 = block_sum(ppv, sh);
+            if (threadIdx.x == 0) {
+                o[3 * q.pstride] = t3;
+                o[4 * q.pstride] = t4;
+            }
+        }
     }
 }
 
@@ -330,13 +356,15 @@ __global__ void __launch_bounds__(256) ks_sub_prev(Src src) {
     if (threadIdx.x == 0) q.pa[at.vec * q.na + at.c] = s;
 }
 
-// pass 2: partial |x|^2 (and <v, x>, <vp, x>) with x = w - alpha_n v
+// pass 2: partial |x|^2 (and <v, x>, <vp, x>) with x = w - alpha_n v; with
+// cond, only for chains whose dot-based finish asked for it (cs.renorm)
 template <typename T, class Src>
-__global__ void __launch_bounds__(256) ks_norm(Src src) {
+__global__ void __launch_bounds__(256) ks_norm(Src src, int cond) {
     __shared__ double sh[256];
     int64_t local;
     const BGroup &q = src.at(blockIdx.x, &local);
     const ChunkAt at = chunk_of(q, local);
+    if (cond && !q.cs.renorm[at.vec]) return;
     const double a = q.cs.alpha[at.vec * q.cs.maxs + q.n];
     const int64_t off = at.vec * q.dim;
     const T *w = (const T *)q.w + off;
@@ -392,6 +420,12 @@ __device__ __forceinline__ double strided_sum(const double *__restrict__ p, int6
     return acc;
 }
 
+// The dots give |x|^2 = <w,w> - 2 a <v,w> + a^2 <v,v> with an absolute
+// error of a few eps <w,w>; below kDotRel <w,w> (beta < 0.03 |w|) that is no
+// longer beta to about 1e-12, and the chain takes the direct norm pass
+// (cs.renorm) instead, as near a breakdown or an exhausted Krylov space.
+constexpr double kDotRel = 1e-3;
+
 // beta_n from |x|^2 and the reorthogonalisation terms c1 = <v, x>,
 // c2 = <vp, x> of x = w - alpha_n v, and the chain's bookkeeping
 __device__ __forceinline__ void finish_beta(const ChainState &cs, int c, int n, int reorth,
@@ -413,7 +447,10 @@ __device__ __forceinline__ void finish_beta(const ChainState &cs, int c, int n, 
 // per-chain sums of the partials and the recurrence bookkeeping
 // mode 0: alpha_n; mode 1: reorthogonalisation terms, beta_n, breakdown, from
 // the norm pass; mode 2: the same from the dots of the two-pass product
-// (pa: <v,w>, <w,w>, and with reorthogonalisation <v,v>, <vp,w>, <vp,v>).
+// (pa: <v,w>, <w,w>, <v,v>, and with reorthogonalisation <vp,w>, <vp,v>);
+// mode 3: modes 0 and 2 together, from the fused product's dots (same
+// layout, q.na partials per chain), unless the dots cannot resolve beta
+// (cs.renorm); mode 4: mode 1 for the chains so marked.
 template <class Src>
 __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
     __shared__ double sh[256];
@@ -434,6 +471,28 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         }
         return;
     }
+    if (mode == 3) {
+        const double *p = q.pa + (int64_t)c * q.na;
+        const double vw = block_sum(strided_sum(p, q.na), sh);
+        const double ww = block_sum(strided_sum(p + q.pstride, q.na), sh);
+        const double vv = block_sum(strided_sum(p + 2 * q.pstride, q.na), sh);
+        double pw = 0.0, pv = 0.0;
+        if (q.reorth) {
+            pw = block_sum(strided_sum(p + 3 * q.pstride, q.na), sh);
+            pv = block_sum(strided_sum(p + 4 * q.pstride, q.na), sh);
+        }
+        if (threadIdx.x != 0) return;
+        cs.alpha[(int64_t)c * cs.maxs + n] = vw;
+        cs.apre[c] = vw;
+        if (fabs(vw) > cs.amax[c]) cs.amax[c] = fabs(vw);
+        const double a = vw;
+        const double s0 = fma(a * a, vv, fma(-2.0 * a, a, ww));
+        const double s1 = q.reorth ? fma(-a, vv, a) : 0.0;
+        const double s2 = q.reorth ? fma(-a, pv, pw) : 0.0;
+        cs.renorm[c] = !(s0 > kDotRel * ww);
+        if (!cs.renorm[c]) finish_beta(cs, c, n, q.reorth, s0, s1, s2);
+        return;
+    }
     if (mode == 2) {
         const double *p = q.pa + (int64_t)c * q.na;
         const double ww = block_sum(strided_sum(p + q.pstride, q.na), sh);
@@ -452,6 +511,7 @@ __global__ void __launch_bounds__(256) ks_finish(Src src, int mode) {
         finish_beta(cs, c, n, q.reorth, s0, s1, s2);
         return;
     }
+    if (mode == 4 && !cs.renorm[c]) return;
     const double *p = q.pn + (int64_t)c * 3 * q.nchunks;
     const double s0 = block_sum(strided_sum(p, q.nchunks), sh);
     double s1 = 0.0, s2 = 0.0;
@@ -528,12 +588,14 @@ __global__ void __launch_bounds__(kDotBlocks) ks_finish_dots(Src src) {
     cs.alpha[(int64_t)c * cs.maxs + n] = vw;
     cs.apre[c] = vw;
     if (fabs(vw) > cs.amax[c]) cs.amax[c] = fabs(vw);
-    // mode 2: x = w - a v: |x|^2, <v, x>, <vp, x> from the dots
+    // mode 2: x = w - a v: |x|^2, <v, x>, <vp, x> from the dots (or the
+    // direct norm pass when they cannot resolve beta)
     const double a = vw;
     const double s0 = fma(a * a, vv, fma(-2.0 * a, a, ww));
     const double s1 = q.reorth ? fma(-a, vv, a) : 0.0;
     const double s2 = q.reorth ? fma(-a, pv, pw) : 0.0;
-    finish_beta(cs, c, n, q.reorth, s0, s1, s2);
+    cs.renorm[c] = !(s0 > kDotRel * ww);
+    if (!cs.renorm[c]) finish_beta(cs, c, n, q.reorth, s0, s1, s2);
 }
 
 // pass 3: w = (w - alpha v - c1 v - c2 vp) / beta_n; psi += svec[n] v (replay)
