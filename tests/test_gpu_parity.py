@@ -188,6 +188,27 @@ def test_fixed_steps_and_breakdown(q):
     assert abs(r["e0"] + 12.0) < 1e-12
 
 
+def test_breakdown_long_rows(q):
+    # the same on a long-row sector (16 orbitals, (8, 1): the two-pass step
+    # with the deferred update): t = 0 but mu = 3, U = 6, so H has the two
+    # eigenvalues -27 and -21 and the Krylov space is exhausted at step 2.
+    # The step's dots give |x|^2 only to a few eps <w,w>, far above a
+    # vanishing beta; the direct norm pass must take over and stop the chain.
+    # FP32 vectors leave a residual of ~1e-7 |w| after the space is exhausted
+    # (their storage floors it), so there no breakdown is detected; the steps
+    # past exhaustion run on that noise and E0 is checked at the FP32 storage
+    # level (relative 1e-6; observed 1.3e-7).
+    L = 16
+    t = np.diag(np.full(L, -3.0))
+    U = np.full(L, 6.0)
+    b = q.sector_basis(L, 8, 1)
+    r = q.lanczos_gs((t, U), b, fixed_steps=40)
+    assert r["breakdown"] and r["n_iter"] <= 3, r["n_iter"]
+    assert abs(r["e0"] + 27.0) < 1e-12, r["e0"]
+    r = q.lanczos_gs((t, U), b, fixed_steps=40, prec="fp32v", reorth=1)
+    assert abs(r["e0"] + 27.0) < 27.0 * 1e-6, r["e0"]
+
+
 def test_degenerate_suspect_flag(q):
     # near-degenerate: two identical dimers (t = -1) coupled by 1e-10, one up
     # electron: the lowest two one-body levels are -1 -+ 5e-11, which the
