@@ -317,6 +317,40 @@ def test_green_full_reorth(q, m, steps, exhaust, prec):
     assert worst <= (1e-9 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32v"])
+def test_green_long_rows(q, prec):
+    """Continued fractions whose sectors have long rows (16 orbitals, ground
+    state in (8, 1); the electron part (9, 1) and the hole part (7, 1) have
+    rows of 11,440 strings): several chains per launch through the two-pass
+    step, its dots and its deferred updates.  From the oracle's ground state,
+    b0^2 of every chain to 1e-12 and the first 12 floors to 1e-9 (FP32
+    vectors: 1e-6 and the first 4 floors to 1e-5)."""
+    torch = _torch()
+    m = synth.rect_cluster(4, 4, U=8.0, mu=4.0, nup=8, ndn=1, name="4x4r")
+    print(f"green long rows {m.name} {prec}", flush=True)
+    b = q.sector_basis(m.L, m.nup, m.ndn)
+    ro = oracle.lanczos_gs(m.t, m.U, m.nup, m.ndn, want_vector=True)
+    psi = torch.from_numpy(ro["psi"]).to("cuda")
+    orbs = [0, 5, 10, 15]
+    g = q.green_cf(m, b, psi, ro["e0"], orbs, Z64, max_steps=12, prec=prec,
+                   reorth=1 if prec == "fp32v" else 0)
+    ch = oracle.green_cf(m.t, m.U, m.nup, m.ndn, ro["psi"], orbs, max_steps=12)
+    p = 0
+    worst = worst_b0 = 0.0
+    for i in range(len(orbs)):
+        for j in range(i, len(orbs)):
+            for part in (0, 1):
+                b0, a, b2 = ch[(i, j, part)]
+                co = g["coef"][p, part]
+                worst_b0 = max(worst_b0, abs(co[0] - b0))
+                k = min(len(a), 12 if prec == "fp64" else 4)
+                worst = max(worst, np.abs(co[1:1 + k] - a[:k]).max() / max(1.0, np.abs(a).max()))
+            p += 1
+    print(f"  b0^2 {worst_b0:.2e}; first floors: max |da| / max |a| = {worst:.2e}")
+    assert worst_b0 <= (1e-12 if prec == "fp64" else 1e-6)
+    assert worst <= (1e-9 if prec == "fp64" else 1e-5)
+
+
 def test_cpt_2x2(q):
     torch = _torch()
     m = synth.plaquette_2x2()
