@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "lanczos_device.h"
@@ -65,7 +66,13 @@ __global__ void k_pack_tiles(int64_t d, const int32_t *__restrict__ nh,
 // its entries are tile-major, so every lane runs the same hop loop with no
 // masking and the entry loads are one contiguous 256-byte load per slot from
 // a wave-uniform base; slots past a lane's own hops read the zero slot.  Eight
-// entries are loaded, then eight neighbours gathered from LDS, then summed.
+// entries are loaded, then eight neighbours gathered from LDS, then summed; a
+// tile's slot count is its largest hop count rounded up to four, the last
+// four taken as a group of their own (4x4 sector: 19.0 slots per string
+// instead of 21.4 with counts rounded up to eight; H.v 2.63 -> 2.60 ms in
+// FP64, 2.60 -> 2.54 ms in FP32).  Ordering each tile span's strings by hop
+// count (15-17 slots) was measured slower: their products are then stored
+// scattered over the span, which costs more than the slots it saves.
 // The row sits at LDS address 0, so the masked entry is the gather address
 // (halved for FP32 rows).  When every bond has the same t (UT), a coefficient
 // is +-t: the entry's sign bit flips the sign of the neighbour value and the
@@ -212,18 +219,20 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
                 }
                 acc = diag * (double)row[iu];
             }
-            for (int s = 0; s < nt; s += kTileChunk) {
-                uint32_t p[kTileChunk];
+            // n entries from slot s: loaded, gathered, then summed in slot order
+            auto group = [&](const int s, auto n_) {
+                constexpr int n = decltype(n_)::value;
+                uint32_t p[n];
 #pragma unroll
-                for (int u = 0; u < kTileChunk; ++u) p[u] = eb[(s + u) * 64];
-                double x[kTileChunk];
+                for (int u = 0; u < n; ++u) p[u] = eb[(s + u) * 64];
+                double x[n];
 #pragma unroll
-                for (int u = 0; u < kTileChunk; ++u) {
+                for (int u = 0; u < n; ++u) {
                     const uint32_t off = sizeof(T) == 8 ? (p[u] & 0x1ffffu) : ((p[u] & 0x1ffffu) >> 1);
                     x[u] = (double)*(lds_t *)(size_t)off;
                 }
 #pragma unroll
-                for (int u = 0; u < kTileChunk; ++u) {
+                for (int u = 0; u < n; ++u) {
                     if constexpr (UT) {
                         const double xs = __hiloint2double(
                             __double2hiint(x[u]) ^ (int)(p[u] & 0x80000000u), __double2loint(x[u]));
@@ -232,7 +241,11 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
                         acc = fma(ct[(p[u] >> 17) & 0x3fffu], x[u], acc);
                     }
                 }
-            }
+            };
+            int s = 0;
+            for (; s + kTileChunk <= nt; s += kTileChunk)
+                group(s, std::integral_constant<int, kTileChunk>{});
+            if (s < nt) group(s, std::integral_constant<int, kTileChunk / 2>{});
             if (in) __builtin_nontemporal_store((T)acc, wrow + iu);
         }
         if (LZ) {
@@ -608,7 +621,7 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
         for (int tt = 0; tt < op.ntile; ++tt) {
             int mx = 0;
             for (int l = 0; l < 64 && tt * 64 + l < du; ++l) mx = std::max(mx, nh[tt * 64 + l]);
-            tnt[tt] = (mx + kTileChunk - 1) / kTileChunk * kTileChunk;
+            tnt[tt] = (mx + 3) / 4 * 4;
             toff[tt] = o;
             o += tnt[tt] * 64;
         }

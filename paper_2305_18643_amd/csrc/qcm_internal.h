@@ -155,7 +155,7 @@ struct HvOp {
     int split = 0;
     // in-row pass by 64-column tiles: the packed up hops (LDS offset | coefficient
     // index | sign) of tile t at tile_ent[tile_off[t] + s * 64 + lane], s <
-    // tile_nt[t] (the tile's largest hop count rounded up to 8, padded with
+    // tile_nt[t] (the tile's largest hop count rounded up to 4, padded with
     // entries that read a zero slot)
     uint32_t *tile_ent = nullptr;
     int32_t *tile_nt = nullptr, *tile_off = nullptr;
