@@ -154,9 +154,9 @@ struct HvOp {
     // two-pass path for long rows (see hv_split.hip); used when split != 0
     int split = 0;
     // in-row pass by 64-column tiles: the packed up hops (LDS offset | coefficient
-    // index | sign) of tile t at tile_ent[tile_off[t] + s * 64 + lane], s <
-    // tile_nt[t] (the tile's largest hop count rounded up to 4, padded with
-    // entries that read a zero slot)
+    // index | sign) of tile t at tile_ent[tile_off[t] + (s / 4) * 256 + lane * 4
+    // + s % 4], s < tile_nt[t] (the tile's largest hop count rounded up to 4,
+    // padded with entries that read a zero slot)
     uint32_t *tile_ent = nullptr;
     int32_t *tile_nt = nullptr, *tile_off = nullptr;
     int32_t ntile = 0;
