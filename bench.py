@@ -282,6 +282,23 @@ def solve_single_fp64(q, m, z, gf_steps, stream=None):
     return r["e0"], g["G"]
 
 
+def floor_bytes(m, r, s_el):
+    """Bytes of one solve at the Lanczos step's floor of 3 s d (read v_n and
+    v_{n-1}, write v_{n+1}): the ground-state recurrence and its replay for
+    the vector (2 n_iter steps on the ground-state sector), then every chain
+    step on its own sector (electron chains add an up electron, hole chains
+    remove one)."""
+    from math import comb
+    L, nu, nd = m.L, m.nup, m.ndn
+    d_gs = comb(L, nu) * comb(L, nd)
+    d_e = comb(L, nu + 1) * comb(L, nd) if nu < L else 0
+    d_h = comb(L, nu - 1) * comb(L, nd) if nu > 0 else 0
+    steps = 2 * int(r["n_iter"]) * d_gs
+    if r.get("len") is not None:
+        steps += int(r["len"][:, 0].sum()) * d_e + int(r["len"][:, 1].sum()) * d_h
+    return 3 * s_el * steps
+
+
 def engine_opts_for(prec):
     # residual test: the engine's automatic tolerance (1e-12 in FP64, 1e-7
     # with FP32 vectors, whose rounding floors the residual estimate)
@@ -658,9 +675,12 @@ def batched_section(args, torch, q, synth, np):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[prec] = rr
+        fb = sum(floor_bytes(m, r, 4 if prec == "fp32v" else 8) for m, r in zip(ms, rr))
         out[f"engine_{prec}"] = {"s": round(dt, 3), "solves_per_s": round(len(ms) / dt, 2),
                                  "pool_GB": round(need / 1e9, 2),
-                                 "gs_steps_mean": round(float(np.mean([r["n_iter"] for r in rr])), 1)}
+                                 "gs_steps_mean": round(float(np.mean([r["n_iter"] for r in rr])), 1),
+                                 "floor_GB": round(fb / 1e9, 1),
+                                 "GBps_floor": round(fb / dt / 1e9, 1)}
         print(f"batched engine {prec}: {dt:.2f} s", file=sys.stderr, flush=True)
     # accuracy of FP32V against the FP64 engine
     e64 = np.array([r["e0"] for r in res["fp64"]])
@@ -694,7 +714,13 @@ def batched_section(args, torch, q, synth, np):
                   file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out["one_at_a_time_fp64"] = {"s": round(dt, 3), "solves_per_s": round(len(ms) / dt, 2)}
+    # the single calls take the FP64 engine's steps (equal bit for bit, below)
+    fb = sum(floor_bytes(m, r, 8) for m, r in zip(ms, res["fp64"]))
+    out["one_at_a_time_fp64"] = {"s": round(dt, 3), "solves_per_s": round(len(ms) / dt, 2),
+                                 "GBps_floor": round(fb / dt / 1e9, 1)}
+    out["floor_bytes"] = ("3 s d per Lanczos step (read v_n, v_{n-1}, write v_{n+1}) over the "
+                          "ground-state recurrence and its replay and every chain step, summed "
+                          "over the solves and divided by the wall time")
     out["speedup_fp32v_engine"] = round(dt / out["engine_fp32v"]["s"], 2)
     out["speedup_fp64_engine"] = round(dt / out["engine_fp64"]["s"], 2)
     # the FP64 engine equals the single-solve calls bit for bit
@@ -764,6 +790,8 @@ def serving_section(args, torch, q, synth, np):
             "engine_fp32v": {"p50_s": round(serving.nearest_rank(lat, 50), 4),
                              "p99_s": round(serving.nearest_rank(lat, 99), 4),
                              "solves_per_s": round(len(meas) / (done_at - arr[warm]), 3),
+                             "GBps_floor": round(sum(floor_bytes(reqs[t], rep.results[t], 4)
+                                                     for t in meas) / (done_at - arr[warm]) / 1e9, 1),
                              "max_in_flight": rep.max_in_flight},
             "fifo_fp64": {"p50_s": round(serving.nearest_rank(bl, 50), 4),
                           "p99_s": round(serving.nearest_rank(bl, 99), 4),
