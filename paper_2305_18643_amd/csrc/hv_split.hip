@@ -126,7 +126,9 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = kInrowThreads;   // the launch's block size
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, nwave = NT >> 6;
+    // the wave index as a scalar, so that the tile loop and its per-tile loads
+    // (slot count, table offset) are wave-uniform scalar work
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = NT >> 6;
     const int dup = (int)d_up;
     T *row = reinterpret_cast<T *>(smem);
     // zero slot: 64 bytes right after the row (a padding entry's offset 8 d_up,
