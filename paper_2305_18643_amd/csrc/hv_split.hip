@@ -119,7 +119,7 @@ template <typename T, int KS, bool UT, int LZ>
 __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     const int64_t d_up, const int64_t d_dn, const uint32_t *__restrict__ su,
     const double *__restrict__ eu, const int ntile, const int32_t *__restrict__ tnt,
-    const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent,
+    const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent, const int ent_bytes,
     const double *__restrict__ ctab_g, const int nctab, const uint32_t *__restrict__ sd,
     const double *__restrict__ ed, const double *__restrict__ ulut_g, const int nbytes,
     const double u_uniform, const double tu, T *__restrict__ v, T *w, const LazyUpd lz) {
@@ -180,6 +180,15 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
             for (int k = 0; k < KS; ++k) zr[k] = row_load<T>(rp, voff, k * sstep);
         }
     };
+    // the up strings' bits and diagonal, and the hop table, through buffer
+    // descriptors: a lane offset register and a scalar tile offset, with no
+    // 64-bit address arithmetic per tile or per group
+    const __amdgpu_buffer_rsrc_t rsu = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(su), (short)0, (int)(4 * d_up), 0x00020000);
+    const __amdgpu_buffer_rsrc_t reu = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(eu), (short)0, (int)(8 * d_up), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rent =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(ent), (short)0, ent_bytes, 0x00020000);
     int64_t r = blockIdx.x;
     if (r < d_dn) fetch(r);
     for (; r < d_dn; r += gridDim.x) {
@@ -208,17 +217,18 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
         if (rn < d_dn) fetch(rn);
         const uint32_t bd = sd[r];
         const double edn = ed[r];
-        T *wrow = ww + r * d_up;
+        const __amdgpu_buffer_rsrc_t rw = row_rsrc(ww + r * d_up, d_up);
         for (int tt = wave; tt < ntile; tt += nwave) {
             const int iu = tt * 64 + lane;
-            const int nt = __builtin_amdgcn_readfirstlane(tnt[tt]);
-            const u32x4_t *e4 =
-                reinterpret_cast<const u32x4_t *>(ent + __builtin_amdgcn_readfirstlane(toff[tt])) + lane;
+            const int nt = tnt[tt];
+            const int eoff = toff[tt] * 4;   // the tile's entries, in bytes
             const bool in = iu < dup;
             double acc = 0.0;
             if (in) {
-                const uint32_t dbl = su[iu] & bd;
-                double diag = eu[iu] + edn;
+                const uint32_t dbl =
+                    __builtin_amdgcn_raw_buffer_load_b32(rsu, lane * 4, tt * 256, 0) & bd;
+                double diag = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(reu, lane * 8, tt * 512, 0)) + edn;
                 if (u_uniform >= 0.0) {
                     diag += u_uniform * (double)__popc(dbl);
                 } else {
@@ -233,7 +243,9 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
                 uint32_t p[n];
 #pragma unroll
                 for (int u = 0; u < n; u += 4) {
-                    const u32x4_t q = e4[((s + u) >> 2) * 64];
+                    const u32x4_t q = __builtin_bit_cast(
+                        u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rent, lane * 16,
+                                                                        eoff + ((s + u) >> 2) * 1024, 0));
                     p[u] = q.x;
                     p[u + 1] = q.y;
                     p[u + 2] = q.z;
@@ -260,7 +272,8 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
             for (; s + kTileChunk <= nt; s += kTileChunk)
                 group(s, std::integral_constant<int, kTileChunk>{});
             if (s < nt) group(s, std::integral_constant<int, kTileChunk / 2>{});
-            if (in) __builtin_nontemporal_store((T)acc, wrow + iu);
+            // lanes past the row are dropped by the descriptor's range check
+            row_store<T>((T)acc, rw, lane * (int)sizeof(T), tt * 64 * (int)sizeof(T));
         }
         if (LZ) {
             // v_{n+1} of this row, from its LDS copy: stored after the hop
@@ -502,6 +515,7 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
 #define QCM_PK_L(KS_, UT_, LZ_)                                                                \
     k_hv_inrow_tile<T, KS_, UT_, LZ_><<<gp, 1024, lds, s>>>(                                   \
         d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off, op.tile_ent, \
+        op.tile_bytes,                                                                         \
         op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut, op.md.nbytes,                \
         op.md.u_uniform, op.md.t_uniform, (T *)v, (T *)w, lz)
 #define QCM_PK_U(KS_, UT_)                                                                     \
@@ -639,6 +653,7 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
             toff[tt] = o;
             o += tnt[tt] * 64;
         }
+        op.tile_bytes = 4 * o;
         QCM_HIP(hipMemcpyAsync(op.tile_nt, tnt.data(), sizeof(int32_t) * op.ntile,
                                hipMemcpyHostToDevice, s));
         QCM_HIP(hipMemcpyAsync(op.tile_off, toff.data(), sizeof(int32_t) * op.ntile,

@@ -159,6 +159,7 @@ struct HvOp {
     // padded with entries that read a zero slot)
     uint32_t *tile_ent = nullptr;
     int32_t *tile_nt = nullptr, *tile_off = nullptr;
+    int32_t tile_bytes = 0;       // bytes of tile_ent in use
     int32_t ntile = 0;
     HopTables hd_rm;              // down hops, row-major, with neighbour offsets
     int32_t *row_order = nullptr; // rows of V in the order the row-mixing pass takes them
