@@ -333,6 +333,8 @@ struct Pair<float> {
 // workgroup writes its partial <v, w> to sp.pa[vec * gridDim.x + block] (0
 // for workgroups without rows), a fixed-order block sum.
 
+typedef long long i64x8_t __attribute__((ext_vector_type(8), aligned(8)));
+
 template <typename T, int RI, int CW, bool SP>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
@@ -412,12 +414,21 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
             double cf[RI][8];
 #pragma unroll
             for (int q = 0; q < RI; ++q) {
-                const int64_t *ol = offs + rr[q] * W;
+                // the plain product takes the group's eight neighbour offsets
+                // as one 64-byte scalar load (entries past the row's hops, or
+                // past the table's last row into its slack, are loaded but not
+                // used), so that the neighbour loads are not each held up by a
+                // scalar load (4x4 FP32 product 2.32 -> 2.20 ms, FP64
+                // unchanged); the Lanczos form loads them one by one (its FP32
+                // step was 2 % slower with the batch)
+                const int64_t *olp = offs + rr[q] * W + s0;
+                i64x8_t ol;
+                if constexpr (!SP) ol = *reinterpret_cast<const i64x8_t *>(olp);
                 const double *cl = cfd + rr[q] * W;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const bool ok = s0 + u < nh[q];
-                    const int64_t jo = ok ? ol[s0 + u] : 0;
+                    const int64_t jo = ok ? (SP ? olp[u] : ol[u]) : 0;
                     cf[q][u] = ok ? cl[s0 + u] : 0.0;
                     if (CW == 2) {
                         T2 t2 = (ok && cok) ? *reinterpret_cast<const T2 *>(vv + jo + c0) : T2{};
@@ -480,7 +491,9 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
 // ---------------------------------------------------------------- set-up and launch
 
 int build_row_offsets(HopTables &ht, int64_t d_up, Carver &cv, hipStream_t s) {
-    ht.off = cv.take<int64_t>((size_t)ht.width * ht.d);
+    // eight entries of slack: the row-mixing pass reads a row's hops eight at
+    // a time
+    ht.off = cv.take<int64_t>((size_t)ht.width * ht.d + 8);
     if (!cv.base) return QCM_OK;
     const int64_t n = (int64_t)ht.width * ht.d;
     k_row_offsets<<<ceil_div(n, 256), 256, 0, s>>>(ht.d, ht.width, d_up, ht.col, ht.off);
