@@ -335,7 +335,7 @@ struct Pair<float> {
 
 typedef long long i64x8_t __attribute__((ext_vector_type(8), aligned(8)));
 
-template <typename T, int RI, int CW, bool SP>
+template <typename T, int RI, int CW, bool SP, bool BUF>
 __global__ void __launch_bounds__(256) k_hv_down_acc(
     const int64_t d_up, const int64_t d_dn, const int W, const int32_t *__restrict__ nhd,
     const int64_t *__restrict__ offs, const double *__restrict__ cfd, const T *__restrict__ v,
@@ -360,6 +360,11 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
     const T *vv = v + vb;
     T *ww = w + vb;
     const T *vpp = SP ? (const T *)sp.vp + vb : nullptr;
+    // BUF: the vector is under 2 GB, so a neighbour row's byte offset fits the
+    // 32-bit scalar offset of a buffer load
+    const __amdgpu_buffer_rsrc_t rvv = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T *>(vv), (short)0, BUF ? (int)(d_up * d_dn * (int64_t)sizeof(T)) : 0, 0x00020000);
+    const int lvo = (int)(c0 * (int64_t)sizeof(T));
     const double bprev = (SP && sp.n > 0) ? sp.beta[(int64_t)blockIdx.y * sp.maxs + sp.n - 1] : 0.0;
     double p_vw = 0.0, p_ww = 0.0, p_vv = 0.0, p_pw = 0.0, p_pv = 0.0;
     // the element as a separate pass would leave it: product rounded once,
@@ -430,7 +435,24 @@ __global__ void __launch_bounds__(256) k_hv_down_acc(
                     const bool ok = s0 + u < nh[q];
                     const int64_t jo = ok ? (SP ? olp[u] : ol[u]) : 0;
                     cf[q][u] = ok ? cl[s0 + u] : 0.0;
-                    if (CW == 2) {
+                    if (CW == 2 && BUF) {
+                        // through the vector's descriptor: the neighbour row
+                        // as a scalar offset, the lane's columns as a
+                        // constant register (lanes past the row read the
+                        // next row's columns, which they do not store; the
+                        // range check covers the last row)
+                        T2 t2 = T2{};
+                        if (ok) {
+                            if constexpr (sizeof(T) == 8)
+                                t2 = __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                rvv, lvo, (int)(jo * 8), 0));
+                            else
+                                t2 = __builtin_bit_cast(T2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                                rvv, lvo, (int)(jo * 4), 0));
+                        }
+                        x[q][u][0] = t2.x;
+                        x[q][u][CW - 1] = t2.y;
+                    } else if (CW == 2) {
                         T2 t2 = (ok && cok) ? *reinterpret_cast<const T2 *>(vv + jo + c0) : T2{};
                         x[q][u][0] = t2.x;
                         x[q][u][CW - 1] = t2.y;
@@ -565,16 +587,31 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
     const int64_t per = (total + 7) / 8;
     dim3 g1((unsigned)(8 * per), (unsigned)nvec);
     const SubPrev none{};
-#define QCM_DACC(RI, CW)                                                                     \
-    do {                                                                                     \
-        if (sp)                                                                              \
-            k_hv_down_acc<T, RI, CW, true><<<g1, 256, 0, s>>>(                               \
-                d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
-                (T *)w, R, nrb, total, per, op.row_order, *sp);                              \
-        else                                                                                 \
-            k_hv_down_acc<T, RI, CW, false><<<g1, 256, 0, s>>>(                              \
-                d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v,      \
-                (T *)w, R, nrb, total, per, op.row_order, none);                             \
+    // neighbour loads through the vector's descriptor when its byte offsets
+    // fit the 32-bit scalar offset (4x4 FP32 product 2.20 -> 1.74 ms, FP64
+    // unchanged)
+    const bool buf = d_up * d_dn * (int64_t)sizeof(T) < ((int64_t)1 << 31);
+#define QCM_DACC_K(RI, CW, SP_, BUF_, SPV)                                                     \
+    k_hv_down_acc<T, RI, CW, SP_, BUF_><<<g1, 256, 0, s>>>(                                    \
+        d_up, d_dn, hd_rm.width, hd_rm.nh, hd_rm.off, hd_rm.coef, (const T *)v, (T *)w, R, nrb, \
+        total, per, op.row_order, SPV)
+#define QCM_DACC(RI, CW)                                                                       \
+    do {                                                                                       \
+        if constexpr (CW == 2) {                                                               \
+            if (sp && buf)                                                                     \
+                QCM_DACC_K(RI, CW, true, true, *sp);                                           \
+            else if (sp)                                                                       \
+                QCM_DACC_K(RI, CW, true, false, *sp);                                          \
+            else if (buf)                                                                      \
+                QCM_DACC_K(RI, CW, false, true, none);                                         \
+            else                                                                               \
+                QCM_DACC_K(RI, CW, false, false, none);                                        \
+        } else {                                                                               \
+            if (sp)                                                                            \
+                QCM_DACC_K(RI, CW, true, false, *sp);                                          \
+            else                                                                               \
+                QCM_DACC_K(RI, CW, false, false, none);                                        \
+        }                                                                                      \
     } while (0)
     // Rows in flight per wave, measured on the 4x4 sector: FP64 keeps four
     // for the product alone; its Lanczos form (the epilogue needs more
@@ -590,6 +627,7 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
     else
         QCM_DACC(2, 1);
 #undef QCM_DACC
+#undef QCM_DACC_K
     QCM_LAUNCH_CHECK();
     return QCM_OK;
 }
