@@ -14,6 +14,26 @@ __device__ __forceinline__ double ldd(const T *p) {
     return (double)*p;
 }
 
+// Vectors and tables live in global memory, but a pointer read from a group
+// table in memory (the batched engine) is generic to the compiler, which then
+// emits flat accesses: those also count against the LDS counter, so every LDS
+// wait waits for them too.  Cast to the global address space, the same
+// accesses become global loads and stores.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T *p) {
+    return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ double ldd(gptr<const T> p) {
+    return (double)*p;
+}
+template <typename T>
+__device__ __forceinline__ double ldd(gptr<T> p) {
+    return (double)*p;
+}
+
 __device__ __forceinline__ double block_sum(double x, double *sh) {
     // 256 threads, fixed tree
     const int t = threadIdx.x;

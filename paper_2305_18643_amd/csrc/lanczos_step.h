@@ -141,15 +141,18 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     double *lut = reinterpret_cast<double *>(smem_raw);
     double *ct = lut + nlut;
     T *row = reinterpret_cast<T *>(ct + q.nctab);
-    const T *v = (const T *)q.v + vec * q.dim;
-    const T *vp = (const T *)q.vp + vec * q.dim;
-    T *w = (T *)q.w + vec * q.dim;
+    const auto v = gp((const T *)q.v) + vec * q.dim;
+    const auto vp = gp((const T *)q.vp) + vec * q.dim;
+    const auto w = gp((T *)q.w) + vec * q.dim;
+    const auto su = gp(q.su), pku = gp(q.pku), sd = gp(q.sd);
+    const auto nhu = gp(q.nhu), nhd = gp(q.nhd), cold = gp(q.cold);
+    const auto eu = gp(q.eu), ed = gp(q.ed), cfd = gp(q.cfd);
     const bool sub = q.n > 0 && q.pa;
     const double b = sub ? q.cs.beta[vec * q.cs.maxs + q.n - 1] : 0.0;
-    for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = q.ulut[k];
-    for (int k = threadIdx.x; k < q.nctab; k += 256) ct[k] = q.ctab[k];
+    for (int k = threadIdx.x; k < nlut; k += 256) lut[k] = gp(q.ulut)[k];
+    for (int k = threadIdx.x; k < q.nctab; k += 256) ct[k] = gp(q.ctab)[k];
     const int64_t nel = nr * d_up;
-    const T *vblk = v + row0 * d_up;
+    const auto vblk = v + row0 * d_up;
     for (int64_t k = threadIdx.x; k < nel; k += 256) row[k] = vblk[k];
     __syncthreads();
     const uint32_t du = (uint32_t)d_up;
@@ -158,8 +161,8 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     // hops from global memory, -beta vp, rounded once
     // diagonal and in-row part of one element: returns the partial sum and v_i
     auto in_row = [&](uint32_t r, uint32_t iu, uint32_t sdn, double edn, double *vi_out) -> double {
-        const uint32_t dbl = q.su[iu] & sdn;
-        double diag = q.eu[iu] + edn;
+        const uint32_t dbl = su[iu] & sdn;
+        double diag = eu[iu] + edn;
         if (q.u_uniform >= 0.0) {
             diag += q.u_uniform * (double)__popc(dbl);
         } else {
@@ -170,10 +173,10 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
         const double vi = (double)rr[iu];
         *vi_out = vi;
         double acc = diag * vi;
-        const int nhu = q.nhu[iu];
-        const uint32_t *pp = q.pku + iu;
+        const int nh_u = nhu[iu];
+        const auto pp = pku + iu;
         int s = 0;
-        for (; s + 4 <= nhu; s += 4) {
+        for (; s + 4 <= nh_u; s += 4) {
             const uint32_t p0 = pp[(int64_t)s * d_up], p1 = pp[(int64_t)(s + 1) * d_up];
             const uint32_t p2 = pp[(int64_t)(s + 2) * d_up], p3 = pp[(int64_t)(s + 3) * d_up];
             const double x0 = (double)rr[p0 & 0xffffu], x1 = (double)rr[p1 & 0xffffu];
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             acc = fma(ct[p2 >> 16], x2, acc);
             acc = fma(ct[p3 >> 16], x3, acc);
         }
-        for (; s < nhu; ++s) {
+        for (; s < nh_u; ++s) {
             const uint32_t p0 = pp[(int64_t)s * d_up];
             acc = fma(ct[p0 >> 16], (double)rr[p0 & 0xffffu], acc);
         }
@@ -207,14 +210,14 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
     };
     // one element: diagonal, in-row hops through the packed entries, row-mixing
     // hops from global memory, -beta vp, rounded once
-    auto element = [&](uint32_t r, uint32_t iu, int64_t idn, uint32_t sdn, double edn, int nhd,
-                       const int32_t *__restrict__ cold_r, const double *__restrict__ cfd_r) {
+    auto element = [&](uint32_t r, uint32_t iu, int64_t idn, uint32_t sdn, double edn, int nh_d,
+                       gptr<const int32_t> cold_r, gptr<const double> cfd_r) {
         double vi;
         double acc = in_row(r, iu, sdn, edn, &vi);
         // row-mixing term (hop s of row idn at cold_r[s * d_dn])
-        const T *vc = v + iu;
+        const auto vc = v + iu;
         int s = 0;
-        for (; s + 4 <= nhd; s += 4) {
+        for (; s + 4 <= nh_d; s += 4) {
             const int64_t e0 = (int64_t)s * d_dn, e1 = e0 + d_dn;
             const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
             const double x0 = (double)vc[(int64_t)cold_r[e0] * d_up];
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             acc = fma(cfd_r[e2], x2, acc);
             acc = fma(cfd_r[e3], x3, acc);
         }
-        for (; s < nhd; ++s) {
+        for (; s < nh_d; ++s) {
             const int64_t e0 = (int64_t)s * d_dn;
             acc = fma(cfd_r[e0], (double)vc[(int64_t)cold_r[e0] * d_up], acc);
         }
@@ -240,23 +243,23 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
         // are issued together; each element's sum keeps its own order.
         for (uint32_t r = 0; r < (uint32_t)nr; ++r) {
             const int64_t idn = row0 + r;
-            const uint32_t sdn = q.sd[idn];
-            const double edn = q.ed[idn];
-            const int nhd = q.nhd[idn];
-            const int32_t *__restrict__ cold_r = q.cold + idn;
-            const double *__restrict__ cfd_r = q.cfd + idn;
+            const uint32_t sdn = sd[idn];
+            const double edn = ed[idn];
+            const int nh_d = nhd[idn];
+            const auto cold_r = cold + idn;
+            const auto cfd_r = cfd + idn;
             for (uint32_t iu = threadIdx.x; iu < du; iu += 512) {
                 const uint32_t iu2 = iu + 256;
                 if (iu2 >= du) {
-                    element(r, iu, idn, sdn, edn, nhd, cold_r, cfd_r);
+                    element(r, iu, idn, sdn, edn, nh_d, cold_r, cfd_r);
                     continue;
                 }
                 double vi1, vi2;
                 double a1 = in_row(r, iu, sdn, edn, &vi1);
                 double a2 = in_row(r, iu2, sdn, edn, &vi2);
-                const T *vc1 = v + iu, *vc2 = v + iu2;
+                const auto vc1 = v + iu, vc2 = v + iu2;
                 int s = 0;
-                for (; s + 4 <= nhd; s += 4) {
+                for (; s + 4 <= nh_d; s += 4) {
                     const int64_t e0 = (int64_t)s * d_dn, e1 = e0 + d_dn;
                     const int64_t e2 = e1 + d_dn, e3 = e2 + d_dn;
                     const int64_t o0 = (int64_t)cold_r[e0] * d_up, o1 = (int64_t)cold_r[e1] * d_up;
@@ -275,7 +278,7 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
                     a1 = fma(c3, x3, a1);
                     a2 = fma(c3, y3, a2);
                 }
-                for (; s < nhd; ++s) {
+                for (; s < nh_d; ++s) {
                     const int64_t e0 = (int64_t)s * d_dn;
                     const int64_t o0 = (int64_t)cold_r[e0] * d_up;
                     a1 = fma(cfd_r[e0], (double)vc1[o0], a1);
@@ -290,7 +293,7 @@ __global__ void __launch_bounds__(256) ks_hv(Src src) {
             const uint32_t r = (uint32_t)e / du;
             const uint32_t iu = (uint32_t)e - r * du;
             const int64_t idn = row0 + r;
-            element(r, iu, idn, q.sd[idn], q.ed[idn], q.nhd[idn], q.cold + idn, q.cfd + idn);
+            element(r, iu, idn, sd[idn], ed[idn], nhd[idn], cold + idn, cfd + idn);
         }
     }
     if (q.pa) {
@@ -336,9 +339,9 @@ __global__ void __launch_bounds__(256) ks_sub_prev(Src src) {
     const int n = q.n;
     const double b = n > 0 ? q.cs.beta[at.vec * q.cs.maxs + n - 1] : 0.0;
     const int64_t off = at.vec * q.dim;
-    T *w = (T *)q.w + off;
-    const T *vp = (const T *)q.vp + off;
-    const T *v = (const T *)q.v + off;
+    const auto w = gp((T *)q.w) + off;
+    const auto vp = gp((const T *)q.vp) + off;
+    const auto v = gp((const T *)q.v) + off;
     double acc = 0.0;
     for (int k = threadIdx.x; k < kChunk; k += 256) {
         const int64_t i = at.base + k;
@@ -367,9 +370,9 @@ __global__ void __launch_bounds__(256) ks_norm(Src src, int cond) {
     if (cond && !q.cs.renorm[at.vec]) return;
     const double a = q.cs.alpha[at.vec * q.cs.maxs + q.n];
     const int64_t off = at.vec * q.dim;
-    const T *w = (const T *)q.w + off;
-    const T *v = (const T *)q.v + off;
-    const T *vp = (const T *)q.vp + off;
+    const auto w = gp((const T *)q.w) + off;
+    const auto v = gp((const T *)q.v) + off;
+    const auto vp = gp((const T *)q.vp) + off;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (q.reorth) {
         for (int k = threadIdx.x; k < kChunk; k += 256) {
@@ -608,10 +611,10 @@ __global__ void __launch_bounds__(256) ks_update(Src src) {
     const double a = cs.apre[at.vec], c1 = cs.corr[at.vec], c2 = cs.corr2[at.vec];
     const double s = cs.inv[at.vec];
     const int64_t off = at.vec * q.dim;
-    T *w = (T *)q.w + off;
-    const T *v = (const T *)q.v + off;
-    const T *vp = (const T *)q.vp + off;
-    double *psi = q.psi;
+    const auto w = gp((T *)q.w) + off;
+    const auto v = gp((const T *)q.v) + off;
+    const auto vp = gp((const T *)q.vp) + off;
+    const auto psi = gp(q.psi);
     const double sv = psi ? q.svec[q.n] : 0.0;
     for (int k = threadIdx.x; k < kChunk; k += 256) {
         const int64_t i = at.base + k;
@@ -634,11 +637,12 @@ __global__ void __launch_bounds__(256) ks_accum(Src src) {
     int64_t local;
     const BGroup &q = src.at(blockIdx.x, &local);
     const ChunkAt at = chunk_of(q, local);
-    const T *v = (const T *)q.v;
+    const auto v = gp((const T *)q.v);
+    const auto psi = gp(q.psi);
     const double sv = q.svec[q.n];
     for (int k = threadIdx.x; k < kChunk; k += 256) {
         const int64_t i = at.base + k;
-        if (i < q.dim) q.psi[i] = fma(sv, ldd(v + i), q.psi[i]);
+        if (i < q.dim) psi[i] = fma(sv, ldd(v + i), psi[i]);
     }
 }
 
