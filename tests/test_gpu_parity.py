@@ -141,6 +141,41 @@ def test_hv_4x4_sampled_rows(q):
     del w, w32, vd, v32
 
 
+def test_hv_sector_over_2gb_sampled_rows(q):
+    """An 18-site 2x9 cluster with next-nearest hops (bond-dependent t) in the
+    (5, 9) sector: d = 8,568 x 48,620 = 416,576,160, rows long enough for the
+    two-pass product.  The FP64 vector (3.3 GB) is past the 2 GB up to which
+    the row-mixing pass reads neighbours through a buffer descriptor, so it
+    takes the 64-bit-address form; its FP32 copy (1.7 GB) takes the
+    descriptor form.  Oracle rows computed one by one."""
+    torch = _torch()
+    m = synth.rect_cluster(2, 9, tp=0.3, U=4.0, mu=2.0, nup=5, ndn=9, name="2x9")
+    print("hv 2x9 (5,9) sector", flush=True)
+    b = q.sector_basis(18, 5, 9)
+    assert b.dim == 8568 * 48620 and b.dim * 8 > 2 ** 31 > b.dim * 4
+    v = oracle.start_vector(7, b.dim)
+    vd = torch.from_numpy(v).to("cuda")
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([rng.integers(0, b.dim, 4000), np.arange(64),
+                                     np.arange(b.dim - 64, b.dim)]))
+    ri = torch.from_numpy(rows).to("cuda")
+    bound = oracle.hv_abs_bound(m.t, m.U, 5, 9, v, rows)
+    w = q.hv(m, b, vd)
+    wr = w[ri].cpu().numpy()
+    del w
+    wo = oracle.hv_rows(m.t, m.U, 5, 9, v, rows)
+    assert np.all(np.abs(wr - wo) <= 64 * EPS * bound)
+    v32 = vd.float()
+    del vd
+    w32 = q.hv(m, b, v32)
+    wr32 = w32[ri].double().cpu().numpy()
+    del w32
+    v32h = v32.cpu().numpy()
+    wo32 = oracle.hv_rows(m.t, m.U, 5, 9, v32h, rows)
+    assert np.all(np.abs(wr32 - wo32) <= 2.0 ** -24 * (np.abs(wo32) + bound) + 64 * EPS * bound)
+    del v32, v32h
+
+
 # ---------------------------------------------------------------- ground state
 
 GS_MODELS = [synth.plaquette_2x2(), synth.two_site(U=8.0), synth.rect_cluster(2, 4, U=4.0, mu=2.0),
