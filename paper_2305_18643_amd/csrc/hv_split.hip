@@ -45,21 +45,35 @@ constexpr int64_t kSplitMinUp = 4096;
 // index 0.  Slot s of lane l is entry (s / 4) 256 + 4 l + s % 4 from the
 // tile's start: a lane's four consecutive slots are adjacent, one 16-byte
 // load.  Block = tile of 64 up strings, thread = lane.
+// out32 (or null): the FP32 entries of a model whose bonds all have the same
+// t, in the same places: the neighbour's LDS byte address itself, in the row
+// (col * 4) for a + sign and in the negated copy of the row (neg + col * 4)
+// for a - sign; padding: the zero slot (4 d).
 __global__ void k_pack_tiles(int64_t d, const int32_t *__restrict__ nh,
                              const uint32_t *__restrict__ pk, const int32_t *__restrict__ tnt,
-                             const int32_t *__restrict__ toff, uint32_t *__restrict__ out) {
+                             const int32_t *__restrict__ toff, uint32_t *__restrict__ out,
+                             uint32_t *__restrict__ out32, const uint32_t neg) {
     const int tt = blockIdx.x, lane = threadIdx.x;
     const int64_t i = (int64_t)tt * 64 + lane;
     const int n = i < d ? nh[i] : 0;
     const uint32_t pad = (uint32_t)(8 * d);
     for (int s = 0; s < tnt[tt]; ++s) {
-        uint32_t e = pad;
+        uint32_t e = pad, e32 = (uint32_t)(4 * d);
         if (s < n) {
             const uint32_t p = pk[(int64_t)s * d + i], col = p & 0xffffu, idx = p >> 16;
             e = (col << 3) | (idx << 17) | ((idx & 1u) << 31);
+            e32 = (col << 2) + ((idx & 1u) ? neg : 0u);
         }
-        out[toff[tt] + (s >> 2) * 256 + lane * 4 + (s & 3)] = e;
+        const int64_t at = toff[tt] + (s >> 2) * 256 + lane * 4 + (s & 3);
+        out[at] = e;
+        if (out32) out32[at] = e32;
     }
+}
+
+// Byte address of the negated copy of an FP32 row in the in-row pass's LDS:
+// after the row and its 64-byte zero slot.
+__host__ __device__ inline uint32_t neg_row_at(int64_t d_up) {
+    return (uint32_t)((4 * d_up + 64 + 15) & ~(int64_t)15);
 }
 
 // Pass A: one row of V in LDS at a time (persistent grid, one 1024-thread
@@ -119,7 +133,8 @@ template <typename T, int KS, bool UT, int LZ>
 __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     const int64_t d_up, const int64_t d_dn, const uint32_t *__restrict__ su,
     const double *__restrict__ eu, const int ntile, const int32_t *__restrict__ tnt,
-    const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent, const int ent_bytes,
+    const int32_t *__restrict__ toff, const uint32_t *__restrict__ ent,
+    const uint32_t *__restrict__ ent32, const int ent_bytes,
     const double *__restrict__ ctab_g, const int nctab, const uint32_t *__restrict__ sd,
     const double *__restrict__ ed, const double *__restrict__ ulut_g, const int nbytes,
     const double u_uniform, const double tu, T *__restrict__ v, T *w, const LazyUpd lz) {
@@ -132,9 +147,16 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     const int dup = (int)d_up;
     T *row = reinterpret_cast<T *>(smem);
     // zero slot: 64 bytes right after the row (a padding entry's offset 8 d_up,
-    // halved for FP32 rows, points there)
+    // halved for FP32 rows, points there).  NEG (FP32 rows, one t for every
+    // bond): a negated copy of the row follows, and the entries are the
+    // neighbours' LDS addresses in the row or in the copy, so that a gather
+    // needs neither a mask nor a sign flip
+    constexpr bool NEG = UT && sizeof(T) == 4;
     const size_t zero_at = sizeof(T) * (size_t)dup;
-    const size_t tab_at = (zero_at + 64 + 15) & ~(size_t)15;
+    const size_t neg_at = NEG ? neg_row_at(dup) : 0;
+    T *rowneg = reinterpret_cast<T *>(smem + neg_at);
+    const size_t tab_at =
+        NEG ? neg_at + ((4 * (size_t)dup + 15) & ~(size_t)15) : (zero_at + 64 + 15) & ~(size_t)15;
     double *ct = reinterpret_cast<double *>(smem + tab_at);
     double *ulut = ct + ((nctab + 1) & ~1);
     if (tid < 16) reinterpret_cast<uint32_t *>(smem + zero_at)[tid] = 0u;
@@ -188,7 +210,8 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     const __amdgpu_buffer_rsrc_t reu = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<double *>(eu), (short)0, (int)(8 * d_up), 0x00020000);
     const __amdgpu_buffer_rsrc_t rent =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(ent), (short)0, ent_bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(NEG ? ent32 : ent), (short)0, ent_bytes,
+                                          0x00020000);
     int64_t r = blockIdx.x;
     if (r < d_dn) fetch(r);
     for (; r < d_dn; r += gridDim.x) {
@@ -210,7 +233,10 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int idx = tid + k * NT;
-            if (idx < dup) row[idx] = xr[k];
+            if (idx < dup) {
+                row[idx] = xr[k];
+                if (NEG) rowneg[idx] = -xr[k];
+            }
         }
         __syncthreads();
         const int64_t rn = r + gridDim.x;
@@ -254,12 +280,15 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
                 double x[n];
 #pragma unroll
                 for (int u = 0; u < n; ++u) {
-                    const uint32_t off = sizeof(T) == 8 ? (p[u] & 0x1ffffu) : ((p[u] & 0x1ffffu) >> 1);
+                    const uint32_t off = NEG ? p[u]
+                                       : sizeof(T) == 8 ? (p[u] & 0x1ffffu) : ((p[u] & 0x1ffffu) >> 1);
                     x[u] = (double)*(lds_t *)(size_t)off;
                 }
 #pragma unroll
                 for (int u = 0; u < n; ++u) {
-                    if constexpr (UT) {
+                    if constexpr (NEG) {
+                        acc = fma(tu, x[u], acc);
+                    } else if constexpr (UT) {
                         const double xs = __hiloint2double(
                             __double2hiint(x[u]) ^ (int)(p[u] & 0x80000000u), __double2loint(x[u]));
                         acc = fma(tu, xs, acc);
@@ -526,8 +555,11 @@ int build_row_offsets(HopTables &ht, int64_t d_up, Carver &cv, hipStream_t s) {
 
 static size_t inrow_lds_bytes(const HvOp &op, int prec) {
     const size_t es = prec == QCM_FP64 ? 8 : 4;
-    // the row, the 64-byte zero slot, then the coefficient and U tables
-    const size_t row = (es * (size_t)op.up.d + 64 + 15) & ~(size_t)15;
+    // the row, the 64-byte zero slot (FP32 rows with one t for every bond:
+    // then the negated row), then the coefficient and U tables
+    size_t row = (es * (size_t)op.up.d + 64 + 15) & ~(size_t)15;
+    if (prec != QCM_FP64 && op.md.t_is_uniform)
+        row = neg_row_at(op.up.d) + ((4 * (size_t)op.up.d + 15) & ~(size_t)15);
     const size_t nct = (size_t)((2 * op.md.nbond + 1) & ~1);
     const size_t lut = op.md.u_uniform >= 0.0 ? 0 : 256 * (size_t)op.md.nbytes;
     return row + 8 * (nct + lut);
@@ -550,7 +582,7 @@ static int split_launch_t(const HvOp &op, void *v, void *w, int nvec, hipStream_
 #define QCM_PK_L(KS_, UT_, LZ_)                                                                \
     k_hv_inrow_tile<T, KS_, UT_, LZ_><<<gp, 1024, lds, s>>>(                                   \
         d_up, d_dn, op.up.states, op.hu.ediag, op.ntile, op.tile_nt, op.tile_off, op.tile_ent, \
-        op.tile_bytes,                                                                         \
+        op.tile_ent32, op.tile_bytes,                                                          \
         op.md.ctab, nctab, op.dn.states, op.hd.ediag, op.md.ulut, op.md.nbytes,                \
         op.md.u_uniform, op.md.t_uniform, (T *)v, (T *)w, lz)
 #define QCM_PK_U(KS_, UT_)                                                                     \
@@ -667,6 +699,7 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
     op.ntile = (int32_t)((du + 63) / 64);
     const int wr = (op.hu.width + kTileChunk - 1) / kTileChunk * kTileChunk;
     op.tile_ent = cv.take<uint32_t>((size_t)op.ntile * wr * 64);
+    op.tile_ent32 = op.md.t_is_uniform ? cv.take<uint32_t>((size_t)op.ntile * wr * 64) : nullptr;
     op.tile_nt = cv.take<int32_t>(op.ntile);
     op.tile_off = cv.take<int32_t>(op.ntile);
     QCM_TRY(build_hop_tables(op.md, op.dn, cv, &op.hd_rm, s, count_bonds(m), 1));
@@ -710,7 +743,7 @@ int split_prepare(const qcm_model *m, HvOp &op, Carver &cv, hipStream_t s) {
         QCM_HIP(hipMemcpyAsync(op.tile_off, toff.data(), sizeof(int32_t) * op.ntile,
                                hipMemcpyHostToDevice, s));
         k_pack_tiles<<<op.ntile, 64, 0, s>>>(du, op.hu.nh, op.hu.pk, op.tile_nt, op.tile_off,
-                                              op.tile_ent);
+                                              op.tile_ent, op.tile_ent32, neg_row_at(du));
         QCM_LAUNCH_CHECK();
         QCM_HIP(hipStreamSynchronize(s));   // tnt and toff are pageable and about to go
     }

@@ -158,6 +158,9 @@ struct HvOp {
     // + s % 4], s < tile_nt[t] (the tile's largest hop count rounded up to 4,
     // padded with entries that read a zero slot)
     uint32_t *tile_ent = nullptr;
+    // with one t for every bond, the FP32 form of the same entries: the
+    // neighbour's LDS byte address in the row or in its negated copy
+    uint32_t *tile_ent32 = nullptr;
     int32_t *tile_nt = nullptr, *tile_off = nullptr;
     int32_t tile_bytes = 0;       // bytes of tile_ent in use
     int32_t ntile = 0;
