@@ -83,18 +83,22 @@ __host__ __device__ inline uint32_t neg_row_at(int64_t d_up) {
 // masking and the entry loads are one contiguous 1 KB load per four slots
 // from a wave-uniform base (2.57 -> 2.55 ms for the 4x4 H.v against one
 // 256-byte load per slot); slots past a lane's own hops read the zero slot.
-// Eight entries are loaded, then eight neighbours gathered from LDS, then
-// summed; a
-// tile's slot count is its largest hop count rounded up to four, the last
-// four taken as a group of their own (4x4 sector: 19.0 slots per string
-// instead of 21.4 with counts rounded up to eight; H.v 2.63 -> 2.60 ms in
-// FP64, 2.60 -> 2.54 ms in FP32).  Ordering each tile span's strings by hop
-// count (15-17 slots) was measured slower: their products are then stored
-// scattered over the span, which costs more than the slots it saves.
-// The row sits at LDS address 0, so the masked entry is the gather address
-// (halved for FP32 rows).  When every bond has the same t (UT), a coefficient
-// is +-t: the entry's sign bit flips the sign of the neighbour value and the
-// coefficient table is not read.  W = V K_up^T + D o V, written once; the
+// The wave index is a scalar, so the tile loop, the tile's slot count and
+// table offset are scalar work (2.55 -> 2.44 ms against two vector loads
+// waited for in turn per tile), and the up-string bits, the up diagonal, the
+// table and W go through buffer descriptors (lane offset register, scalar
+// tile offset).  Eight entries are loaded, then eight neighbours gathered
+// from LDS, then summed; a tile's slot count is its largest hop count
+// rounded up to four, the last four taken as a group of their own (4x4
+// sector: 19.0 slots per string instead of 21.4 with counts rounded up to
+// eight; H.v 2.63 -> 2.60 ms in FP64, 2.60 -> 2.54 ms in FP32).  Ordering
+// each tile span's strings by hop count (15-17 slots) was measured slower:
+// their products are then stored scattered over the span, which costs more
+// than the slots it saves.  The row sits at LDS address 0, so the masked
+// entry is the gather address (halved for FP32 rows).  When every bond has
+// the same t (UT), a coefficient is +-t: the entry's sign bit flips the sign
+// of the neighbour value and the coefficient table is not read (FP32 rows:
+// the negated copy below instead).  W = V K_up^T + D o V, written once; the
 // per-element sum is the diagonal term, then the hops in list order.
 // LZ > 0 (a Lanczos step after a deferred update, LazyUpd): v holds w_n; the
 // prefetch of the next row also loads v_n (and v_{n-1} for LZ = 2, with
@@ -141,8 +145,6 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NT = kInrowThreads;   // the launch's block size
     const int tid = threadIdx.x;
-    // the wave index as a scalar, so that the tile loop and its per-tile loads
-    // (slot count, table offset) are wave-uniform scalar work
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = NT >> 6;
     const int dup = (int)d_up;
     T *row = reinterpret_cast<T *>(smem);
@@ -324,14 +326,14 @@ __global__ void __launch_bounds__(kInrowThreads) k_hv_inrow_tile(
 // wave-uniform (scalar loads), RI rows of a wave with 8 neighbour segments
 // each in flight (RI: chosen at the launch below; for the FP64 product four
 // rows were 2.5 % faster than two on the 4x4 sector, while 1, 6 or 8 rows, or
-// 32-row slabs, were slower).  When
-// d_up is even a lane takes two adjacent columns (one 2-element load per
-// neighbour), which halves the load instructions.  Within a slab the rows are
-// taken in row_order: grouped by the popcount of the high half of the down
-// string.  Hops inside either half
+// 32-row slabs, were slower).  When d_up is even a lane takes two adjacent
+// columns (one 2-element load per neighbour), which halves the load
+// instructions.  Within a slab the rows are taken in row_order: grouped by
+// the popcount of the high half of the down string.  Hops inside either half
 // keep that popcount, so the rows an XCD has in flight find most of their
-// neighbour segments among rows of the same group, a working set that fits
-// its L2 (4,900 rows x 512 B for the 4x4 FP64 slab of the largest group).
+// neighbour segments among rows of the same group (4,900 rows x 1 KB for the
+// 4x4 FP64 slab of the largest group: a little more than the XCD's 4 MB L2,
+// so part of them come back from the Infinity Cache).
 // Row-major list of the down hops of every row, as element offsets of the
 // neighbour row (j_dn * d_up) and coefficients, padded to the width W.
 __global__ void k_row_offsets(int64_t d_dn, int W, int64_t d_up, const int32_t *__restrict__ col,
